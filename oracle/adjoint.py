@@ -1,0 +1,141 @@
+"""Hand-written reverse-mode adjoint of the learnable V-cycle -- TEST INFRASTRUCTURE ONLY.
+
+Training the cycle (paper Sec. 3.1, Alg. 3) back-propagates a residual loss
+through LMG.  This module computes, for one cycle u_out = LMG(A, f, u_in) and a
+cotangent g = dL/du_out, the vector-Jacobian products dL/df, dL/du_in and
+dL/dTheta, by running the steps of Alg. 2 backwards.  Every step of Alg. 2 is
+linear in the vectors, so each reverse rule is a transpose:
+
+  smoothing  delta = theta D^{-1}(f - A u), u' = u + eta Phi(delta):
+      Phi_bar = eta g,  d eta += <g, Phi(delta)>,  d c_k += <Phi_bar, M^k delta>,
+      delta_bar = sum_k c_k (M^T)^k Phi_bar,  d theta += <delta_bar, D^{-1}(f - A u)>,
+      s = theta D^{-1} delta_bar,  f_bar += s,  u_bar = g - A^T s
+  restriction r_c = R Phi_R(f - A u):  y = R^T r_c_bar, r_bar = Phi_R^T(y), ...
+  prolongation u += Phi_P(P e_c):  e_c_bar = P^T Phi_P^T(g)
+  coarsest   u = A_J^{-1} f:  f_bar = A_J^{-T} g
+with M^T = A_g^T D_g^{-1}.  Inner products sum over all right-hand-side
+columns.  Plain NumPy, FP64; shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .lmg import OLevel, OParams, graph_conv, neighbour_mean, residual, smooth, lmg
+
+
+def neighbour_mean_T(lv: OLevel, y: np.ndarray) -> np.ndarray:
+    """M^T y = A_g^T (D_g^{-1} y)."""
+    return lv.G.T @ (lv.inv_deg[:, None] * y)
+
+
+def graph_conv_vjp(c: np.ndarray, lv: OLevel, x: np.ndarray, ybar: np.ndarray):
+    """For y = sum_k c_k M^k x: returns (x_bar, c_bar)."""
+    K = len(c) - 1
+    cbar = np.zeros(K + 1)
+    w = x
+    for k in range(K + 1):
+        cbar[k] = np.sum(ybar * w)
+        if k < K:
+            w = neighbour_mean(lv, w)
+    xbar = np.zeros_like(ybar)
+    z = ybar
+    for k in range(K + 1):
+        xbar = xbar + c[k] * z
+        if k < K:
+            z = neighbour_mean_T(lv, z)
+    return xbar, cbar
+
+
+def zero_grads(prm: OParams) -> OParams:
+    return OParams(np.zeros_like(prm.theta), np.zeros_like(prm.eta), np.zeros_like(prm.cB),
+                   np.zeros_like(prm.cR), np.zeros_like(prm.cP), prm.nu_pre, prm.nu_post)
+
+
+def _smooth_vjp(lv, l, prm, f, u, g, grads):
+    rs = lv.Dinv[:, None] * residual(lv, f, u)         # D^{-1}(f - A u)
+    delta = prm.theta[l] * rs
+    phi = graph_conv(prm.cB[l], lv, delta)
+    grads.eta[l] += np.sum(g * phi)
+    phibar = prm.eta[l] * g
+    dbar, cbar = graph_conv_vjp(prm.cB[l], lv, delta, phibar)
+    grads.cB[l] += cbar
+    grads.theta[l] += np.sum(dbar * rs)
+    s = prm.theta[l] * (lv.Dinv[:, None] * dbar)
+    return s, g - lv.A.T @ s                           # (f_bar contribution, u_bar)
+
+
+def lmg_vjp(levels, prm: OParams, l: int, f, u, g, grads: OParams):
+    """Reverse of u_out = LMG(A_l, f, u, l).  Returns (f_bar, u_bar); adds the
+    parameter gradients into `grads`."""
+    J = len(levels)
+    lv = levels[l]
+    if l == J - 1:
+        fbar = sla.lu_solve(lv.lu, g, trans=1)
+        return fbar, np.zeros_like(u)
+    # forward recomputation, keeping the states the reverse sweep needs
+    pre = []
+    for _ in range(prm.nu_pre):
+        pre.append(u)
+        u = smooth(lv, l, prm, f, u)
+    r = residual(lv, f, u)
+    rc = lv.R @ graph_conv(prm.cR[l], lv, r)
+    ec = lmg(levels, prm, l + 1, rc, np.zeros((levels[l + 1].A.shape[0], f.shape[1])))
+    pe = lv.P @ ec
+    u = u + graph_conv(prm.cP[l], lv, pe)
+    post = []
+    for _ in range(prm.nu_post):
+        post.append(u)
+        u = smooth(lv, l, prm, f, u)
+    # reverse sweep
+    fbar = np.zeros_like(f)
+    for up in reversed(post):
+        s, g = _smooth_vjp(lv, l, prm, f, up, g, grads)
+        fbar += s
+    xbar, cbar = graph_conv_vjp(prm.cP[l], lv, pe, g)
+    grads.cP[l] += cbar
+    ecbar = lv.P.T @ xbar
+    rcbar, _ = lmg_vjp(levels, prm, l + 1, rc, np.zeros_like(ec), ecbar, grads)
+    rbar, cbar = graph_conv_vjp(prm.cR[l], lv, r, lv.R.T @ rcbar)
+    grads.cR[l] += cbar
+    fbar += rbar
+    g = g - lv.A.T @ rbar
+    for up in reversed(pre):
+        s, g = _smooth_vjp(lv, l, prm, f, up, g, grads)
+        fbar += s
+    return fbar, g
+
+
+def cycle_vjp(levels, prm: OParams, f, u, g):
+    """Finest-level VJP; returns (f_bar, u_bar, grads)."""
+    grads = zero_grads(prm)
+    fbar, ubar = lmg_vjp(levels, prm, 0, f, u, g, grads)
+    return fbar, ubar, grads
+
+
+def unrolled_loss(levels, prm: OParams, f, cycles: int = 10):
+    """Alg. 3 forward unrolled: u^0 = 0, u^m = LMG(A, f, u^{m-1});
+    L = mean_b ||f_b - A u_b^{cycles}||^2 / ||f_b||^2."""
+    u = np.zeros_like(f)
+    for _ in range(cycles):
+        u = lmg(levels, prm, 0, f, u)
+    r = residual(levels[0], f, u)
+    fn2 = np.sum(f * f, axis=0)
+    return float(np.mean(np.sum(r * r, axis=0) / fn2))
+
+
+def unrolled_loss_and_grad(levels, prm: OParams, f, cycles: int = 10):
+    """Loss of `unrolled_loss` and its gradient w.r.t. the parameters."""
+    us = [np.zeros_like(f)]
+    for _ in range(cycles):
+        us.append(lmg(levels, prm, 0, f, us[-1]))
+    A = levels[0].A
+    r = residual(levels[0], f, us[-1])
+    fn2 = np.sum(f * f, axis=0)
+    B = f.shape[1]
+    loss = float(np.mean(np.sum(r * r, axis=0) / fn2))
+    g = -(2.0 / B) * (A.T @ (r / fn2[None, :]))      # dL/du^{cycles}
+    grads = zero_grads(prm)
+    for m in range(cycles, 0, -1):
+        _, g = lmg_vjp(levels, prm, 0, f, us[m - 1], g, grads)
+    return loss, grads
