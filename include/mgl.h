@@ -1,0 +1,213 @@
+/*
+ * mgl.h -- C ABI of the learnable graph-convolution multigrid V-cycle for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves A u = f with the stationary iteration
+ *     u^m = u^{m-1} + B_Theta (f - A u^{m-1})                 (paper Sec. 1)
+ * whose approximate inverse B_Theta is one learnable V-cycle (paper Alg. 2):
+ * on every level l < J-1 (0 = finest) the smoother is
+ *     delta = theta_l D_A^{-1} (f - A_l u),   u <- u + eta_l Phi_B,l(delta)
+ * (Sec. 3, learnable smoother; damped Jacobi B_l = D_A^{-1}, Sec. 2.3), the
+ * restriction is r_c = R_l Phi_R,l(f - A_l u) and the prolongation adds
+ * Phi_P,l(P_l e_c) (Sec. 3, learnable transfers), and level J-1 is solved
+ * exactly.  Every graph convolution is a polynomial in the neighbour-mean
+ * operator M_l = D_g^{-1} A_g of the level's graph (Sec. 3.5 eq. graph-conv-
+ * matrix; K = 1 is SAGEConv with mean aggregation, Sec. 3.3; order K per the
+ * polynomial-smoother remark of Sec. 3.5):
+ *     Phi(x) = sum_{k=0..K} c_k M^k x .
+ * The graph of level l is {(i, j): A_ij != 0, i != j} unless given (Sec. 2.1).
+ *
+ * Conventions for every entry point:
+ *  - Return an mg_status; they never abort and never throw.  On failure a
+ *    thread-local message is available from mg_last_error().
+ *  - Vectors are device arrays of n x B values, row-major with the B
+ *    right-hand sides contiguous (element (i, b) at i*B + b).  Their element
+ *    type depends on the context precision: double for MG_FP64, float for
+ *    MG_FP32 and MG_FP32_BF16 ("cycle type").  Solver-level vectors
+ *    (mg_solve, mg_residual, mg_refine_step*) are always double.
+ *  - Work is enqueued on the HIP stream passed in (hipStream_t, may be NULL
+ *    for the default stream) and is asynchronous unless stated otherwise.
+ *  - Columns are independent: a column's result does not depend on the other
+ *    columns, except parameter gradients, which sum over all columns.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef MGL_H
+#define MGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx mg_ctx;
+
+typedef enum {
+    MG_OK = 0,
+    MG_ERR_INVALID_ARG = 1,   /* null pointer, bad size or option */
+    MG_ERR_SHAPE = 2,         /* inconsistent matrix shapes or malformed CSR */
+    MG_ERR_OOM = 3,           /* device allocation failed or workspace too small */
+    MG_ERR_HIP = 4,           /* a HIP call or kernel launch failed */
+    MG_ERR_NOT_CONVERGED = 5, /* mg_solve: some column missed rtol in max_outer cycles */
+    MG_ERR_DIVERGED = 6,      /* mg_solve: some column's residual became non-finite or grew */
+    MG_ERR_STATE = 7,         /* call not valid in this context state */
+    MG_ERR_UNSUPPORTED = 8    /* feature not available for these inputs */
+} mg_status;
+
+typedef enum {
+    MG_FP64 = 0,       /* cycle in FP64 */
+    MG_FP32 = 1,       /* cycle in FP32, FP64 outer residual / update / coarsest solve */
+    MG_FP32_BF16 = 2   /* as MG_FP32, with the smoother and transfer intermediates stored in BF16 */
+} mg_precision;
+
+/* Host CSR matrix, 0-based, column indices sorted and unique within a row.
+ * The library copies what it needs during mg_setup; the arrays may be freed
+ * afterwards. */
+typedef struct {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    const int32_t* rowptr;   /* [nrows + 1] */
+    const int32_t* col;      /* [nnz] */
+    const double* val;       /* [nnz]; ignored for graph patterns */
+} mg_csr;
+
+/* Multigrid hierarchy (paper Sec. 2.2).  Level 0 is the finest. */
+typedef struct {
+    int32_t nlevels;         /* J >= 2 */
+    const mg_csr* A;         /* [J] system matrices A_l, nonzero diagonal */
+    const mg_csr* P;         /* [J-1] prolongations, n_l x n_{l+1} */
+    const mg_csr* R;         /* [J-1] restrictions n_{l+1} x n_l, or NULL for R_l = P_l^T */
+    const mg_csr* G;         /* [J] graph patterns (diagonal ignored), or NULL for the
+                                off-diagonal nonzero pattern of A_l */
+} mg_hierarchy;
+
+/* Learnable parameters Theta (paper Sec. 3, parameter set).  values is a host
+ * array of mg_num_params(J, KB, KR, KP) doubles laid out per level
+ * l = 0 .. J-2 as
+ *     [theta_l, eta_l, cB_l[0..KB], cR_l[0..KR], cP_l[0..KP]] .
+ * Identity initialisation (Sec. 3.4): theta = omega, eta = 1, c_0 = 1,
+ * c_k = 0 for k > 0, which is the classical V-cycle (Alg. 1). */
+typedef struct {
+    int32_t KB, KR, KP;      /* orders of Phi_B, Phi_R, Phi_P (0..8) */
+    int32_t nu_pre, nu_post; /* smoothing steps per level (0..8) */
+    const double* values;
+} mg_params;
+
+enum { MG_FLAG_BACKWARD = 1 };   /* reserve buffers for mg_*_backward */
+
+typedef struct {
+    int32_t precision;       /* mg_precision */
+    int32_t nrhs;            /* B, 1..256 */
+    int32_t max_outer;       /* mg_solve: cycle cap (>= 1) */
+    int32_t check_every;     /* mg_solve: host reads the active-column count every this many cycles */
+    double rtol;             /* mg_solve: stop a column when ||f - A u|| <= rtol ||f|| */
+    double diverge_factor;   /* mg_solve: a column diverges when its residual norm exceeds
+                                this factor times the initial one or is not finite; <= 0 disables */
+    int32_t flags;           /* MG_FLAG_* */
+} mg_options;
+
+typedef struct {
+    int32_t iters;           /* cycles applied to the column */
+    int32_t status;          /* MG_OK, MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED */
+    double relres;           /* final ||f - A u||_2 / ||f||_2 (FP64); 0 when f = 0 */
+} mg_rhs_info;
+
+/* Number of doubles in the parameter vector. */
+int64_t mg_num_params(int32_t nlevels, int32_t KB, int32_t KR, int32_t KP);
+
+/* Device bytes the context needs (workspace) and the size of one forward
+ * checkpoint (ckpt) for the backward entry points.  No device work. */
+mg_status mg_workspace_bytes(const mg_hierarchy* h, const mg_params* p, const mg_options* o,
+                             size_t* workspace_bytes, size_t* ckpt_bytes);
+
+/* Validate the hierarchy, build the device data structures (ELL matrices,
+ * inverse diagonals and degrees, FP32 copies, the coarsest-level inverse by
+ * Gauss-Jordan elimination with partial pivoting in FP64) and return a
+ * context.  workspace: caller-owned device memory of at least the size
+ * reported by mg_workspace_bytes (kept for the context's lifetime), or NULL
+ * to let the library allocate it.  Synchronises `stream` before returning. */
+mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* o,
+                   void* workspace, size_t workspace_bytes, void* stream, mg_ctx** out);
+
+/* Replace Theta (same layout and orders as at setup).  Synchronises `stream`. */
+mg_status mg_set_params(mg_ctx* ctx, const double* values, void* stream);
+
+/* One learnable V-cycle on the finest level, in place:
+ *     u <- LMG(A_0, f, u, Theta)                                 (Alg. 2)
+ * f, u: cycle-type device vectors [n_0 x B].  ckpt: device buffer of
+ * ckpt_bytes to record what mg_vcycle_backward needs, or NULL. */
+mg_status mg_vcycle(mg_ctx* ctx, const void* f, void* u, void* ckpt, void* stream);
+
+/* Reverse of the mg_vcycle call recorded in ckpt (Sec. 3.1, training by
+ * back-propagation).  Given gu_out = dL/du_out, writes gu_in = dL/du_in and
+ * gf = dL/df (cycle-type vectors, either may be NULL) and gparams = dL/dTheta
+ * (device, mg_num_params doubles, overwritten; NULL to skip).  Requires
+ * MG_FLAG_BACKWARD at setup, symmetric A_l and a symmetric graph. */
+mg_status mg_vcycle_backward(mg_ctx* ctx, const void* ckpt, const void* gu_out,
+                             void* gu_in, void* gf, double* gparams, void* stream);
+
+/* FP64 outer residual r = f - A_0 u (r may be NULL) and its per-column
+ * 2-norms (norms: device double [B], may be NULL). */
+mg_status mg_residual(mg_ctx* ctx, const double* f, const double* u, double* r,
+                      double* norms, void* stream);
+
+/* One outer iteration of the solver in refinement form:
+ *     u_out = u_in + LMG_p(A_0, fl_p(f - A_0 u_in), 0)
+ * with the residual and the update in FP64 and the cycle in the context
+ * precision p.  f, u_in, u_out: device double [n_0 x B]; u_out may equal
+ * u_in.  ckpt as for mg_vcycle. */
+mg_status mg_refine_step(mg_ctx* ctx, const double* f, const double* u_in, double* u_out,
+                         void* ckpt, void* stream);
+
+/* Reverse of mg_refine_step: gu_in = gu_out - A_0^T C^T gu_out,
+ * gf = C^T gu_out, where C is the cycle at zero initial guess.  Vectors are
+ * device double; gu_in may equal gu_out; gf and gparams may be NULL. */
+mg_status mg_refine_step_backward(mg_ctx* ctx, const void* ckpt, const double* gu_out,
+                                  double* gu_in, double* gf, double* gparams, void* stream);
+
+/* Solve A u = f for all B columns: refinement steps from the given u until
+ * every column meets rtol (a column stops updating at the first iterate that
+ * meets it), diverges, or max_outer cycles ran.  f, u: device double
+ * [n_0 x B].  info: host array [B] (may be NULL).  Blocks the calling thread
+ * (it reads the active count every check_every cycles).  Returns MG_OK,
+ * MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED. */
+mg_status mg_solve(mg_ctx* ctx, const double* f, double* u, mg_rhs_info* info, void* stream);
+
+/* Per-level sizes: n_l for l < J (out: host int64 [J]) plus ELL widths of
+ * A_l (wA: host int32 [J], may be NULL). */
+mg_status mg_level_info(const mg_ctx* ctx, int64_t* n, int32_t* wA);
+
+/* Instrumentation.  Kernel families for mg_timing_start. */
+enum {
+    MG_KF_NONE = 0,
+    MG_KF_HOP = 1,       /* graph-convolution hops (neighbour mean + axpy) */
+    MG_KF_RESID = 2,     /* residual / Jacobi-scaled residual sweeps */
+    MG_KF_RESTRICT = 3,  /* restriction (with fused residual or last hop) */
+    MG_KF_PROLONG = 4,   /* prolongation (with fused correction) */
+    MG_KF_OUTER = 5      /* FP64 outer residual with column norms */
+};
+
+/* Start timing every launch of one kernel family on every level: a HIP event
+ * pair is recorded around each such launch on its stream, and the
+ * algorithmic bytes of the launch (each operand streamed once: vectors read
+ * and written, ELL indices and values, per-row scalars) are added up.
+ * kernel_family MG_KF_NONE stops timing.  Clears earlier records. */
+mg_status mg_timing_start(mg_ctx* ctx, int32_t kernel_family);
+
+/* Number of timed launches, their summed duration (milliseconds, from the
+ * event pairs) and their summed algorithmic bytes.  Synchronises on the
+ * recorded events. */
+mg_status mg_timing_read(mg_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
+
+/* Release the context (and the workspace if the library allocated it).
+ * Waits for the context's work to finish.  NULL is ignored. */
+void mg_destroy(mg_ctx* ctx);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGL_H */

@@ -1,0 +1,306 @@
+"""Python binding of libmgl.so (the C ABI declared in include/mgl.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+Device vectors are torch tensors (torch supplies device memory and streams);
+the hierarchy is handed over as host CSR arrays (scipy matrices).  There is no
+CPU fallback: if the library cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgl.so")
+
+STATUS = {0: "MG_OK", 1: "MG_ERR_INVALID_ARG", 2: "MG_ERR_SHAPE", 3: "MG_ERR_OOM", 4: "MG_ERR_HIP",
+          5: "MG_ERR_NOT_CONVERGED", 6: "MG_ERR_DIVERGED", 7: "MG_ERR_STATE", 8: "MG_ERR_UNSUPPORTED"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+FLAG_BACKWARD = 1
+
+EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
+            "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
+            "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_destroy", "mg_last_error"]
+KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5}
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _CSR(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class _Hier(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("A", C.POINTER(_CSR)), ("P", C.POINTER(_CSR)),
+                ("R", C.POINTER(_CSR)), ("G", C.POINTER(_CSR))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("KB", C.c_int32), ("KR", C.c_int32), ("KP", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("values", C.POINTER(C.c_double))]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("nrhs", C.c_int32), ("max_outer", C.c_int32),
+                ("check_every", C.c_int32), ("rtol", C.c_double), ("diverge_factor", C.c_double),
+                ("flags", C.c_int32)]
+
+
+class RhsInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmgl.so once; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run `python -m paper_2608_29082_amd.build`")
+    lib = C.CDLL(path)
+    vp, sz = C.c_void_p, C.c_size_t
+    lib.mg_num_params.restype = C.c_int64
+    lib.mg_num_params.argtypes = [C.c_int32] * 4
+    lib.mg_workspace_bytes.argtypes = [C.POINTER(_Hier), C.POINTER(_Params), C.POINTER(_Options),
+                                       C.POINTER(sz), C.POINTER(sz)]
+    lib.mg_setup.argtypes = [C.POINTER(_Hier), C.POINTER(_Params), C.POINTER(_Options), vp, sz, vp,
+                             C.POINTER(vp)]
+    lib.mg_set_params.argtypes = [vp, C.POINTER(C.c_double), vp]
+    lib.mg_vcycle.argtypes = [vp, vp, vp, vp, vp]
+    lib.mg_vcycle_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.mg_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mg_refine_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mg_refine_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.mg_solve.argtypes = [vp, vp, vp, C.POINTER(RhsInfo), vp]
+    lib.mg_level_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.mg_timing_start.argtypes = [vp, C.c_int32]
+    lib.mg_timing_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.mg_destroy.argtypes = [vp]
+    lib.mg_destroy.restype = None
+    lib.mg_last_error.restype = C.c_char_p
+    for name in ("mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle", "mg_vcycle_backward",
+                 "mg_residual", "mg_refine_step", "mg_refine_step_backward", "mg_solve", "mg_level_info",
+                 "mg_timing_start", "mg_timing_read"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str = ""):
+    if status != 0:
+        msg = _lib.mg_last_error().decode() if _lib is not None else ""
+        raise MGError(status, f"{what}: {msg}")
+
+
+def num_params(nlevels: int, KB: int, KR: int, KP: int) -> int:
+    return int(load_library().mg_num_params(nlevels, KB, KR, KP))
+
+
+class _HostHierarchy:
+    """Keeps the numpy arrays behind the ctypes CSR descriptors alive."""
+
+    def __init__(self, A, P, R=None, G=None):
+        self._keep = []
+        J = len(A)
+        self.A = self._csr_array(A)
+        self.P = self._csr_array(P)
+        self.R = self._csr_array(R) if R is not None else None
+        self.G = self._csr_array(G, pattern=True) if G is not None else None
+        self.h = _Hier(J, self.A, self.P, self.R if self.R is not None else C.POINTER(_CSR)(),
+                       self.G if self.G is not None else C.POINTER(_CSR)())
+
+    def _csr_array(self, mats, pattern=False):
+        arr = (_CSR * len(mats))()
+        for k, m in enumerate(mats):
+            m = m.tocsr()
+            rp = np.ascontiguousarray(m.indptr, dtype=np.int32)
+            ci = np.ascontiguousarray(m.indices, dtype=np.int32)
+            va = np.ascontiguousarray(m.data, dtype=np.float64)
+            self._keep += [rp, ci, va]
+            arr[k] = _CSR(m.shape[0], m.shape[1], m.nnz,
+                          rp.ctypes.data_as(C.POINTER(C.c_int32)), ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                          va.ctypes.data_as(C.POINTER(C.c_double)))
+        self._keep.append(arr)
+        return arr
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class SolveInfo:
+    iters: np.ndarray
+    status: np.ndarray
+    relres: np.ndarray
+    code: int
+
+
+class Context:
+    """A set-up learnable V-cycle on one GPU (wraps mg_ctx).
+
+    A, P: lists of scipy sparse matrices (levels 0..J-1, 0 finest);
+    params: flat float64 parameter vector; precision: "fp64", "fp32" or "bf16".
+    """
+
+    def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
+                 R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
+                 backward=False, device=None, stream=None, workspace=True):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device or "cuda")
+        self.J = len(A)
+        self.KB, self.KR, self.KP = KB, KR, KP
+        self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.precision = precision
+        self.B = nrhs
+        self.n = [a.shape[0] for a in A]
+        self.cycle_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.nparams = num_params(self.J, KB, KR, KP)
+        self._hh = _HostHierarchy(A, P, R, G)
+        self._params = np.ascontiguousarray(params, dtype=np.float64)
+        if self._params.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {self._params.size}")
+        self._p = _Params(KB, KR, KP, nu_pre, nu_post, self._params.ctypes.data_as(C.POINTER(C.c_double)))
+        self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
+                           FLAG_BACKWARD if backward else 0)
+        ws, ck = C.c_size_t(), C.c_size_t()
+        _check(self.lib.mg_workspace_bytes(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
+                                           C.byref(ws), C.byref(ck)), "mg_workspace_bytes")
+        self.workspace_bytes, self.ckpt_bytes = ws.value, ck.value
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device) if workspace else None
+        h = C.c_void_p()
+        _check(self.lib.mg_setup(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
+                                 _ptr(self._ws), self.workspace_bytes, self._s(), C.byref(h)), "mg_setup")
+        self._h = h
+        self._hh = None   # the library copied what it needs
+
+    # ------------------------------------------------------------------ helpers
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def _vec(self, t, dtype, name, n=None):
+        n = self.n[0] if n is None else n
+        if t is None:
+            return None
+        if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != (n, self.B):
+            raise ValueError(f"{name}: expected contiguous {dtype} CUDA tensor of shape ({n}, {self.B}), "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+        return t
+
+    def empty(self, dtype=None):
+        return self.torch.empty((self.n[0], self.B), dtype=dtype or self.cycle_dtype, device=self.device)
+
+    def new_ckpt(self):
+        return self.torch.empty(self.ckpt_bytes, dtype=self.torch.uint8, device=self.device)
+
+    # ------------------------------------------------------------------ entry points
+    def set_params(self, values):
+        self._params = np.ascontiguousarray(values, dtype=np.float64)
+        if self._params.size != self.nparams:
+            raise ValueError("wrong parameter count")
+        _check(self.lib.mg_set_params(self._h, self._params.ctypes.data_as(C.POINTER(C.c_double)), self._s()),
+               "mg_set_params")
+
+    @property
+    def params(self):
+        return self._params.copy()
+
+    def vcycle(self, f, u, ckpt=None):
+        """u <- LMG(A, f, u) in place (cycle dtype)."""
+        self._vec(f, self.cycle_dtype, "f")
+        self._vec(u, self.cycle_dtype, "u")
+        _check(self.lib.mg_vcycle(self._h, _ptr(f), _ptr(u), _ptr(ckpt), self._s()), "mg_vcycle")
+        return u
+
+    def vcycle_backward(self, ckpt, gu_out, want_gu=True, want_gf=True, want_gp=True):
+        self._vec(gu_out, self.cycle_dtype, "gu_out")
+        gu = self.empty() if want_gu else None
+        gf = self.empty() if want_gf else None
+        gp = self.torch.empty(self.nparams, dtype=self.torch.float64, device=self.device) if want_gp else None
+        _check(self.lib.mg_vcycle_backward(self._h, _ptr(ckpt), _ptr(gu_out), _ptr(gu), _ptr(gf), _ptr(gp),
+                                           self._s()), "mg_vcycle_backward")
+        return gu, gf, gp
+
+    def residual(self, f, u, want_r=True):
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u, self.torch.float64, "u")
+        r = self.empty(self.torch.float64) if want_r else None
+        norms = self.torch.empty(self.B, dtype=self.torch.float64, device=self.device)
+        _check(self.lib.mg_residual(self._h, _ptr(f), _ptr(u), _ptr(r), _ptr(norms), self._s()), "mg_residual")
+        return r, norms
+
+    def refine_step(self, f, u_in, u_out=None, ckpt=None):
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u_in, self.torch.float64, "u_in")
+        if u_out is None:
+            u_out = self.empty(self.torch.float64)
+        self._vec(u_out, self.torch.float64, "u_out")
+        _check(self.lib.mg_refine_step(self._h, _ptr(f), _ptr(u_in), _ptr(u_out), _ptr(ckpt), self._s()),
+               "mg_refine_step")
+        return u_out
+
+    def refine_step_backward(self, ckpt, gu_out, want_gu=True, want_gf=True, want_gp=True):
+        self._vec(gu_out, self.torch.float64, "gu_out")
+        gu = self.empty(self.torch.float64) if want_gu else None
+        gf = self.empty(self.torch.float64) if want_gf else None
+        gp = self.torch.empty(self.nparams, dtype=self.torch.float64, device=self.device) if want_gp else None
+        _check(self.lib.mg_refine_step_backward(self._h, _ptr(ckpt), _ptr(gu_out), _ptr(gu), _ptr(gf), _ptr(gp),
+                                                self._s()), "mg_refine_step_backward")
+        return gu, gf, gp
+
+    def solve(self, f, u, raise_on_failure=False) -> SolveInfo:
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u, self.torch.float64, "u")
+        info = (RhsInfo * self.B)()
+        st = self.lib.mg_solve(self._h, _ptr(f), _ptr(u), info, self._s())
+        if st not in (0, 5, 6) or (raise_on_failure and st != 0):
+            _check(st, "mg_solve")
+        return SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
+                         np.array([x.relres for x in info]), st)
+
+    def level_info(self):
+        n = (C.c_int64 * self.J)()
+        w = (C.c_int32 * self.J)()
+        _check(self.lib.mg_level_info(self._h, n, w), "mg_level_info")
+        return list(n), list(w)
+
+    def timing_start(self, family: str | None):
+        """Time every launch of one kernel family (see mg_timing_start)."""
+        _check(self.lib.mg_timing_start(self._h, KERNEL_FAMILIES[family] if family else 0), "mg_timing_start")
+
+    def timing_read(self):
+        """(launches, total_ms, total_algorithmic_bytes) of the timed family."""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        _check(self.lib.mg_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(by)), "mg_timing_read")
+        return n.value, ms.value, by.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.mg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_hierarchy(hier, params, KB, KR, KP, **kw) -> Context:
+    """Context from an object with A, P, R lists (e.g. a generated hierarchy)."""
+    return Context(hier.A, hier.P, params, KB, KR, KP, R=getattr(hier, "R", None), **kw)

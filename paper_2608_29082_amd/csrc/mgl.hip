@@ -1,0 +1,1211 @@
+// Host driver and C ABI of the learnable V-cycle (see include/mgl.h).
+//
+// mg_setup turns the host CSR hierarchy into device ELL structures inside one
+// workspace buffer; the V-cycle (paper Alg. 2), the refinement iteration
+// u^m = u^{m-1} + B(f - A u^{m-1}) (Sec. 1), the solver loop and the reverse
+// sweep used for training (Sec. 3.1) are sequences of the kernels of
+// kernels.hpp enqueued on the caller's stream.  Three precisions share the
+// code: FP64 throughout; FP32 cycles; FP32 cycles with BF16 intermediates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mgl.h"
+
+using namespace mgl;
+
+namespace {
+
+thread_local std::string g_err;
+
+mg_status fail(mg_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define MG_TRY(...)                            \
+  do {                                         \
+    mg_status s_ = (__VA_ARGS__);              \
+    if (s_ != MG_OK) return s_;                \
+  } while (0)
+#define HIP_TRY(x)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) return fail(MG_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define LAUNCH_OK()                                                                         \
+  do {                                                                                      \
+    hipError_t e_ = hipGetLastError();                                                      \
+    if (e_ != hipSuccess) return fail(MG_ERR_HIP, std::string("kernel launch at line ") +   \
+                                                   std::to_string(__LINE__) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// launch `...` bracketed by the timing events of kernel family `fam`
+#define TIMED(fam, bytes, ...)                   \
+  do {                                           \
+    MG_TRY(tmark((fam), false, 0.0, st));        \
+    __VA_ARGS__;                                 \
+    LAUNCH_OK();                                 \
+    MG_TRY(tmark((fam), true, (bytes), st));     \
+  } while (0)
+
+constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 1024;
+
+// ------------------------------------------------------------------ host-side structures
+struct HEll {          // slot-major ELL
+  int n = 0, w = 0;
+  std::vector<int> col;
+  std::vector<double> val;
+};
+
+struct HLevel {
+  int n = 0;
+  std::vector<double> diag;
+  HEll off;            // off-diagonal nonzeros of A
+  bool graph_is_A = true;
+  HEll graph;          // only when a separate graph was given
+  std::vector<double> invdeg;
+  bool sym_graph = false, sym_A = false;
+};
+
+mg_status check_csr(const mg_csr* m, const char* what, int l) {
+  const std::string w = std::string(what) + "[" + std::to_string(l) + "]";
+  if (!m || !m->rowptr || (m->nnz > 0 && !m->col)) return fail(MG_ERR_INVALID_ARG, w + ": null array");
+  if (m->nrows < 1 || m->ncols < 1 || m->nnz < 0) return fail(MG_ERR_SHAPE, w + ": bad dimensions");
+  if (m->rowptr[0] != 0 || m->rowptr[m->nrows] != m->nnz) return fail(MG_ERR_SHAPE, w + ": rowptr ends");
+  for (int i = 0; i < m->nrows; ++i) {
+    if (m->rowptr[i + 1] < m->rowptr[i]) return fail(MG_ERR_SHAPE, w + ": rowptr not monotone");
+    for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p) {
+      const int j = m->col[p];
+      if (j < 0 || j >= m->ncols) return fail(MG_ERR_SHAPE, w + ": column out of range");
+      if (p > m->rowptr[i] && m->col[p - 1] >= j) return fail(MG_ERR_SHAPE, w + ": columns not sorted/unique");
+    }
+  }
+  return MG_OK;
+}
+
+bool has_entry(const mg_csr* m, int i, int j, double* v) {
+  const int* b = m->col + m->rowptr[i];
+  const int* e = m->col + m->rowptr[i + 1];
+  const int* p = std::lower_bound(b, e, j);
+  if (p == e || *p != j) return false;
+  if (v) *v = m->val ? m->val[p - m->col] : 0.0;
+  return true;
+}
+
+mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
+  const int n = A->nrows;
+  L.n = n;
+  L.diag.assign(n, 0.0);
+  if (!A->val) return fail(MG_ERR_INVALID_ARG, "A values missing");
+  std::vector<int> cnt(n, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+      if (A->col[p] == i) L.diag[i] = A->val[p];
+      else if (A->val[p] != 0.0) cnt[i]++;
+    }
+    if (!(L.diag[i] != 0.0) || !std::isfinite(L.diag[i]))
+      return fail(MG_ERR_SHAPE, "A[" + std::to_string(l) + "]: zero or non-finite diagonal at row " + std::to_string(i));
+  }
+  int w = 0;
+  for (int c : cnt) w = std::max(w, c);
+  if (w > kMaxW) return fail(MG_ERR_UNSUPPORTED, "A[" + std::to_string(l) + "]: more than 64 off-diagonal entries in a row");
+  L.off.n = n;
+  L.off.w = w;
+  L.off.col.assign((size_t)w * n, 0);
+  L.off.val.assign((size_t)w * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    int k = 0;
+    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
+      if (A->col[p] != i && A->val[p] != 0.0) {
+        L.off.col[(size_t)k * n + i] = A->col[p];
+        L.off.val[(size_t)k * n + i] = A->val[p];
+        ++k;
+      }
+    for (; k < w; ++k) L.off.col[(size_t)k * n + i] = i;
+  }
+  // graph
+  std::vector<int> deg(n, 0);
+  L.graph_is_A = (G == nullptr);
+  if (G) {
+    int wg = 0;
+    for (int i = 0; i < n; ++i) {
+      int c = 0;
+      for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p) c += (G->col[p] != i);
+      deg[i] = c;
+      wg = std::max(wg, c);
+    }
+    if (wg > kMaxW) return fail(MG_ERR_UNSUPPORTED, "G: more than 64 neighbours");
+    L.graph.n = n;
+    L.graph.w = wg;
+    L.graph.col.assign((size_t)wg * n, 0);
+    for (int i = 0; i < n; ++i) {
+      int k = 0;
+      for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p)
+        if (G->col[p] != i) L.graph.col[(size_t)(k++) * n + i] = G->col[p];
+      for (; k < wg; ++k) L.graph.col[(size_t)k * n + i] = i;
+    }
+  } else {
+    deg = cnt;
+  }
+  L.invdeg.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) L.invdeg[i] = deg[i] > 0 ? 1.0 / deg[i] : 0.0;
+  // symmetry of the graph and of A (needed by the reverse sweep)
+  L.sym_A = true;
+  for (int i = 0; i < n && L.sym_A; ++i)
+    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+      double v = 0.0;
+      if (!has_entry(A, A->col[p], i, &v) || v != A->val[p]) {
+        // an explicit zero may lack its mirror
+        if (A->val[p] == 0.0 && !has_entry(A, A->col[p], i, nullptr)) continue;
+        L.sym_A = false;
+        break;
+      }
+    }
+  if (!G) {
+    L.sym_graph = L.sym_A;
+  } else {
+    L.sym_graph = true;
+    for (int i = 0; i < n && L.sym_graph; ++i)
+      for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p)
+        if (G->col[p] != i && !has_entry(G, G->col[p], i, nullptr)) { L.sym_graph = false; break; }
+  }
+  return MG_OK;
+}
+
+HEll ell_from_csr(const mg_csr* m) {
+  HEll e;
+  e.n = m->nrows;
+  int w = 0;
+  for (int i = 0; i < m->nrows; ++i) w = std::max(w, m->rowptr[i + 1] - m->rowptr[i]);
+  e.w = w;
+  e.col.assign((size_t)w * e.n, 0);
+  e.val.assign((size_t)w * e.n, 0.0);
+  for (int i = 0; i < e.n; ++i) {
+    int k = 0;
+    for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p, ++k) {
+      e.col[(size_t)k * e.n + i] = m->col[p];
+      e.val[(size_t)k * e.n + i] = m->val ? m->val[p] : 0.0;
+    }
+  }
+  return e;
+}
+
+HEll ell_transpose(const mg_csr* m) {
+  std::vector<int> cnt(m->ncols, 0);
+  for (int64_t p = 0; p < m->nnz; ++p) cnt[m->col[p]]++;
+  HEll e;
+  e.n = m->ncols;
+  int w = 0;
+  for (int c : cnt) w = std::max(w, c);
+  e.w = w;
+  e.col.assign((size_t)w * e.n, 0);
+  e.val.assign((size_t)w * e.n, 0.0);
+  std::vector<int> fill(m->ncols, 0);
+  for (int i = 0; i < m->nrows; ++i)
+    for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p) {
+      const int j = m->col[p];
+      const int k = fill[j]++;
+      e.col[(size_t)k * e.n + j] = i;
+      e.val[(size_t)k * e.n + j] = m->val[p];
+    }
+  return e;
+}
+
+struct HostPlan {
+  int J = 0, B = 1, prec = 0, KB = 0, KR = 0, KP = 0, nu_pre = 0, nu_post = 0, flags = 0;
+  int max_outer = 1, check_every = 1;
+  double rtol = 1e-8, divf = 1e6;
+  std::vector<HLevel> lv;
+  std::vector<HEll> P, R, PT, RT;
+  bool R_is_PT = true;
+  std::vector<double> Acoarse;   // dense n_J x n_J row-major
+  std::vector<double> params;
+  bool sym_all = true;
+};
+
+int64_t num_params(int J, int KB, int KR, int KP) { return (int64_t)(J - 1) * (2 + (KB + 1) + (KR + 1) + (KP + 1)); }
+
+mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options* o, HostPlan& pl, bool full) {
+  if (!h || !p || !o) return fail(MG_ERR_INVALID_ARG, "null hierarchy, params or options");
+  if (h->nlevels < 2 || !h->A || !h->P) return fail(MG_ERR_INVALID_ARG, "need nlevels >= 2 with A and P");
+  if (o->nrhs < 1 || o->nrhs > kMaxB) return fail(MG_ERR_INVALID_ARG, "nrhs must be in 1..256");
+  if (o->precision < 0 || o->precision > 2) return fail(MG_ERR_INVALID_ARG, "unknown precision");
+  if (p->KB < 0 || p->KR < 0 || p->KP < 0 || p->KB > kMaxK || p->KR > kMaxK || p->KP > kMaxK)
+    return fail(MG_ERR_INVALID_ARG, "convolution orders must be in 0..8");
+  if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre > kMaxNu || p->nu_post > kMaxNu)
+    return fail(MG_ERR_INVALID_ARG, "smoothing steps must be in 0..8");
+  if (o->max_outer < 1 || o->check_every < 1) return fail(MG_ERR_INVALID_ARG, "max_outer and check_every must be >= 1");
+  if (!(o->rtol >= 0.0)) return fail(MG_ERR_INVALID_ARG, "rtol must be >= 0");
+  const int J = h->nlevels;
+  pl.J = J; pl.B = o->nrhs; pl.prec = o->precision; pl.KB = p->KB; pl.KR = p->KR; pl.KP = p->KP;
+  pl.nu_pre = p->nu_pre; pl.nu_post = p->nu_post; pl.flags = o->flags;
+  pl.max_outer = o->max_outer; pl.check_every = o->check_every; pl.rtol = o->rtol; pl.divf = o->diverge_factor;
+  for (int l = 0; l < J; ++l) {
+    MG_TRY(check_csr(&h->A[l], "A", l));
+    if (h->A[l].nrows != h->A[l].ncols) return fail(MG_ERR_SHAPE, "A[" + std::to_string(l) + "] not square");
+    if (h->G) {
+      MG_TRY(check_csr(&h->G[l], "G", l));
+      if (h->G[l].nrows != h->A[l].nrows || h->G[l].ncols != h->A[l].nrows) return fail(MG_ERR_SHAPE, "G shape");
+    }
+  }
+  for (int l = 0; l + 1 < J; ++l) {
+    MG_TRY(check_csr(&h->P[l], "P", l));
+    if (!h->P[l].val) return fail(MG_ERR_INVALID_ARG, "P values missing");
+    if (h->P[l].nrows != h->A[l].nrows || h->P[l].ncols != h->A[l + 1].nrows)
+      return fail(MG_ERR_SHAPE, "P[" + std::to_string(l) + "] must be n_l x n_{l+1}");
+    if (h->R) {
+      MG_TRY(check_csr(&h->R[l], "R", l));
+      if (!h->R[l].val) return fail(MG_ERR_INVALID_ARG, "R values missing");
+      if (h->R[l].nrows != h->A[l + 1].nrows || h->R[l].ncols != h->A[l].nrows)
+        return fail(MG_ERR_SHAPE, "R[" + std::to_string(l) + "] must be n_{l+1} x n_l");
+    }
+  }
+  if (J > 32) return fail(MG_ERR_UNSUPPORTED, "at most 32 levels");
+  if (h->A[J - 1].nrows > 4096) return fail(MG_ERR_UNSUPPORTED, "coarsest level larger than 4096 unknowns");
+  if (p->values == nullptr) return fail(MG_ERR_INVALID_ARG, "params.values is null");
+  const int64_t np = num_params(J, p->KB, p->KR, p->KP);
+  pl.params.assign(p->values, p->values + np);
+  for (double v : pl.params)
+    if (!std::isfinite(v)) return fail(MG_ERR_INVALID_ARG, "non-finite parameter");
+  pl.lv.resize(J);
+  for (int l = 0; l < J; ++l) {
+    if (full) {
+      MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l));
+      pl.sym_all = pl.sym_all && pl.lv[l].sym_A && pl.lv[l].sym_graph;
+    } else {
+      // sizes only: widths from row counts
+      HLevel& L = pl.lv[l];
+      L.n = h->A[l].nrows;
+      int w = 0;
+      for (int i = 0; i < L.n; ++i) w = std::max(w, h->A[l].rowptr[i + 1] - h->A[l].rowptr[i]);
+      L.off.n = L.n;
+      L.off.w = w;
+      L.graph_is_A = (h->G == nullptr);
+      if (h->G) {
+        int wg = 0;
+        for (int i = 0; i < L.n; ++i) wg = std::max(wg, h->G[l].rowptr[i + 1] - h->G[l].rowptr[i]);
+        L.graph.n = L.n;
+        L.graph.w = wg;
+      }
+    }
+  }
+  pl.P.resize(J - 1); pl.R.resize(J - 1); pl.PT.resize(J - 1); pl.RT.resize(J - 1);
+  pl.R_is_PT = (h->R == nullptr);
+  for (int l = 0; l + 1 < J; ++l) {
+    if (full) {
+      pl.P[l] = ell_from_csr(&h->P[l]);
+      pl.PT[l] = ell_transpose(&h->P[l]);
+      if (h->R) {
+        pl.R[l] = ell_from_csr(&h->R[l]);
+        pl.RT[l] = ell_transpose(&h->R[l]);
+        // R == P^T exactly?  then the transposes alias
+        bool same = pl.R[l].w == pl.PT[l].w && pl.R[l].col == pl.PT[l].col && pl.R[l].val == pl.PT[l].val;
+        pl.R_is_PT = pl.R_is_PT && same;
+      }
+    } else {
+      auto rows_w = [](const mg_csr* m) {
+        int w = 0;
+        for (int i = 0; i < m->nrows; ++i) w = std::max(w, m->rowptr[i + 1] - m->rowptr[i]);
+        return w;
+      };
+      auto cols_w = [](const mg_csr* m) {
+        std::vector<int> c(m->ncols, 0);
+        for (int64_t q = 0; q < m->nnz; ++q) c[m->col[q]]++;
+        int w = 0;
+        for (int x : c) w = std::max(w, x);
+        return w;
+      };
+      pl.P[l].n = h->P[l].nrows; pl.P[l].w = rows_w(&h->P[l]);
+      pl.PT[l].n = h->P[l].ncols; pl.PT[l].w = cols_w(&h->P[l]);
+      if (h->R) {
+        pl.R[l].n = h->R[l].nrows; pl.R[l].w = rows_w(&h->R[l]);
+        pl.RT[l].n = h->R[l].ncols; pl.RT[l].w = cols_w(&h->R[l]);
+      }
+    }
+  }
+  if (h->R == nullptr) pl.R_is_PT = true;
+  if (full) {
+    const mg_csr* Ac = &h->A[J - 1];
+    const int n = Ac->nrows;
+    pl.Acoarse.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int q = Ac->rowptr[i]; q < Ac->rowptr[i + 1]; ++q) pl.Acoarse[(size_t)i * n + Ac->col[q]] = Ac->val[q];
+  }
+  return MG_OK;
+}
+
+// ------------------------------------------------------------------ workspace bump allocator
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+inline int lb_shift(int B) {
+  int s = 0;
+  while ((1 << s) < B && s < 6) ++s;
+  return s;
+}
+inline unsigned nblocks(long threads) { return (unsigned)((threads + 255) / 256); }
+
+struct EngineBase {
+  virtual mg_status vcycle(const void* f, void* u, void* ck, hipStream_t st) = 0;
+  virtual mg_status vcycle_bwd(const void* ck, const void* gout, void* gin, void* gf, double* gp, hipStream_t st) = 0;
+  virtual mg_status residual(const double* f, const double* u, double* r, double* norms, hipStream_t st) = 0;
+  virtual mg_status refine(const double* f, const double* uin, double* uout, void* ck, hipStream_t st) = 0;
+  virtual mg_status refine_bwd(const void* ck, const double* gout, double* gin, double* gf, double* gp, hipStream_t st) = 0;
+  virtual mg_status solve(const double* f, double* u, mg_rhs_info* info, hipStream_t st) = 0;
+  virtual mg_status set_params(const double* v, hipStream_t st) = 0;
+  virtual mg_status setup(void* ws, hipStream_t st) = 0;
+  virtual size_t ws_bytes() = 0;
+  virtual size_t ck_bytes() = 0;
+  HostPlan pl;
+  std::vector<int64_t> sizes;
+  std::vector<int32_t> widths;
+
+  // ---- launch timing (instrumentation)
+  int tfam = MG_KF_NONE;
+  std::vector<hipEvent_t> tev;   // start/stop pairs, reused across runs
+  size_t tn = 0;                 // pairs recorded
+  double tbytes = 0.0;
+  virtual ~EngineBase() {
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+  }
+  mg_status timing_start(int fam) {
+    tfam = fam;
+    tn = 0;
+    tbytes = 0.0;
+    return MG_OK;
+  }
+  // record one event of the pair for launch family `fam`; returns false when not timed
+  mg_status tmark(int fam, bool stop, double bytes, hipStream_t st) {
+    if (fam != tfam || tfam == MG_KF_NONE) return MG_OK;
+    const size_t k = 2 * tn + (stop ? 1 : 0);
+    while (tev.size() <= k) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      tev.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(tev[k], st));
+    if (stop) {
+      ++tn;
+      tbytes += bytes;
+    }
+    return MG_OK;
+  }
+  mg_status timing_read(int64_t* n, double* ms, double* bytes) {
+    double tot = 0.0;
+    if (tn) HIP_TRY(hipEventSynchronize(tev[2 * tn - 1]));
+    for (size_t k = 0; k < tn; ++k) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, tev[2 * k], tev[2 * k + 1]));
+      tot += t;
+    }
+    if (n) *n = (int64_t)tn;
+    if (ms) *ms = tot;
+    if (bytes) *bytes = tbytes;
+    return MG_OK;
+  }
+};
+
+// ------------------------------------------------------------------ engine
+template <class C, class TU, class TH>
+struct Engine final : EngineBase {
+  struct DL {
+    Lvl<C> L{};
+    Xfer<C> P{}, R{}, PT{}, RT{};   // P: n_l x n_{l+1}, R: n_{l+1} x n_l, PT = P^T, RT = R^T
+    TU *f = nullptr, *u = nullptr;  // levels >= 1
+    TH *s = nullptr, *ya = nullptr, *yb = nullptr, *x = nullptr;
+    TU* r = nullptr;
+    // reverse sweep
+    TH* S[2 * kMaxNu] = {};
+    TU *Rv = nullptr, *ut = nullptr, *g = nullptr, *za = nullptr, *zb = nullptr, *acc = nullptr, *q = nullptr,
+       *gfo = nullptr, *gin = nullptr;
+    TH* X = nullptr;
+    unsigned blocks = 0;            // n * LB / 256
+  };
+  std::vector<DL> d;
+  Lvl<double> L64{};                // level-0 operator in FP64 (outer residual)
+  double* Ainv = nullptr;           // coarsest inverse, row-major
+  double* gj = nullptr;             // Gauss-Jordan scratch n x 2n
+  int* dinfo = nullptr;
+  TU *r0 = nullptr, *e0 = nullptr;  // refinement: cycle input / output (level 0)
+  double* dbuf = nullptr;           // FP64 level-0 scratch
+  double *part = nullptr, *norms = nullptr, *fnorm = nullptr, *init = nullptr;
+  int* dstat = nullptr;
+  double *dots = nullptr, *dpart = nullptr, *dprm = nullptr;
+  long* doff = nullptr;
+  int *dcnt = nullptr, *ddesc = nullptr;
+  int nslots = 0;
+  std::vector<long> h_off;
+  std::vector<int> h_cnt, h_desc;
+  int* hcount = nullptr;            // pinned host
+  char* wsbase = nullptr;
+  bool owns_ws = false;
+  int lbs = 0;
+  // device-side host copies kept alive during setup
+  std::vector<std::vector<char>> staging;
+
+  ~Engine() override {
+    if (owns_ws && wsbase) (void)hipFree(wsbase);
+    if (hcount) (void)hipHostFree(hcount);
+  }
+
+  bool bwd() const { return (pl.flags & MG_FLAG_BACKWARD) != 0; }
+  int per() const { return 2 + (pl.KB + 1) + (pl.KR + 1) + (pl.KP + 1); }
+  double theta(int l) const { return pl.params[(size_t)l * per()]; }
+  double eta(int l) const { return pl.params[(size_t)l * per() + 1]; }
+  const double* cB(int l) const { return &pl.params[(size_t)l * per() + 2]; }
+  const double* cR(int l) const { return cB(l) + pl.KB + 1; }
+  const double* cP(int l) const { return cR(l) + pl.KR + 1; }
+
+  // slots of the reverse sweep, in launch order (kind, level, k)
+  void enum_slots(int l) {
+    const int J = pl.J;
+    if (l == J - 1) return;
+    auto add = [&](int kind, int K) {
+      for (int k = 0; k <= K; ++k) {
+        h_desc.push_back(kind); h_desc.push_back(l); h_desc.push_back(k);
+        h_cnt.push_back((int)d[l].blocks);
+        h_off.push_back(h_off.empty() ? 0 : h_off.back() + h_cnt[h_cnt.size() - 2]);
+      }
+    };
+    for (int j = 0; j < pl.nu_post; ++j) add(0, pl.KB);
+    add(2, pl.KP);
+    enum_slots(l + 1);
+    add(1, pl.KR);
+    for (int j = 0; j < pl.nu_pre; ++j) add(0, pl.KB);
+  }
+
+  // assign device pointers (base == nullptr: sizes only)
+  size_t carve(char* base) {
+    Bump bp;
+    bp.base = base;
+    const int J = pl.J, B = pl.B;
+    d.assign(J, DL{});
+    lbs = lb_shift(B);
+    for (int l = 0; l < J; ++l) {
+      const HLevel& H = pl.lv[l];
+      DL& x = d[l];
+      const int n = H.n;
+      x.blocks = nblocks((long)n << lbs);
+      x.L.n = n;
+      x.L.w = H.off.w;
+      x.L.col = bp.take<int>((size_t)H.off.w * n);
+      x.L.val = bp.take<C>((size_t)H.off.w * n);
+      x.L.diag = bp.take<C>(n);
+      x.L.invdiag = bp.take<C>(n);
+      x.L.invdeg = bp.take<C>(n);
+      if (H.graph_is_A) {
+        x.L.wg = H.off.w;
+        x.L.gcol = x.L.col;
+      } else {
+        x.L.wg = H.graph.w;
+        x.L.gcol = bp.take<int>((size_t)H.graph.w * n);
+      }
+      const size_t nv = (size_t)n * B;
+      if (l > 0) { x.f = bp.take<TU>(nv); x.u = bp.take<TU>(nv); }
+      x.s = bp.take<TH>(nv); x.ya = bp.take<TH>(nv); x.yb = bp.take<TH>(nv); x.x = bp.take<TH>(nv);
+      x.r = bp.take<TU>(nv);
+      if (bwd()) {
+        for (int j = 0; j < pl.nu_pre + pl.nu_post; ++j) x.S[j] = bp.take<TH>(nv);
+        x.Rv = bp.take<TU>(nv); x.X = bp.take<TH>(nv); x.ut = bp.take<TU>(nv); x.g = bp.take<TU>(nv);
+        x.za = bp.take<TU>(nv); x.zb = bp.take<TU>(nv); x.acc = bp.take<TU>(nv); x.q = bp.take<TU>(nv);
+        x.gfo = bp.take<TU>(nv); x.gin = bp.take<TU>(nv);
+      }
+    }
+    for (int l = 0; l + 1 < J; ++l) {
+      DL& x = d[l];
+      auto mk = [&](const HEll& e, Xfer<C>& t) {
+        t.n = e.n; t.w = e.w;
+        t.col = bp.take<int>((size_t)e.w * e.n);
+        t.val = bp.take<C>((size_t)e.w * e.n);
+      };
+      mk(pl.P[l], x.P);
+      mk(pl.PT[l], x.PT);
+      if (pl.R_is_PT) { x.R = x.PT; x.RT = x.P; }
+      else { mk(pl.R[l], x.R); mk(pl.RT[l], x.RT); }
+    }
+    if constexpr (std::is_same<C, double>::value) {
+      L64 = d[0].L;
+    } else {
+      L64.n = d[0].L.n; L64.w = d[0].L.w; L64.col = d[0].L.col; L64.wg = d[0].L.wg; L64.gcol = d[0].L.gcol;
+      L64.val = bp.take<double>((size_t)pl.lv[0].off.w * pl.lv[0].n);
+      L64.diag = bp.take<double>(pl.lv[0].n);
+      L64.invdiag = nullptr;
+      L64.invdeg = nullptr;
+    }
+    const int nJ = pl.lv[J - 1].n;
+    Ainv = bp.take<double>((size_t)nJ * nJ);
+    gj = bp.take<double>((size_t)nJ * 2 * nJ);
+    dinfo = bp.take<int>(1);
+    const size_t n0B = (size_t)pl.lv[0].n * B;
+    r0 = bp.take<TU>(n0B);
+    e0 = bp.take<TU>(n0B);
+    dbuf = bp.take<double>(n0B);
+    part = bp.take<double>((size_t)kOuterBlocks * B);
+    norms = bp.take<double>(B);
+    fnorm = bp.take<double>(B);
+    init = bp.take<double>(B);
+    dstat = bp.take<int>(3 * B + 1);
+    dprm = bp.take<double>(pl.params.size());
+    if (bwd()) {
+      h_off.clear(); h_cnt.clear(); h_desc.clear();
+      enum_slots(0);
+      nslots = (int)h_cnt.size();
+      const long tot = nslots ? h_off.back() + h_cnt.back() : 0;
+      dpart = bp.take<double>(tot);
+      dots = bp.take<double>(nslots);
+      doff = bp.take<long>(nslots);
+      dcnt = bp.take<int>(nslots);
+      ddesc = bp.take<int>(3 * (size_t)nslots);
+    }
+    return bp.off + 256;
+  }
+
+  size_t ws_bytes() override { return carve(nullptr); }
+
+  size_t ck_bytes() override {
+    size_t b = 0;
+    for (int l = 0; l < pl.J; ++l) b += 2 * (((size_t)pl.lv[l].n * pl.B * sizeof(TU) + 255) & ~size_t(255));
+    return b;
+  }
+
+  struct Ck {
+    TU* f[32];
+    TU* u[32];
+  };
+  Ck ck_ptrs(void* base) const {
+    Ck c{};
+    char* p = static_cast<char*>(base);
+    for (int l = 0; l < pl.J; ++l) {
+      const size_t b = ((size_t)pl.lv[l].n * pl.B * sizeof(TU) + 255) & ~size_t(255);
+      c.f[l] = reinterpret_cast<TU*>(p); p += b;
+      c.u[l] = reinterpret_cast<TU*>(p); p += b;
+    }
+    return c;
+  }
+
+  template <class T>
+  mg_status up(T* dst, const std::vector<double>& src, hipStream_t st) {
+    if (src.empty()) return MG_OK;
+    std::vector<char> buf(src.size() * sizeof(T));
+    T* t = reinterpret_cast<T*>(buf.data());
+    for (size_t i = 0; i < src.size(); ++i) t[i] = (T)src[i];
+    HIP_TRY(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
+    staging.push_back(std::move(buf));
+    return MG_OK;
+  }
+  mg_status upi(const int* dst, const std::vector<int>& src, hipStream_t st) {
+    if (src.empty()) return MG_OK;
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(dst), src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    return MG_OK;
+  }
+
+  mg_status setup(void* ws, hipStream_t st) override {
+    const size_t need = ws_bytes();
+    if (ws) {
+      wsbase = static_cast<char*>(ws);
+    } else {
+      HIP_TRY(hipMalloc(&wsbase, need));
+      owns_ws = true;
+    }
+    carve(wsbase);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&hcount), sizeof(int) * 4, hipHostMallocDefault));
+    const int J = pl.J;
+    for (int l = 0; l < J; ++l) {
+      const HLevel& H = pl.lv[l];
+      DL& x = d[l];
+      MG_TRY(upi(x.L.col, H.off.col, st));
+      MG_TRY(up(const_cast<C*>(x.L.val), H.off.val, st));
+      MG_TRY(up(const_cast<C*>(x.L.diag), H.diag, st));
+      std::vector<double> inv(H.n);
+      for (int i = 0; i < H.n; ++i) inv[i] = 1.0 / H.diag[i];
+      MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
+      MG_TRY(up(const_cast<C*>(x.L.invdeg), H.invdeg, st));
+      if (!H.graph_is_A) MG_TRY(upi(x.L.gcol, H.graph.col, st));
+    }
+    for (int l = 0; l + 1 < J; ++l) {
+      DL& x = d[l];
+      MG_TRY(upi(x.P.col, pl.P[l].col, st));
+      MG_TRY(up(const_cast<C*>(x.P.val), pl.P[l].val, st));
+      MG_TRY(upi(x.PT.col, pl.PT[l].col, st));
+      MG_TRY(up(const_cast<C*>(x.PT.val), pl.PT[l].val, st));
+      if (!pl.R_is_PT) {
+        MG_TRY(upi(x.R.col, pl.R[l].col, st));
+        MG_TRY(up(const_cast<C*>(x.R.val), pl.R[l].val, st));
+        MG_TRY(upi(x.RT.col, pl.RT[l].col, st));
+        MG_TRY(up(const_cast<C*>(x.RT.val), pl.RT[l].val, st));
+      }
+    }
+    if (!std::is_same<C, double>::value) {
+      MG_TRY(up(const_cast<double*>(L64.val), pl.lv[0].off.val, st));
+      MG_TRY(up(const_cast<double*>(L64.diag), pl.lv[0].diag, st));
+    }
+    // coarsest inverse: W = [A | I], Gauss-Jordan on the device
+    const int nJ = pl.lv[J - 1].n;
+    std::vector<double> W((size_t)nJ * 2 * nJ, 0.0);
+    for (int i = 0; i < nJ; ++i) {
+      for (int j = 0; j < nJ; ++j) W[(size_t)i * 2 * nJ + j] = pl.Acoarse[(size_t)i * nJ + j];
+      W[(size_t)i * 2 * nJ + nJ + i] = 1.0;
+    }
+    MG_TRY(up(gj, W, st));
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, nJ, gj, dinfo);
+    LAUNCH_OK();
+    HIP_TRY(hipMemcpy2DAsync(Ainv, nJ * sizeof(double), gj + nJ, 2 * nJ * sizeof(double), nJ * sizeof(double), nJ,
+                             hipMemcpyDeviceToDevice, st));
+    MG_TRY(up(dprm, pl.params, st));
+    if (bwd()) {
+      HIP_TRY(hipMemcpyAsync(doff, h_off.data(), h_off.size() * sizeof(long), hipMemcpyHostToDevice, st));
+      MG_TRY(upi(dcnt, h_cnt, st));
+      MG_TRY(upi(ddesc, h_desc, st));
+    }
+    int info = 0;
+    HIP_TRY(hipMemcpyAsync(hcount, dinfo, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    info = hcount[0];
+    staging.clear();
+    staging.shrink_to_fit();
+    if (info != 0) return fail(MG_ERR_SHAPE, "coarsest matrix is singular (zero pivot in column " + std::to_string(info - 1) + ")");
+    sizes.resize(J);
+    widths.resize(J);
+    for (int l = 0; l < J; ++l) { sizes[l] = pl.lv[l].n; widths[l] = pl.lv[l].off.w; }
+    return MG_OK;
+  }
+
+  mg_status set_params(const double* v, hipStream_t st) override {
+    for (size_t i = 0; i < pl.params.size(); ++i)
+      if (!std::isfinite(v[i])) return fail(MG_ERR_INVALID_ARG, "non-finite parameter");
+    pl.params.assign(v, v + pl.params.size());
+    HIP_TRY(hipMemcpyAsync(dprm, pl.params.data(), pl.params.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MG_OK;
+  }
+
+  // ---------------------------------------------------------------- forward building blocks
+  int B() const { return pl.B; }
+
+  template <class TY, class TX, class TO>
+  mg_status hop(int l, const TY* yin, double a, const TX* x, double c, TO* out, int mode, double scale, int oz,
+                hipStream_t st) {
+    const DL& D = d[l];
+    const double nB = (double)D.L.n * B();
+    const double bytes = nB * (sizeof(TY) + sizeof(TX) + sizeof(TO) * (mode ? 2 : 1)) +
+                         (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C);
+    TIMED(MG_KF_HOP, bytes,
+          hipLaunchKernelGGL((k_hop<C, TY, TX, TO>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, yin, (C)a, x,
+                             (C)c, out, mode, (C)scale, oz));
+    return MG_OK;
+  }
+
+  // algorithmic bytes of streaming A_l once (ELL indices, values, diagonal)
+  double bytes_A(int l) const { return (double)d[l].L.w * d[l].L.n * (4 + sizeof(C)) + (double)d[l].L.n * sizeof(C); }
+  double bytes_X(const Xfer<C>& x) const { return (double)x.w * x.n * (4 + sizeof(C)); }
+  double nB(int l) const { return (double)d[l].L.n * B(); }
+
+  // u = (oz ? 0 : u) + scale * sum_k c_k M^k x
+  mg_status conv_add(int l, const double* c, int K, const TH* x, double scale, TU* u, int oz, hipStream_t st) {
+    const DL& D = d[l];
+    if (K == 0) {
+      hipLaunchKernelGGL((k_axpy<C, TH, TU>), dim3(D.blocks), dim3(256), 0, st, D.L.n, B(), lbs, x, (C)(scale * c[0]),
+                         u, oz);
+      LAUNCH_OK();
+      return MG_OK;
+    }
+    const TH* yin = x;
+    double a = c[K];
+    TH* buf[2] = {D.ya, D.yb};
+    int cur = 0;
+    for (int k = K - 1; k >= 1; --k) {
+      MG_TRY(hop<TH, TH, TH>(l, yin, a, x, c[k], buf[cur], 0, 0.0, 0, st));
+      yin = buf[cur];
+      cur ^= 1;
+      a = 1.0;
+    }
+    return hop<TH, TH, TU>(l, yin, a, x, c[0], u, 1, scale, oz, st);
+  }
+
+  // one learnable smoothing step; s receives D^{-1}(f - A u)
+  mg_status smooth(int l, const TU* f, TU* u, int uz, TH* s, hipStream_t st) {
+    const DL& D = d[l];
+    TIMED(MG_KF_RESID, nB(l) * (sizeof(TU) * (uz ? 1 : 2) + sizeof(TH)) + (uz ? 0.0 : bytes_A(l)) +
+                           (double)D.L.n * sizeof(C),
+          hipLaunchKernelGGL((k_resid<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, u, uz, 1, s));
+    return conv_add(l, cB(l), pl.KB, s, eta(l) * theta(l), u, uz, st);
+  }
+
+  // rc = R_l Phi_R(f - A u)
+  mg_status restrict_(int l, const TU* f, const TU* u, int uz, TU* rc, hipStream_t st) {
+    const DL& D = d[l];
+    const int K = pl.KR;
+    const double* c = cR(l);
+    const unsigned cb = d[l + 1].blocks;
+    if (K == 0) {
+      TIMED(MG_KF_RESTRICT, nB(l) * sizeof(TU) * (uz ? 1 : 2) + (uz ? 0.0 : bytes_A(l)) + bytes_X(D.R) +
+                                nB(l + 1) * sizeof(TU),
+            hipLaunchKernelGGL((k_restrict<C, TU, TU, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 2,
+                               (const TU*)nullptr, (C)0, (const TU*)nullptr, (C)0, f, u, uz, (C)c[0], rc));
+      return MG_OK;
+    }
+    TIMED(MG_KF_RESID, nB(l) * sizeof(TU) * (uz ? 2 : 3) + (uz ? 0.0 : bytes_A(l)),
+          hipLaunchKernelGGL((k_resid<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, u, uz, 0,
+                             D.r));
+    const double rbytes = nB(l) * 2 * sizeof(TU) + (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C) +
+                          bytes_X(D.R) + nB(l + 1) * sizeof(TU);
+    if (K == 1) {
+      TIMED(MG_KF_RESTRICT, rbytes,
+            hipLaunchKernelGGL((k_restrict<C, TU, TU, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 1,
+                               (const TU*)D.r, (C)c[1], (const TU*)D.r, (C)c[0], (const TU*)nullptr,
+                               (const TU*)nullptr, 0, (C)1, rc));
+      return MG_OK;
+    }
+    MG_TRY(hop<TU, TU, TH>(l, D.r, c[K], D.r, c[K - 1], D.ya, 0, 0.0, 0, st));
+    const TH* y = D.ya;
+    TH* bufs[2] = {D.ya, D.yb};
+    int cur = 1;
+    for (int k = K - 2; k >= 1; --k) {
+      MG_TRY(hop<TH, TU, TH>(l, y, 1.0, D.r, c[k], bufs[cur], 0, 0.0, 0, st));
+      y = bufs[cur];
+      cur ^= 1;
+    }
+    TIMED(MG_KF_RESTRICT, rbytes - nB(l) * (sizeof(TU) - sizeof(TH)),
+          hipLaunchKernelGGL((k_restrict<C, TU, TH, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 1, y,
+                             (C)1, (const TU*)D.r, (C)c[0], (const TU*)nullptr, (const TU*)nullptr, 0, (C)1, rc));
+    return MG_OK;
+  }
+
+  // u = (uz ? 0 : u) + Phi_P(P ec);  xbuf receives P ec when K >= 1
+  mg_status prolong(int l, const TU* ec, TU* u, int uz, TH* xbuf, hipStream_t st) {
+    const DL& D = d[l];
+    if (pl.KP == 0) {
+      TIMED(MG_KF_PROLONG, nB(l + 1) * sizeof(TU) + bytes_X(D.P) + nB(l) * sizeof(TU) * (uz ? 1 : 2),
+            hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, u, 1,
+                               (C)cP(l)[0], uz));
+      return MG_OK;
+    }
+    TIMED(MG_KF_PROLONG, nB(l + 1) * sizeof(TU) + bytes_X(D.P) + nB(l) * sizeof(TH),
+          hipLaunchKernelGGL((k_prolong<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, xbuf, 0,
+                             (C)1, 0));
+    return conv_add(l, cP(l), pl.KP, xbuf, 1.0, u, uz, st);
+  }
+
+  mg_status coarse(const TU* f, TU* u, int trans, hipStream_t st) {
+    const int n = pl.lv[pl.J - 1].n;
+    hipLaunchKernelGGL((k_coarse<TU>), dim3(nblocks((long)n * B())), dim3(256), 0, st, n, B(), Ainv, f, u, trans);
+    LAUNCH_OK();
+    return MG_OK;
+  }
+
+  // u = LMG(A_l, f, u) (Alg. 2); uz: u is identically zero on entry
+  mg_status fwd(int l, const TU* f, TU* u, int uz, const Ck* ck, hipStream_t st) {
+    if (l == pl.J - 1) return coarse(f, u, 0, st);
+    DL& D = d[l];
+    for (int j = 0; j < pl.nu_pre; ++j) {
+      MG_TRY(smooth(l, f, u, uz, D.s, st));
+      uz = 0;
+    }
+    TU* fn = ck ? ck->f[l + 1] : d[l + 1].f;
+    TU* un = ck ? ck->u[l + 1] : d[l + 1].u;
+    MG_TRY(restrict_(l, f, u, uz, fn, st));
+    MG_TRY(fwd(l + 1, fn, un, 1, ck, st));
+    MG_TRY(prolong(l, un, u, uz, D.x, st));
+    uz = 0;
+    for (int j = 0; j < pl.nu_post; ++j) MG_TRY(smooth(l, f, u, 0, D.s, st));
+    return MG_OK;
+  }
+
+  template <class TI, class TO>
+  mg_status copy(const TI* in, TO* out, long cnt, hipStream_t st) {
+    hipLaunchKernelGGL((k_copy<TI, TO>), dim3(nblocks(cnt)), dim3(256), 0, st, cnt, in, out);
+    LAUNCH_OK();
+    return MG_OK;
+  }
+
+  mg_status vcycle(const void* fv, void* uv, void* ckv, hipStream_t st) override {
+    const TU* f = static_cast<const TU*>(fv);
+    TU* u = static_cast<TU*>(uv);
+    const long n0B = (long)pl.lv[0].n * B();
+    if (ckv) {
+      Ck ck = ck_ptrs(ckv);
+      MG_TRY(copy(f, ck.f[0], n0B, st));
+      MG_TRY(copy((const TU*)u, ck.u[0], n0B, st));
+      return fwd(0, f, u, 0, &ck, st);
+    }
+    return fwd(0, f, u, 0, nullptr, st);
+  }
+
+  unsigned outer_blocks() const {
+    const long rows_per_block = 256 >> lbs;
+    return (unsigned)std::min<long>(kOuterBlocks, (pl.lv[0].n + rows_per_block - 1) / rows_per_block);
+  }
+
+  template <class TR>
+  mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st) {
+    const unsigned g = outer_blocks();
+    const double nb0 = (double)L64.n * B();
+    const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
+                      (rc ? nb0 * sizeof(TR) : 0.0);
+    TIMED(MG_KF_OUTER, ob,
+          hipLaunchKernelGGL((k_outer_resid<TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u, r64, rc, part));
+    if (nrm) {
+      hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, (int)g, B(), nrm);
+      LAUNCH_OK();
+    }
+    return MG_OK;
+  }
+
+  mg_status residual(const double* f, const double* u, double* r, double* nrm, hipStream_t st) override {
+    return outer_resid<TU>(f, u, r, nullptr, nrm, st);
+  }
+
+  mg_status refine(const double* f, const double* uin, double* uout, void* ckv, hipStream_t st) override {
+    const long n0B = (long)pl.lv[0].n * B();
+    Ck ck{};
+    if (ckv) ck = ck_ptrs(ckv);
+    TU* rc = ckv ? ck.f[0] : r0;
+    MG_TRY(outer_resid<TU>(f, uin, nullptr, rc, nullptr, st));
+    MG_TRY(fwd(0, rc, e0, 1, ckv ? &ck : nullptr, st));
+    if (uout != uin) MG_TRY(copy(uin, uout, n0B, st));
+    hipLaunchKernelGGL((k_update<TU>), dim3(d[0].blocks), dim3(256), 0, st, pl.lv[0].n, B(), lbs, (const TU*)e0, uout,
+                       (const int*)nullptr, 1.0);
+    LAUNCH_OK();
+    return MG_OK;
+  }
+
+  mg_status solve(const double* f, double* u, mg_rhs_info* info, hipStream_t st) override {
+    const int n0 = pl.lv[0].n;
+    // ||f|| per column: residual of u = 0 is f itself
+    hipLaunchKernelGGL((k_fill0<double>), dim3(nblocks((long)n0 * B())), dim3(256), 0, st, (long)n0 * B(), dbuf);
+    LAUNCH_OK();
+    MG_TRY(outer_resid<TU>(f, dbuf, nullptr, (TU*)nullptr, fnorm, st));
+    int m = 0;
+    for (; m < pl.max_outer; ++m) {
+      MG_TRY(outer_resid<TU>(f, u, nullptr, r0, norms, st));
+      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf,
+                         m == 0 ? 1 : 0);
+      LAUNCH_OK();
+      if ((m + 1) % pl.check_every == 0 || m == 0) {
+        HIP_TRY(hipMemcpyAsync(hcount, st_ptr() + 3 * B(), sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hcount[0] == 0) break;
+      }
+      MG_TRY(fwd(0, r0, e0, 1, nullptr, st));
+      hipLaunchKernelGGL((k_update<TU>), dim3(d[0].blocks), dim3(256), 0, st, n0, B(), lbs, (const TU*)e0, u,
+                         (const int*)st_ptr(), 1.0);
+      LAUNCH_OK();
+    }
+    if (m == pl.max_outer) {
+      // account for the last iterate
+      MG_TRY(outer_resid<TU>(f, u, nullptr, (TU*)nullptr, norms, st));
+      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf, 0);
+      LAUNCH_OK();
+    }
+    std::vector<int> hst(3 * B() + 1);
+    std::vector<double> hn(B()), hf(B());
+    HIP_TRY(hipMemcpyAsync(hst.data(), st_ptr(), hst.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hn.data(), norms, B() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf.data(), fnorm, B() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    mg_status ret = MG_OK;
+    for (int b = 0; b < B(); ++b) {
+      // iters counted for columns still active after a check: they were updated
+      // only if a cycle followed; a column active at the end ran every cycle
+      int it = hst[B() + b];
+      if (hst[b]) it = std::min(it, m);
+      const int s = hst[2 * B() + b];
+      if (info) {
+        info[b].iters = it;
+        info[b].status = s;
+        info[b].relres = hf[b] > 0 ? hn[b] / hf[b] : hn[b];
+      }
+      if (s == MG_ERR_DIVERGED) ret = MG_ERR_DIVERGED;
+      else if (s != MG_OK && ret == MG_OK) ret = MG_ERR_NOT_CONVERGED;
+    }
+    if (ret != MG_OK) g_err = ret == MG_ERR_DIVERGED ? "a column diverged" : "a column did not converge";
+    return ret;
+  }
+  int* st_ptr() { return dstat; }
+
+  // ---------------------------------------------------------------- reverse sweep
+  int slot = 0;
+
+  // z_0 = src, z_k = M^T z_{k-1};  acc = sum_k c_k z_k;  dot slots <z_k, sdot>
+  mg_status chainT(int l, const double* c, int K, const TU* src, const void* sdot, bool sdot_is_TH, hipStream_t st) {
+    const DL& D = d[l];
+    TU* zbuf[2] = {D.za, D.zb};
+    const TU* zprev = src;
+    int cur = 0;
+    for (int k = 0; k <= K; ++k) {
+      if (slot >= nslots) return fail(MG_ERR_STATE, "reverse sweep slot overflow");
+      double* pp = dpart + h_off[slot];
+      TU* zout = (k >= 1 && k < K) ? zbuf[cur] : nullptr;
+      const TU* zin = k == 0 ? nullptr : zprev;
+      const TU* zsrc = k == 0 ? src : nullptr;
+      if (sdot_is_TH)
+        hipLaunchKernelGGL((k_hopT<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, zin, zsrc, zout,
+                           (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TH*>(sdot), pp);
+      else
+        hipLaunchKernelGGL((k_hopT<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, zin, zsrc, zout,
+                           (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TU*>(sdot), pp);
+      LAUNCH_OK();
+      ++slot;
+      if (zout) {
+        zprev = zout;
+        cur ^= 1;
+      }
+    }
+    return MG_OK;
+  }
+
+  // reverse of one smoothing step whose Jacobi residual was s: g <- g - A q, gf += q
+  mg_status smoothT(int l, const TH* s, TU* g, TU* gf, int& gfz, hipStream_t st) {
+    const DL& D = d[l];
+    MG_TRY(chainT(l, cB(l), pl.KB, g, s, true, st));
+    hipLaunchKernelGGL((k_scale_acc<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)D.acc,
+                       (C)(eta(l) * theta(l)), 1, D.q, gf, gfz);
+    LAUNCH_OK();
+    gfz = 0;
+    hipLaunchKernelGGL((k_sub_Aq<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)g,
+                       (const TU*)D.q, g);
+    LAUNCH_OK();
+    return MG_OK;
+  }
+
+  // reverse of level l: gout = dL/du_out; writes gfl = dL/df_l, gul = dL/du_in (optional)
+  mg_status bwd_level(int l, const TU* f, const TU* uin, const TU* gout, TU* gfl, TU* gul, const Ck& ck,
+                      hipStream_t st) {
+    const long nB = (long)pl.lv[l].n * B();
+    if (l == pl.J - 1) {
+      MG_TRY(coarse(gout, gfl, 1, st));
+      if (gul) {
+        hipLaunchKernelGGL((k_fill0<TU>), dim3(nblocks(nB)), dim3(256), 0, st, nB, gul);
+        LAUNCH_OK();
+      }
+      return MG_OK;
+    }
+    DL& D = d[l];
+    // forward recomputation of this level from its checkpoint
+    int uz = uin ? 0 : 1;
+    if (uin) MG_TRY(copy(uin, D.ut, nB, st));
+    for (int j = 0; j < pl.nu_pre; ++j) {
+      MG_TRY(smooth(l, f, D.ut, uz, D.S[j], st));
+      uz = 0;
+    }
+    hipLaunchKernelGGL((k_resid<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, (const TU*)D.ut, uz,
+                       0, D.Rv);
+    LAUNCH_OK();
+    const TU* ec = ck.u[l + 1];
+    hipLaunchKernelGGL((k_prolong<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, D.X, 0, (C)1, 0);
+    LAUNCH_OK();
+    MG_TRY(prolong(l, ec, D.ut, uz, D.x, st));
+    for (int j = 0; j < pl.nu_post; ++j) MG_TRY(smooth(l, f, D.ut, 0, D.S[pl.nu_pre + j], st));
+    // reverse
+    MG_TRY(copy(gout, D.g, nB, st));
+    int gfz = 1;
+    for (int j = pl.nu_post - 1; j >= 0; --j) MG_TRY(smoothT(l, D.S[pl.nu_pre + j], D.g, gfl, gfz, st));
+    // correction u += Phi_P(P ec):  dL/d ec = P^T Phi_P^T g
+    MG_TRY(chainT(l, cP(l), pl.KP, D.g, D.X, true, st));
+    DL& Dn = d[l + 1];
+    hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(Dn.blocks), dim3(256), 0, st, D.PT, B(), lbs, (const TU*)D.acc,
+                       Dn.gin, 0, (C)1, 0);
+    LAUNCH_OK();
+    MG_TRY(bwd_level(l + 1, ck.f[l + 1], nullptr, Dn.gin, Dn.gfo, nullptr, ck, st));
+    // restriction rc = R Phi_R(r):  r_bar = Phi_R^T R^T rc_bar
+    hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.RT, B(), lbs, (const TU*)Dn.gfo, D.q,
+                       0, (C)1, 0);
+    LAUNCH_OK();
+    MG_TRY(chainT(l, cR(l), pl.KR, D.q, D.Rv, false, st));
+    hipLaunchKernelGGL((k_scale_acc<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)D.acc, (C)1,
+                       0, D.q, gfl, gfz);
+    LAUNCH_OK();
+    gfz = 0;
+    hipLaunchKernelGGL((k_sub_Aq<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)D.g,
+                       (const TU*)D.q, D.g);
+    LAUNCH_OK();
+    for (int j = pl.nu_pre - 1; j >= 0; --j) MG_TRY(smoothT(l, D.S[j], D.g, gfl, gfz, st));
+    if (gul) MG_TRY(copy((const TU*)D.g, gul, nB, st));
+    return MG_OK;
+  }
+
+  mg_status finish_grads(double* gp, hipStream_t st) {
+    if (slot != nslots) return fail(MG_ERR_STATE, "reverse sweep slot count mismatch");
+    if (!gp) return MG_OK;
+    hipLaunchKernelGGL(k_dots_final, dim3(nslots), dim3(256), 0, st, dpart, doff, dcnt, nslots, dots);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_grad_combine, dim3(1), dim3(1), 0, st, dots, ddesc, nslots, dprm, per(), pl.KB, pl.KR, gp,
+                       (int)pl.params.size());
+    LAUNCH_OK();
+    return MG_OK;
+  }
+
+  mg_status bwd_ok() {
+    if (!bwd()) return fail(MG_ERR_STATE, "context was set up without MG_FLAG_BACKWARD");
+    if (!pl.sym_all) return fail(MG_ERR_UNSUPPORTED, "reverse sweep needs symmetric A_l and graphs");
+    return MG_OK;
+  }
+
+  mg_status vcycle_bwd(const void* ckv, const void* goutv, void* ginv, void* gfv, double* gp, hipStream_t st) override {
+    MG_TRY(bwd_ok());
+    if (!ckv || !goutv) return fail(MG_ERR_INVALID_ARG, "checkpoint and gu_out are required");
+    Ck ck = ck_ptrs(const_cast<void*>(ckv));
+    slot = 0;
+    TU* gf = gfv ? static_cast<TU*>(gfv) : d[0].gfo;
+    MG_TRY(bwd_level(0, ck.f[0], ck.u[0], static_cast<const TU*>(goutv), gf, static_cast<TU*>(ginv), ck, st));
+    return finish_grads(gp, st);
+  }
+
+  mg_status refine_bwd(const void* ckv, const double* gout, double* gin, double* gf, double* gp, hipStream_t st) override {
+    MG_TRY(bwd_ok());
+    if (!ckv || !gout) return fail(MG_ERR_INVALID_ARG, "checkpoint and gu_out are required");
+    Ck ck = ck_ptrs(const_cast<void*>(ckv));
+    const long n0B = (long)pl.lv[0].n * B();
+    slot = 0;
+    MG_TRY(copy(gout, d[0].gin, n0B, st));
+    MG_TRY(bwd_level(0, ck.f[0], nullptr, d[0].gin, d[0].gfo, nullptr, ck, st));
+    MG_TRY(copy((const TU*)d[0].gfo, dbuf, n0B, st));
+    if (gf) MG_TRY(copy((const double*)dbuf, gf, n0B, st));
+    if (gin) {
+      hipLaunchKernelGGL((k_sub_Aq<double, double>), dim3(d[0].blocks), dim3(256), 0, st, L64, B(), lbs, gout,
+                         (const double*)dbuf, gin);
+      LAUNCH_OK();
+    }
+    return finish_grads(gp, st);
+  }
+};
+
+}  // namespace
+
+struct mg_ctx {
+  std::unique_ptr<EngineBase> e;
+};
+
+static EngineBase* make_engine(int prec) {
+  switch (prec) {
+    case MG_FP64: return new Engine<double, double, double>();
+    case MG_FP32: return new Engine<float, float, float>();
+    default: return new Engine<float, float, bf16_t>();
+  }
+}
+
+extern "C" {
+
+int64_t mg_num_params(int32_t nlevels, int32_t KB, int32_t KR, int32_t KP) {
+  if (nlevels < 2 || KB < 0 || KR < 0 || KP < 0) return -1;
+  return num_params(nlevels, KB, KR, KP);
+}
+
+mg_status mg_workspace_bytes(const mg_hierarchy* h, const mg_params* p, const mg_options* o, size_t* ws, size_t* ck) {
+  g_err.clear();
+  std::unique_ptr<EngineBase> e(make_engine(o ? o->precision : 0));
+  MG_TRY(build_plan(h, p, o, e->pl, false));
+  if (ws) *ws = e->ws_bytes();
+  if (ck) *ck = e->ck_bytes();
+  return MG_OK;
+}
+
+mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* o, void* ws, size_t ws_bytes,
+                   void* stream, mg_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(MG_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  std::unique_ptr<EngineBase> e(make_engine(o ? o->precision : 0));
+  MG_TRY(build_plan(h, p, o, e->pl, true));
+  const size_t need = e->ws_bytes();
+  if (ws && ws_bytes < need)
+    return fail(MG_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
+  MG_TRY(e->setup(ws, static_cast<hipStream_t>(stream)));
+  mg_ctx* c = new mg_ctx;
+  c->e = std::move(e);
+  *out = c;
+  return MG_OK;
+}
+
+mg_status mg_set_params(mg_ctx* c, const double* v, void* stream) {
+  g_err.clear();
+  if (!c || !v) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->set_params(v, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_vcycle(mg_ctx* c, const void* f, void* u, void* ckpt, void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->vcycle(f, u, ckpt, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_vcycle_backward(mg_ctx* c, const void* ckpt, const void* gu_out, void* gu_in, void* gf, double* gp,
+                             void* stream) {
+  g_err.clear();
+  if (!c) return fail(MG_ERR_INVALID_ARG, "null context");
+  return c->e->vcycle_bwd(ckpt, gu_out, gu_in, gf, gp, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_residual(mg_ctx* c, const double* f, const double* u, double* r, double* norms, void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->residual(f, u, r, norms, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_refine_step(mg_ctx* c, const double* f, const double* uin, double* uout, void* ckpt, void* stream) {
+  g_err.clear();
+  if (!c || !f || !uin || !uout) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->refine(f, uin, uout, ckpt, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_refine_step_backward(mg_ctx* c, const void* ckpt, const double* gout, double* gin, double* gf, double* gp,
+                                  void* stream) {
+  g_err.clear();
+  if (!c) return fail(MG_ERR_INVALID_ARG, "null context");
+  return c->e->refine_bwd(ckpt, gout, gin, gf, gp, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_solve(mg_ctx* c, const double* f, double* u, mg_rhs_info* info, void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->solve(f, u, info, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
+  g_err.clear();
+  if (!c || !n) return fail(MG_ERR_INVALID_ARG, "null argument");
+  for (size_t l = 0; l < c->e->sizes.size(); ++l) {
+    n[l] = c->e->sizes[l];
+    if (wA) wA[l] = c->e->widths[l];
+  }
+  return MG_OK;
+}
+
+mg_status mg_timing_start(mg_ctx* c, int32_t fam) {
+  g_err.clear();
+  if (!c || fam < MG_KF_NONE || fam > MG_KF_OUTER) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
+  return c->e->timing_start(fam);
+}
+
+mg_status mg_timing_read(mg_ctx* c, int64_t* n, double* ms, double* bytes) {
+  g_err.clear();
+  if (!c) return fail(MG_ERR_INVALID_ARG, "null context");
+  return c->e->timing_read(n, ms, bytes);
+}
+
+void mg_destroy(mg_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  delete c;
+}
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""GPU solver (refinement loop) against the oracle: iteration counts on the FP64
+path, final relative residual <= 1e-8 recomputed by the oracle in FP64 on the
+mixed paths, divergence and non-convergence reporting, column invariance."""
+import numpy as np
+import pytest
+
+from mginputs import configs as C, hierarchy as H
+from oracle import lmg as O
+from tests.gpu_util import ctx_for, oracle_levels, oracle_params, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(w, precision, B=None, params=None, **kw):
+    import torch
+    B = B or w.B
+    flat = w.params if params is None else params
+    ctx = ctx_for(w.hier, flat, (w.KB, w.KR, w.KP), B, precision, **kw)
+    f = to_dev(w.f[:, :B], torch.float64)
+    u = torch.zeros_like(f)
+    info = ctx.solve(f, u)
+    return info, to_np(u)
+
+
+def test_poisson33_fp64_iterations_match_oracle():
+    w = C.poisson_unit()
+    info, u = _solve(w, "fp64")
+    ref = O.solve(oracle_levels(w.hier), oracle_params(w.params, w.hier.nlevels, 2), w.f, rtol=1e-8)
+    assert info.code == 0
+    assert info.iters[0] == ref.iters[0]
+    assert rel(u, ref.u) <= 1e-10
+    relres = np.linalg.norm(w.f - w.hier.A[0] @ u) / np.linalg.norm(w.f)
+    assert relres <= 1e-8 and abs(relres - info.relres[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mixed_precision_reaches_1e8(precision):
+    w = C.block_diffusion(2, 129, -2, 2, B=8, K=3)
+    info, u = _solve(w, precision, max_outer=4000)
+    relres = np.linalg.norm(w.f - w.hier.A[0] @ u, axis=0) / np.linalg.norm(w.f, axis=0)
+    print(precision, info.iters, relres, flush=True)
+    assert info.code == 0 and np.all(info.status == 0)
+    assert np.all(relres <= 1e-8)
+    ref = O.solve(oracle_levels(w.hier), oracle_params(w.params, w.hier.nlevels, 3), w.f[:, :2], rtol=1e-12)
+    err = np.linalg.norm(u[:, :2] - ref.u, axis=0) / np.linalg.norm(ref.u, axis=0)
+    print("forward error vs FP64 oracle solution", err, flush=True)
+
+
+def test_mixed_lshape_reaches_1e8():
+    w = C.lshape_aniso(refinements=2, target_nodes=300)
+    info, u = _solve(w, "fp32", max_outer=4000)
+    relres = np.linalg.norm(w.f - w.hier.A[0] @ u) / np.linalg.norm(w.f)
+    print("lshape", info.iters, relres, flush=True)
+    assert info.code == 0 and relres <= 1e-8
+
+
+def test_solve_columns_invariant_alone_and_in_batch():
+    w = C.block_diffusion(2, 65, -2, 2, B=6, K=2)
+    info_all, u_all = _solve(w, "fp32", B=6)
+    import torch
+    for b in (0, 3, 5):
+        ctx = ctx_for(w.hier, w.params, 2, 1, "fp32")
+        f = to_dev(w.f[:, b:b + 1], torch.float64)
+        u = torch.zeros_like(f)
+        info = ctx.solve(f, u)
+        assert info.iters[0] == info_all.iters[b]
+        assert np.array_equal(to_np(u)[:, 0], u_all[:, b])
+
+
+def test_divergence_and_cap_are_reported():
+    w = C.block_diffusion(2, 65, -1, 1, B=2, K=1)
+    J = w.hier.nlevels
+    bad = C.identity_params(J, 1, 1, 1).reshape(J - 1, -1)
+    bad[:, 1] = 10.0           # eta = 10 makes the smoother unstable
+    info, _ = _solve(w, "fp64", params=bad.ravel(), max_outer=500)
+    assert info.code == 6 and np.all(info.status == 6)
+    info, _ = _solve(w, "fp64", max_outer=1)
+    assert info.code == 5 and np.all(info.iters == 1)
+
+
+def test_zero_rhs_converges_immediately():
+    import torch
+    w = C.poisson_unit()
+    ctx = ctx_for(w.hier, w.params, 2, 2)
+    f = torch.zeros((w.hier.sizes[0], 2), dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(f)
+    info = ctx.solve(f, u)
+    assert info.code == 0 and np.all(info.iters == 0)
