@@ -188,12 +188,13 @@ enum {
     MG_KF_OUTER = 5      /* FP64 outer residual with column norms */
 };
 
-/* Start timing every launch of one kernel family on every level: a HIP event
- * pair is recorded around each such launch on its stream, and the
- * algorithmic bytes of the launch (each operand streamed once: vectors read
- * and written, ELL indices and values, per-row scalars) are added up.
+/* Start timing every launch of one kernel family on one level (level -1:
+ * every level; the FP64 outer residual counts as level 0): a HIP event pair
+ * is recorded around each such launch on its stream, and the algorithmic
+ * bytes of the launch (each operand streamed once: vectors read and
+ * written, ELL indices and values, per-row scalars) are added up.
  * kernel_family MG_KF_NONE stops timing.  Clears earlier records. */
-mg_status mg_timing_start(mg_ctx* ctx, int32_t kernel_family);
+mg_status mg_timing_start(mg_ctx* ctx, int32_t kernel_family, int32_t level);
 
 /* Number of timed launches, their summed duration (milliseconds, from the
  * event pairs) and their summed algorithmic bytes.  Synchronises on the

@@ -50,7 +50,8 @@ def clean_csr(A: sp.spmatrix) -> sp.csr_matrix:
 
 
 def drop_roundoff(A: sp.csr_matrix, tol: float = DROP_TOL) -> sp.csr_matrix:
-    """Symmetrise and remove off-diagonal round-off residue."""
+    """Symmetrise (assembly and Galerkin products are symmetric up to
+    round-off) and remove off-diagonal round-off residue."""
     A = 0.5 * (A + A.T)
     A = sp.coo_matrix(A)
     d = np.abs(A.diagonal())
@@ -106,7 +107,7 @@ def square_hierarchy(side: int, blocks: np.ndarray | None = None, nlevels: int |
     def assemble(s):
         pts, tris, interior = fem.square_mesh(s)
         coef = 1.0 if blocks is None else triangle_coef_from_blocks(pts, tris, blocks)
-        return clean_csr(fem.assemble_p1(pts, tris, coef, interior))
+        return drop_roundoff(fem.assemble_p1(pts, tris, coef, interior))
 
     A = [assemble(side)]
     P, R = [], []
@@ -194,7 +195,7 @@ def lshape_hierarchy(rng: np.random.Generator, target_nodes: int = 800, refineme
     meshes = meshes[::-1]           # finest first
     parents = parents[::-1]
     maps = [interior_map(b) for (_, _, b) in meshes]
-    A0 = clean_csr(fem.assemble_p1(meshes[0][0], meshes[0][1], Kt, maps[0]))
+    A0 = drop_roundoff(fem.assemble_p1(meshes[0][0], meshes[0][1], Kt, maps[0]))
     A, P, R = [A0], [], []
     for l in range(refinements):
         Pl = clean_csr(fem.nested_prolongation(parents[l], maps[l], maps[l + 1]))
@@ -204,7 +205,7 @@ def lshape_hierarchy(rng: np.random.Generator, target_nodes: int = 800, refineme
             A.append(galerkin(A[-1], Pl))
         else:
             pc, tc, _ = meshes[l + 1]
-            A.append(clean_csr(fem.assemble_p1(pc, tc, Kt, maps[l + 1])))
+            A.append(drop_roundoff(fem.assemble_p1(pc, tc, Kt, maps[l + 1])))
     coords = [m[0][mp >= 0] for m, mp in zip(meshes, maps)]
     return Hierarchy(A, P, R, meta={"kind": "lshape", "coords0": coords[0], "coarsening": coarsening})
 

@@ -53,7 +53,13 @@ def make_levels(A_list, P_list, R_list=None, G_list=None, ghost_degree=None) -> 
     levels = []
     for l in range(J):
         A = sp.csr_matrix(A_list[l], dtype=np.float64)
-        G = algebraic_graph(A) if G_list is None or G_list[l] is None else sp.csr_matrix(G_list[l])
+        if G_list is None or G_list[l] is None:
+            G = algebraic_graph(A)
+        else:
+            # a given pattern: its edges join distinct nodes, so the diagonal is not an edge
+            Gc = sp.coo_matrix(G_list[l])
+            off = Gc.row != Gc.col
+            G = sp.csr_matrix((np.ones(int(off.sum())), (Gc.row[off], Gc.col[off])), shape=A.shape)
         G = sp.csr_matrix((np.ones(G.nnz), G.indices, G.indptr), shape=G.shape)
         deg = np.asarray(G.sum(axis=1)).ravel()
         if ghost_degree is not None:

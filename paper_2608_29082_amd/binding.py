@@ -85,7 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.mg_refine_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.mg_solve.argtypes = [vp, vp, vp, C.POINTER(RhsInfo), vp]
     lib.mg_level_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
-    lib.mg_timing_start.argtypes = [vp, C.c_int32]
+    lib.mg_timing_start.argtypes = [vp, C.c_int32, C.c_int32]
     lib.mg_timing_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.mg_destroy.argtypes = [vp]
     lib.mg_destroy.restype = None
@@ -279,9 +279,10 @@ class Context:
         _check(self.lib.mg_level_info(self._h, n, w), "mg_level_info")
         return list(n), list(w)
 
-    def timing_start(self, family: str | None):
-        """Time every launch of one kernel family (see mg_timing_start)."""
-        _check(self.lib.mg_timing_start(self._h, KERNEL_FAMILIES[family] if family else 0), "mg_timing_start")
+    def timing_start(self, family: str | None, level: int = -1):
+        """Time every launch of one kernel family on one level (-1: all levels)."""
+        _check(self.lib.mg_timing_start(self._h, KERNEL_FAMILIES[family] if family else 0, level),
+               "mg_timing_start")
 
     def timing_read(self):
         """(launches, total_ms, total_algorithmic_bytes) of the timed family."""

@@ -43,10 +43,14 @@ __device__ __forceinline__ void put(float* p, float v) { *p = v; }
 __device__ __forceinline__ void put(float* p, double v) { *p = (float)v; }
 __device__ __forceinline__ void put(bf16_t* p, float v) { *p = f2bf(v); }
 
-// Level operator in ELL form.  Off-diagonal slots are slot-major
-// (entry (k, i) at k*n + i); a padding slot has col == i and val == 0.
+// Level operator in ELL form.  Off-diagonal slots are slot-major (entry
+// (k, i) at k*ld + i); a padding slot has col == i and val == 0.  Rows
+// [n, ld) of every slot and of the per-row arrays are padding with a valid
+// column (n - 1) and zero values, so four consecutive rows starting at a
+// multiple of 4 can always be read as one 16-byte vector.
 template <class C> struct Lvl {
   int n;
+  int ld;                   // slot stride of the ELL arrays: n rounded up to a multiple of 4
   int w;                    // off-diagonal ELL width of A
   const int* col;
   const C* val;
@@ -79,67 +83,227 @@ __device__ __forceinline__ int xcd_block() {
   const int lane = (int)(gt_ & ((1 << lbs) - 1));                             \
   if (i >= (NROWS)) return;
 
-// (A u)_i for column b
-template <class C, class TU>
-__device__ __forceinline__ C row_Au(const Lvl<C>& L, const TU* __restrict__ u, int i, int B, int b) {
-  C au = L.diag[i] * ldc<C>(u + (size_t)i * B + b);
-  for (int k = 0; k < L.w; ++k) {
-    const int j = L.col[(size_t)k * L.n + i];
-    au += L.val[(size_t)k * L.n + i] * ldc<C>(u + (size_t)j * B + b);
-  }
-  return au;
+// Values that are the same in every lane of a wavefront: WIDE kernels (64
+// lanes per row, B >= 64) broadcast them from the first lane so the compiler
+// keeps them in scalar registers and loads their operands with scalar loads.
+template <bool W> __device__ __forceinline__ int uni(int v) { return W ? __builtin_amdgcn_readfirstlane(v) : v; }
+template <bool W> __device__ __forceinline__ float uni(float v) {
+  return W ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))) : v;
+}
+template <bool W> __device__ __forceinline__ double uni(double v) {
+  if (!W) return v;
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// (M y)_i = invdeg_i * sum_{j in N(i)} y_j
-template <class C, class TY>
-__device__ __forceinline__ C row_My(const Lvl<C>& L, const TY* __restrict__ y, int i, int B, int b) {
-  C s = C(0);
-  for (int k = 0; k < L.wg; ++k) {
-    const int j = L.gcol[(size_t)k * L.n + i];
-    if (j != i) s += ldc<C>(y + (size_t)j * B + b);
+// Row tiles: a block of 256 work-items covers ROWS * (256 >> lbs) rows.
+//  - WIDE (lbs == 6): wavefront g handles the ROWS consecutive rows
+//    base + g * ROWS + r; rows are wave-uniform.
+//  - otherwise the work-items of row group g handle rows base + r * (256 >> lbs) + g,
+//    so the lane groups of a wavefront cover consecutive rows (coalesced).
+// All index loads of a tile are issued before its value loads, so every
+// wavefront keeps ROWS * 4 independent loads in flight per phase.  Rows past
+// the end are clamped to n - 1 for loads and skipped for stores.
+template <int ROWS, bool WIDE>
+struct Tile {
+  int lane, LB;
+  int row0;                 // WIDE: first of the ROWS consecutive rows (a multiple of ROWS)
+  bool any;                 // WIDE: row0 < n
+  int row[ROWS];
+  bool ok[ROWS];
+  __device__ __forceinline__ Tile(int n, int lbs) {
+    LB = 1 << lbs;
+    lane = threadIdx.x & (LB - 1);
+    const int rpb = 256 >> lbs;
+    const int g = uni<WIDE>((int)(threadIdx.x >> lbs));
+    const long base = (long)xcd_block() * rpb * ROWS;
+    row0 = (int)(base + (long)g * ROWS);
+    any = row0 < n;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const long rr = WIDE ? base + (long)g * ROWS + r : base + (long)r * rpb + g;
+      ok[r] = rr < n;
+      row[r] = ok[r] ? (int)rr : n - 1;
+    }
   }
-  return L.invdeg[i] * s;
+};
+
+// Four consecutive entries p[0..3] (p 16-byte aligned for 4-byte types).
+template <class T> struct V4 { T v[4]; };
+__device__ __forceinline__ V4<int> ld4(const int* p) {
+  const int4 t = *reinterpret_cast<const int4*>(p);
+  return V4<int>{{t.x, t.y, t.z, t.w}};
+}
+__device__ __forceinline__ V4<float> ld4(const float* p) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  return V4<float>{{t.x, t.y, t.z, t.w}};
+}
+__device__ __forceinline__ V4<double> ld4(const double* p) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  return V4<double>{{a.x, a.y, b.x, b.y}};
 }
 
-// (M^T z)_i = sum_{j in N(i)} invdeg_j z_j   (graph pattern is symmetric)
-template <class C, class TY>
-__device__ __forceinline__ C row_MTz(const Lvl<C>& L, const TY* __restrict__ z, int i, int B, int b) {
-  C s = C(0);
-  for (int k = 0; k < L.wg; ++k) {
-    const int j = L.gcol[(size_t)k * L.n + i];
-    if (j != i) s += L.invdeg[j] * ldc<C>(z + (size_t)j * B + b);
+// s[r] += sum_k val(k, row_r) * x[col(k, row_r)] over W slots (W multiple of 4).
+// CONSEC (WIDE, NR == 4): the rows are row0 .. row0 + 3 and each slot's four
+// indices and values are one scalar 16-byte load.
+template <bool WIDE, bool CONSEC, int NR, class C, class TX>
+__device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ col, const C* __restrict__ val,
+                                        const int (&row)[NR], int row0, const TX* __restrict__ x, int B, int b,
+                                        C (&s)[NR]) {
+  for (int k = 0; k < W; k += 4) {
+    int j[NR][4];
+    C v[NR][4];
+    if constexpr (CONSEC && NR == 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const V4<int> jj = ld4(col + (size_t)(k + q) * ld + row0);
+        const V4<C> vv = ld4(val + (size_t)(k + q) * ld + row0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          j[r][q] = uni<WIDE>(jj.v[r]);
+          v[r][q] = uni<WIDE>(vv.v[r]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const size_t o = (size_t)(k + q) * ld + row[r];
+          j[r][q] = uni<WIDE>(col[o]);
+          v[r][q] = uni<WIDE>(val[o]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[r] += v[r][q] * ldc<C>(x + (size_t)j[r][q] * B + b);
   }
-  return s;
+}
+
+// Neighbour sums over the graph (W multiple of 4, padding col == row):
+//   TRANS = false: s[r] += sum_{j in N(row)} y_j            ((M y) = invdeg_row * s)
+//   TRANS = true:  s[r] += sum_{j in N(row)} invdeg_j y_j   ((M^T y) = s, symmetric pattern)
+// The padding test uses the unclamped row (row0 + r under CONSEC).
+template <bool WIDE, bool CONSEC, int NR, bool TRANS, class C, class TY>
+__device__ __forceinline__ void graph_sum(const Lvl<C>& L, const int (&row)[NR], int row0, const TY* __restrict__ y,
+                                          int B, int b, C (&s)[NR]) {
+  for (int k = 0; k < L.wg; k += 4) {
+    int j[NR][4];
+    if constexpr (CONSEC && NR == 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const V4<int> jj = ld4(L.gcol + (size_t)(k + q) * L.ld + row0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) j[r][q] = uni<WIDE>(jj.v[r]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) j[r][q] = uni<WIDE>(L.gcol[(size_t)(k + q) * L.ld + row[r]]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int self = (CONSEC && NR == 4) ? row0 + r : row[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        C v = ldc<C>(y + (size_t)j[r][q] * B + b);
+        if (TRANS) v *= uni<WIDE>(L.invdeg[j[r][q]]);
+        s[r] += (j[r][q] != self) ? v : C(0);
+      }
+    }
+  }
+}
+
+// per-row scalar p[row_r] for the rows of a tile (one 16-byte load under CONSEC)
+template <bool WIDE, bool CONSEC, int NR, class C>
+__device__ __forceinline__ void row_vals(const C* __restrict__ p, const int (&row)[NR], int row0, C (&out)[NR]) {
+  if constexpr (CONSEC && NR == 4) {
+    const V4<C> t = ld4(p + row0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = uni<WIDE>(t.v[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[r] = uni<WIDE>(p[row[r]]);
+  }
 }
 
 // out = [invdiag *] (f - A u); uz: u is identically zero.
-template <class C, class TU, class TO>
+// FINE only tags finest-level launches with their own kernel symbol (for
+// per-level profiles); the code is the same.
+template <int ROWS, bool WIDE, bool FINE, class C, class TU, class TO>
 __global__ __launch_bounds__(256) void k_resid(Lvl<C> L, int B, int lbs, const TU* __restrict__ f,
                                                const TU* __restrict__ u, int uz, int jacobi,
                                                TO* __restrict__ out) {
-  MGL_ROW_LANE(L.n)
-  for (int b = lane; b < B; b += (1 << lbs)) {
-    const size_t o = (size_t)i * B + b;
-    C v = ldc<C>(f + o);
-    if (!uz) v -= row_Au(L, u, i, B, b);
-    if (jacobi) v *= L.invdiag[i];
-    put(out + o, v);
+  constexpr bool CS = WIDE && ROWS == 4;
+  const Tile<ROWS, WIDE> t(L.n, lbs);
+  if (WIDE && !t.any) return;
+  C dinv[ROWS];
+  if (jacobi) row_vals<WIDE, CS>(L.invdiag, t.row, t.row0, dinv);
+  if (uz) {
+    for (int b = t.lane; b < B; b += t.LB) {
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        if (!t.ok[r]) continue;
+        C v = ldc<C>(f + (size_t)t.row[r] * B + b);
+        if (jacobi) v *= dinv[r];
+        put(out + (size_t)t.row[r] * B + b, v);
+      }
+    }
+    return;
+  }
+  C dg[ROWS];
+  row_vals<WIDE, CS>(L.diag, t.row, t.row0, dg);
+  for (int b = t.lane; b < B; b += t.LB) {
+    C fv[ROWS], s[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      fv[r] = ldc<C>(f + (size_t)t.row[r] * B + b);
+      s[r] = dg[r] * ldc<C>(u + (size_t)t.row[r] * B + b);
+    }
+    ell_dot<WIDE, CS>(L.w, L.ld, L.col, L.val, t.row, t.row0, u, B, b, s);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      if (!t.ok[r]) continue;
+      C v = fv[r] - s[r];
+      if (jacobi) v *= dinv[r];
+      put(out + (size_t)t.row[r] * B + b, v);
+    }
   }
 }
 
 // Horner hop v = a * (M yin)_i + c * x_i.
 //   mode 0: out = v (type TO)
 //   mode 1: out = (oz ? 0 : out) + scale * v
-template <class C, class TY, class TX, class TO>
+template <int ROWS, bool WIDE, bool FINE, class C, class TY, class TX, class TO>
 __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY* __restrict__ yin, C a,
-                                             const TX* __restrict__ x, C c, TO* out, int mode, C scale,
+                                             const TX* __restrict__ x, C c, TO* __restrict__ out, int mode, C scale,
                                              int oz) {
-  MGL_ROW_LANE(L.n)
-  for (int b = lane; b < B; b += (1 << lbs)) {
-    const size_t o = (size_t)i * B + b;
-    const C v = a * row_My(L, yin, i, B, b) + c * ldc<C>(x + o);
-    if (mode == 0) put(out + o, v);
-    else put(out + o, (oz ? C(0) : ldc<C>(out + o)) + scale * v);
+  constexpr bool CS = WIDE && ROWS == 4;
+  const Tile<ROWS, WIDE> t(L.n, lbs);
+  if (WIDE && !t.any) return;
+  C idg[ROWS];
+  row_vals<WIDE, CS>(L.invdeg, t.row, t.row0, idg);
+  for (int b = t.lane; b < B; b += t.LB) {
+    C xv[ROWS], ov[ROWS], s[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const size_t o = (size_t)t.row[r] * B + b;
+      xv[r] = ldc<C>(x + o);
+      ov[r] = (mode == 1 && !oz) ? ldc<C>(out + o) : C(0);
+      s[r] = C(0);
+    }
+    graph_sum<WIDE, CS, ROWS, false>(L, t.row, t.row0, yin, B, b, s);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      if (!t.ok[r]) continue;
+      const C v = a * (idg[r] * s[r]) + c * xv[r];
+      put(out + (size_t)t.row[r] * B + b, mode == 0 ? v : ov[r] + scale * v);
+    }
   }
 }
 
@@ -158,49 +322,89 @@ __global__ __launch_bounds__(256) void k_axpy(int n, int B, int lbs, const TX* _
 //   mode 0: v = y
 //   mode 1: v = a (M y)_j + c x_j       (last hop of Phi_R fused)
 //   mode 2: v = f_j - (A u)_j           (residual fused; uz: u == 0)
-template <class C, class TU, class TY, class TX>
+// R's ELL width is a multiple of 4 (padding val == 0); the four fine rows of
+// a slot chunk are processed together.
+template <bool WIDE, class C, class TU, class TY, class TX>
 __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, int lbs, int mode,
                                                   const TY* __restrict__ y, C a, const TX* __restrict__ x,
                                                   C c, const TU* __restrict__ f, const TU* __restrict__ u,
                                                   int uz, C scale, TU* __restrict__ rc) {
-  MGL_ROW_LANE(R.n)
+  const long gt_ = (long)xcd_block() * blockDim.x + threadIdx.x;
+  const int i = uni<WIDE>((int)(gt_ >> lbs));
+  const int lane = (int)(gt_ & ((1 << lbs) - 1));
+  if (i >= R.n) return;
   for (int b = lane; b < B; b += (1 << lbs)) {
     C acc = C(0);
-    for (int k = 0; k < R.w; ++k) {
-      const C wgt = R.val[(size_t)k * R.n + i];
-      if (wgt == C(0)) continue;
-      const int j = R.col[(size_t)k * R.n + i];
-      C v;
-      if (mode == 0) {
-        v = ldc<C>(y + (size_t)j * B + b);
-      } else if (mode == 1) {
-        v = a * row_My(L, y, j, B, b) + c * ldc<C>(x + (size_t)j * B + b);
-      } else {
-        v = ldc<C>(f + (size_t)j * B + b);
-        if (!uz) v -= row_Au(L, u, j, B, b);
+    for (int k = 0; k < R.w; k += 4) {
+      int jr[4];
+      C wr[4], v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        jr[q] = uni<WIDE>(R.col[(size_t)(k + q) * R.n + i]);
+        wr[q] = uni<WIDE>(R.val[(size_t)(k + q) * R.n + i]);
       }
-      acc += wgt * v;
+      if (mode == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = ldc<C>(y + (size_t)jr[q] * B + b);
+      } else if (mode == 1) {
+        C sm[4] = {C(0), C(0), C(0), C(0)}, xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = ldc<C>(x + (size_t)jr[q] * B + b);
+        graph_sum<WIDE, false, 4, false>(L, jr, 0, y, B, b, sm);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = a * (uni<WIDE>(L.invdeg[jr[q]]) * sm[q]) + c * xv[q];
+      } else {
+        C fv[4], sa[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          fv[q] = ldc<C>(f + (size_t)jr[q] * B + b);
+          sa[q] = uz ? C(0) : uni<WIDE>(L.diag[jr[q]]) * ldc<C>(u + (size_t)jr[q] * B + b);
+        }
+        if (!uz) ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, jr, 0, u, B, b, sa);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = fv[q] - sa[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc += (wr[q] != C(0)) ? wr[q] * v[q] : C(0);
     }
     put(rc + (size_t)i * B + b, scale * acc);
   }
 }
 
-// Prolongation (or any ELL transfer applied to a coarse vector):
+// Prolongation (or any ELL transfer applied to a coarse vector); even width:
 //   mode 0: out = scale * (P ec)     mode 1: out = (oz ? 0 : out) + scale * (P ec)
-template <class C, class TU, class TO>
+template <int ROWS, bool WIDE, class C, class TU, class TO>
 __global__ __launch_bounds__(256) void k_prolong(Xfer<C> P, int B, int lbs, const TU* __restrict__ ec,
-                                                 TO* out, int mode, C scale, int oz) {
-  MGL_ROW_LANE(P.n)
-  for (int b = lane; b < B; b += (1 << lbs)) {
-    C acc = C(0);
-    for (int k = 0; k < P.w; ++k) {
-      const C wgt = P.val[(size_t)k * P.n + i];
-      const int j = P.col[(size_t)k * P.n + i];
-      acc += wgt * ldc<C>(ec + (size_t)j * B + b);
+                                                 TO* __restrict__ out, int mode, C scale, int oz) {
+  const Tile<ROWS, WIDE> t(P.n, lbs);
+  for (int b = t.lane; b < B; b += t.LB) {
+    C acc[ROWS], ov[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      acc[r] = C(0);
+      ov[r] = (mode == 1 && !oz) ? ldc<C>(out + (size_t)t.row[r] * B + b) : C(0);
     }
-    const size_t o = (size_t)i * B + b;
-    if (mode == 0) put(out + o, scale * acc);
-    else put(out + o, (oz ? C(0) : ldc<C>(out + o)) + scale * acc);
+    for (int k = 0; k < P.w; k += 2) {
+      int j[ROWS][2];
+      C w[ROWS][2];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const size_t o = (size_t)(k + q) * P.n + t.row[r];
+          j[r][q] = uni<WIDE>(P.col[o]);
+          w[r][q] = uni<WIDE>(P.val[o]);
+        }
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[r] += w[r][q] * ldc<C>(ec + (size_t)j[r][q] * B + b);
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      if (!t.ok[r]) continue;
+      put(out + (size_t)t.row[r] * B + b, mode == 0 ? scale * acc[r] : ov[r] + scale * acc[r]);
+    }
   }
 }
 
@@ -285,44 +489,73 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* W, int* in
 // ------------------------------------------------------------------ FP64 outer residual
 // r = f - A u in FP64; writes r64 (optional) and rc = fl(r) in the cycle type
 // (optional); per-block, per-column partial sums of r^2 to part[block][B].
-// Fixed grid; rows are visited grid-stride in a fixed order (deterministic).
-template <class TR>
+// Fixed grid; rows are visited grid-stride in a fixed order (deterministic),
+// four independent rows per step.  B <= 256.
+template <bool WIDE, class TR>
 __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, const double* __restrict__ f,
                                                      const double* __restrict__ u, double* __restrict__ r64,
                                                      TR* __restrict__ rc, double* __restrict__ part) {
   __shared__ double red[256 * 4];
-  const int LB = 1 << lbs, rows_per_block = 256 >> lbs;
-  const int lane = threadIdx.x & (LB - 1), rg = threadIdx.x >> lbs;
+  const int LB = 1 << lbs, rpb = 256 >> lbs;
+  const int lane = threadIdx.x & (LB - 1), rg = uni<WIDE>((int)(threadIdx.x >> lbs));
+  const long step = (long)gridDim.x * rpb;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = blockIdx.x * rows_per_block + rg; i < L.n; i += gridDim.x * rows_per_block) {
+  for (long i0 = (long)blockIdx.x * rpb + rg; i0 < L.n; i0 += 4 * step) {
+    int row[4];
+    bool ok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long rr = i0 + r * step;
+      ok[r] = rr < L.n;
+      row[r] = ok[r] ? (int)rr : L.n - 1;
+    }
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
-      const size_t o = (size_t)i * B + b;
-      const double v = f[o] - row_Au(L, u, i, B, b);
-      if (r64) r64[o] = v;
-      if (rc) put(rc + o, v);
-      acc[q] += v * v;
+      double fv[4], s[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        fv[r] = f[(size_t)row[r] * B + b];
+        s[r] = uni<WIDE>(L.diag[row[r]]) * u[(size_t)row[r] * B + b];
+      }
+      ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, row, 0, u, B, b, s);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!ok[r]) continue;
+        const size_t o = (size_t)row[r] * B + b;
+        const double v = fv[r] - s[r];
+        if (r64) r64[o] = v;
+        if (rc) put(rc + o, v);
+        acc[q] += v * v;
+      }
     }
   }
   for (int q = 0; q < 4; ++q) red[q * 256 + threadIdx.x] = acc[q];
   __syncthreads();
-  if (rg == 0) {
+  if (threadIdx.x < LB) {
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
       double s = 0.0;
-      for (int g = 0; g < rows_per_block; ++g) s += red[q * 256 + g * LB + lane];
+      for (int g = 0; g < rpb; ++g) s += red[q * 256 + g * LB + lane];
       part[(size_t)blockIdx.x * B + b] = s;
     }
   }
 }
 
-// norms[b] = sqrt(sum over blocks of part[block][b]) (fixed order)
-__global__ void k_norm_final(const double* __restrict__ part, int nblk, int B, double* __restrict__ norms) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// norms[b] = sqrt(sum over blocks of part[block][b]); one block per column,
+// fixed strided order and fixed tree (deterministic).
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nblk, int B,
+                                                    double* __restrict__ norms) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
   double s = 0.0;
-  for (int g = 0; g < nblk; ++g) s += part[(size_t)g * B + b];
-  norms[b] = sqrt(s);
+  for (int g = threadIdx.x; g < nblk; g += 256) s += part[(size_t)g * B + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[b] = sqrt(red[0]);
 }
 
 // Per-column solver bookkeeping after the residual of iterate m.
@@ -396,23 +629,32 @@ __device__ __forceinline__ void block_sum_store(double v, double* part, double* 
 // One power step of a transposed convolution:
 //   zin == nullptr: z = zsrc (k = 0);  else z = M^T zin
 //   acc = (first ? 0 : acc) + c * z;  zout = z (if zout);  part <- sum(z * s)
-// The launch must cover every row (no early return before the block sum).
-template <class C, class TZ, class TS>
+// Every work-item reaches the block sum (no early return).
+template <int ROWS, bool WIDE, class C, class TZ, class TS>
 __global__ __launch_bounds__(256) void k_hopT(Lvl<C> L, int B, int lbs, const TZ* __restrict__ zin,
                                               const TZ* __restrict__ zsrc, TZ* __restrict__ zout, C c,
-                                              TZ* acc, int first, const TS* __restrict__ s,
+                                              TZ* __restrict__ acc, int first, const TS* __restrict__ s,
                                               double* __restrict__ part) {
   __shared__ double red[256];
-  const long gt = (long)xcd_block() * blockDim.x + threadIdx.x;
-  const int i = (int)(gt >> lbs), lane = (int)(gt & ((1 << lbs) - 1));
+  const Tile<ROWS, WIDE> t(L.n, lbs);
   double d = 0.0;
-  if (i < L.n) {
-    for (int b = lane; b < B; b += (1 << lbs)) {
-      const size_t o = (size_t)i * B + b;
-      const C z = zin ? row_MTz(L, zin, i, B, b) : ldc<C>(zsrc + o);
-      if (zout) put(zout + o, z);
-      put(acc + o, (first ? C(0) : ldc<C>(acc + o)) + c * z);
-      d += (double)z * (double)ldc<C>(s + o);
+  for (int b = t.lane; b < B; b += t.LB) {
+    C z[ROWS], av[ROWS], sv[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const size_t o = (size_t)t.row[r] * B + b;
+      z[r] = zin ? C(0) : ldc<C>(zsrc + o);
+      av[r] = first ? C(0) : ldc<C>(acc + o);
+      sv[r] = ldc<C>(s + o);
+    }
+    if (zin) graph_sum<WIDE, false, ROWS, true>(L, t.row, t.row0, zin, B, b, z);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      if (!t.ok[r]) continue;
+      const size_t o = (size_t)t.row[r] * B + b;
+      if (zout) put(zout + o, z[r]);
+      put(acc + o, av[r] + c * z[r]);
+      d += (double)z[r] * (double)sv[r];
     }
   }
   block_sum_store(d, part, red);
@@ -434,13 +676,21 @@ __global__ __launch_bounds__(256) void k_scale_acc(Lvl<C> L, int B, int lbs, con
 }
 
 // g_out = g_in - A q  (A symmetric, so A^T q = A q); g_out may alias g_in.
-template <class C, class TZ>
+template <int ROWS, bool WIDE, class C, class TZ>
 __global__ __launch_bounds__(256) void k_sub_Aq(Lvl<C> L, int B, int lbs, const TZ* gin,
                                                 const TZ* __restrict__ q, TZ* gout) {
-  MGL_ROW_LANE(L.n)
-  for (int b = lane; b < B; b += (1 << lbs)) {
-    const size_t o = (size_t)i * B + b;
-    put(gout + o, ldc<C>(gin + o) - row_Au(L, q, i, B, b));
+  const Tile<ROWS, WIDE> t(L.n, lbs);
+  for (int b = t.lane; b < B; b += t.LB) {
+    C gv[ROWS], s[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      gv[r] = ldc<C>(gin + (size_t)t.row[r] * B + b);
+      s[r] = uni<WIDE>(L.diag[t.row[r]]) * ldc<C>(q + (size_t)t.row[r] * B + b);
+    }
+    ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, t.row, t.row0, q, B, b, s);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+      if (t.ok[r]) put(gout + (size_t)t.row[r] * B + b, gv[r] - s[r]);
   }
 }
 

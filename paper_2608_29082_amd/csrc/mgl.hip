@@ -50,17 +50,51 @@ mg_status fail(mg_status s, const std::string& m) {
 // launch `...` bracketed by the timing events of kernel family `fam`
 #define TIMED(fam, bytes, ...)                   \
   do {                                           \
-    MG_TRY(tmark((fam), false, 0.0, st));        \
+    MG_TRY(tmark((fam), l, false, 0.0, st));     \
     __VA_ARGS__;                                 \
     LAUNCH_OK();                                 \
-    MG_TRY(tmark((fam), true, (bytes), st));     \
+    MG_TRY(tmark((fam), l, true, (bytes), st));  \
   } while (0)
 
-constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 1024;
+#define MGL_UNPAREN(...) __VA_ARGS__
+// launch row-tile kernel KERN<ROWS, TARGS...> over the rows of level record D
+#define ROWS_LAUNCH(D, KERN, TARGS, ...)                                                                        \
+  do {                                                                                                          \
+    if (lbs == 6) {                                                                                             \
+      if ((D).rows4)                                                                                            \
+        hipLaunchKernelGGL((KERN<4, true, MGL_UNPAREN TARGS>), dim3((D).rblocks), dim3(256), 0, st, __VA_ARGS__); \
+      else                                                                                                      \
+        hipLaunchKernelGGL((KERN<1, true, MGL_UNPAREN TARGS>), dim3((D).rblocks), dim3(256), 0, st, __VA_ARGS__); \
+    } else {                                                                                                    \
+      if ((D).rows4)                                                                                            \
+        hipLaunchKernelGGL((KERN<4, false, MGL_UNPAREN TARGS>), dim3((D).rblocks), dim3(256), 0, st, __VA_ARGS__); \
+      else                                                                                                      \
+        hipLaunchKernelGGL((KERN<1, false, MGL_UNPAREN TARGS>), dim3((D).rblocks), dim3(256), 0, st, __VA_ARGS__); \
+    }                                                                                                           \
+  } while (0)
+// as ROWS_LAUNCH for kernels with a finest-level tag (FINE = level 0)
+#define ROWS_LAUNCH_F(D, FINE, KERN, TARGS, ...)                                                      \
+  do {                                                                                                \
+    if (FINE) ROWS_LAUNCH(D, KERN, (true, MGL_UNPAREN TARGS), __VA_ARGS__);                           \
+    else ROWS_LAUNCH(D, KERN, (false, MGL_UNPAREN TARGS), __VA_ARGS__);                               \
+  } while (0)
+// restriction sweep (one coarse row per lane group), wave-uniform rows when B >= 64
+#define RESTRICT_LAUNCH(GRID, TARGS, ...)                                                                        \
+  do {                                                                                                          \
+    if (lbs == 6)                                                                                               \
+      hipLaunchKernelGGL((k_restrict<true, MGL_UNPAREN TARGS>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__);      \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_restrict<false, MGL_UNPAREN TARGS>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__);     \
+  } while (0)
+
+constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 4096;
+
+inline int round_up(int w, int m) { return (w + m - 1) / m * m; }
 
 // ------------------------------------------------------------------ host-side structures
 struct HEll {          // slot-major ELL
   int n = 0, w = 0;
+  int ld = 0;          // slot stride (level operators: n rounded up to 4; transfers: n)
   std::vector<int> col;
   std::vector<double> val;
 };
@@ -117,19 +151,22 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
   int w = 0;
   for (int c : cnt) w = std::max(w, c);
   if (w > kMaxW) return fail(MG_ERR_UNSUPPORTED, "A[" + std::to_string(l) + "]: more than 64 off-diagonal entries in a row");
+  w = round_up(w, 4);   // the sweeps gather four slots at a time
+  const int ld = round_up(n, 4);
   L.off.n = n;
   L.off.w = w;
-  L.off.col.assign((size_t)w * n, 0);
-  L.off.val.assign((size_t)w * n, 0.0);
+  L.off.ld = ld;
+  L.off.col.assign((size_t)w * ld, n - 1);   // rows [n, ld): padding with a valid column
+  L.off.val.assign((size_t)w * ld, 0.0);
   for (int i = 0; i < n; ++i) {
     int k = 0;
     for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
       if (A->col[p] != i && A->val[p] != 0.0) {
-        L.off.col[(size_t)k * n + i] = A->col[p];
-        L.off.val[(size_t)k * n + i] = A->val[p];
+        L.off.col[(size_t)k * ld + i] = A->col[p];
+        L.off.val[(size_t)k * ld + i] = A->val[p];
         ++k;
       }
-    for (; k < w; ++k) L.off.col[(size_t)k * n + i] = i;
+    for (; k < w; ++k) L.off.col[(size_t)k * ld + i] = i;
   }
   // graph
   std::vector<int> deg(n, 0);
@@ -143,14 +180,16 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
       wg = std::max(wg, c);
     }
     if (wg > kMaxW) return fail(MG_ERR_UNSUPPORTED, "G: more than 64 neighbours");
+    wg = round_up(wg, 4);
     L.graph.n = n;
     L.graph.w = wg;
-    L.graph.col.assign((size_t)wg * n, 0);
+    L.graph.ld = round_up(n, 4);
+    L.graph.col.assign((size_t)wg * L.graph.ld, n - 1);
     for (int i = 0; i < n; ++i) {
       int k = 0;
       for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p)
-        if (G->col[p] != i) L.graph.col[(size_t)(k++) * n + i] = G->col[p];
-      for (; k < wg; ++k) L.graph.col[(size_t)k * n + i] = i;
+        if (G->col[p] != i) L.graph.col[(size_t)(k++) * L.graph.ld + i] = G->col[p];
+      for (; k < wg; ++k) L.graph.col[(size_t)k * L.graph.ld + i] = i;
     }
   } else {
     deg = cnt;
@@ -180,11 +219,12 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
   return MG_OK;
 }
 
-HEll ell_from_csr(const mg_csr* m) {
+HEll ell_from_csr(const mg_csr* m, int mult) {
   HEll e;
   e.n = m->nrows;
   int w = 0;
   for (int i = 0; i < m->nrows; ++i) w = std::max(w, m->rowptr[i + 1] - m->rowptr[i]);
+  w = round_up(std::max(w, 1), mult);
   e.w = w;
   e.col.assign((size_t)w * e.n, 0);
   e.val.assign((size_t)w * e.n, 0.0);
@@ -198,13 +238,14 @@ HEll ell_from_csr(const mg_csr* m) {
   return e;
 }
 
-HEll ell_transpose(const mg_csr* m) {
+HEll ell_transpose(const mg_csr* m, int mult) {
   std::vector<int> cnt(m->ncols, 0);
   for (int64_t p = 0; p < m->nnz; ++p) cnt[m->col[p]]++;
   HEll e;
   e.n = m->ncols;
   int w = 0;
   for (int c : cnt) w = std::max(w, c);
+  w = round_up(std::max(w, 1), mult);
   e.w = w;
   e.col.assign((size_t)w * e.n, 0);
   e.val.assign((size_t)w * e.n, 0.0);
@@ -287,13 +328,13 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
       int w = 0;
       for (int i = 0; i < L.n; ++i) w = std::max(w, h->A[l].rowptr[i + 1] - h->A[l].rowptr[i]);
       L.off.n = L.n;
-      L.off.w = w;
+      L.off.w = round_up(w, 4);
       L.graph_is_A = (h->G == nullptr);
       if (h->G) {
         int wg = 0;
         for (int i = 0; i < L.n; ++i) wg = std::max(wg, h->G[l].rowptr[i + 1] - h->G[l].rowptr[i]);
         L.graph.n = L.n;
-        L.graph.w = wg;
+        L.graph.w = round_up(wg, 4);
       }
     }
   }
@@ -301,33 +342,35 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
   pl.R_is_PT = (h->R == nullptr);
   for (int l = 0; l + 1 < J; ++l) {
     if (full) {
-      pl.P[l] = ell_from_csr(&h->P[l]);
-      pl.PT[l] = ell_transpose(&h->P[l]);
+      // P and R^T feed the prolongation sweep (pairs of slots), R and P^T the
+      // restriction sweep (four slots at a time)
+      pl.P[l] = ell_from_csr(&h->P[l], 2);
+      pl.PT[l] = ell_transpose(&h->P[l], 4);
       if (h->R) {
-        pl.R[l] = ell_from_csr(&h->R[l]);
-        pl.RT[l] = ell_transpose(&h->R[l]);
+        pl.R[l] = ell_from_csr(&h->R[l], 4);
+        pl.RT[l] = ell_transpose(&h->R[l], 2);
         // R == P^T exactly?  then the transposes alias
         bool same = pl.R[l].w == pl.PT[l].w && pl.R[l].col == pl.PT[l].col && pl.R[l].val == pl.PT[l].val;
         pl.R_is_PT = pl.R_is_PT && same;
       }
     } else {
-      auto rows_w = [](const mg_csr* m) {
+      auto rows_w = [](const mg_csr* m, int mult) {
         int w = 0;
         for (int i = 0; i < m->nrows; ++i) w = std::max(w, m->rowptr[i + 1] - m->rowptr[i]);
-        return w;
+        return round_up(std::max(w, 1), mult);
       };
-      auto cols_w = [](const mg_csr* m) {
+      auto cols_w = [](const mg_csr* m, int mult) {
         std::vector<int> c(m->ncols, 0);
         for (int64_t q = 0; q < m->nnz; ++q) c[m->col[q]]++;
         int w = 0;
         for (int x : c) w = std::max(w, x);
-        return w;
+        return round_up(std::max(w, 1), mult);
       };
-      pl.P[l].n = h->P[l].nrows; pl.P[l].w = rows_w(&h->P[l]);
-      pl.PT[l].n = h->P[l].ncols; pl.PT[l].w = cols_w(&h->P[l]);
+      pl.P[l].n = h->P[l].nrows; pl.P[l].w = rows_w(&h->P[l], 2);
+      pl.PT[l].n = h->P[l].ncols; pl.PT[l].w = cols_w(&h->P[l], 4);
       if (h->R) {
-        pl.R[l].n = h->R[l].nrows; pl.R[l].w = rows_w(&h->R[l]);
-        pl.RT[l].n = h->R[l].ncols; pl.RT[l].w = cols_w(&h->R[l]);
+        pl.R[l].n = h->R[l].nrows; pl.R[l].w = rows_w(&h->R[l], 4);
+        pl.RT[l].n = h->R[l].ncols; pl.RT[l].w = cols_w(&h->R[l], 2);
       }
     }
   }
@@ -379,21 +422,23 @@ struct EngineBase {
 
   // ---- launch timing (instrumentation)
   int tfam = MG_KF_NONE;
+  int tlevel = -1;               // -1: every level
   std::vector<hipEvent_t> tev;   // start/stop pairs, reused across runs
   size_t tn = 0;                 // pairs recorded
   double tbytes = 0.0;
   virtual ~EngineBase() {
     for (hipEvent_t e : tev) (void)hipEventDestroy(e);
   }
-  mg_status timing_start(int fam) {
+  mg_status timing_start(int fam, int level) {
     tfam = fam;
+    tlevel = level;
     tn = 0;
     tbytes = 0.0;
     return MG_OK;
   }
   // record one event of the pair for launch family `fam`; returns false when not timed
-  mg_status tmark(int fam, bool stop, double bytes, hipStream_t st) {
-    if (fam != tfam || tfam == MG_KF_NONE) return MG_OK;
+  mg_status tmark(int fam, int level, bool stop, double bytes, hipStream_t st) {
+    if (fam != tfam || tfam == MG_KF_NONE || (tlevel >= 0 && level != tlevel)) return MG_OK;
     const size_t k = 2 * tn + (stop ? 1 : 0);
     while (tev.size() <= k) {
       hipEvent_t e;
@@ -436,7 +481,9 @@ struct Engine final : EngineBase {
     TU *Rv = nullptr, *ut = nullptr, *g = nullptr, *za = nullptr, *zb = nullptr, *acc = nullptr, *q = nullptr,
        *gfo = nullptr, *gin = nullptr;
     TH* X = nullptr;
-    unsigned blocks = 0;            // n * LB / 256
+    unsigned blocks = 0;            // one work-item per (row, lane): n * LB / 256
+    int rows4 = 0;                  // row-tile sweeps use 4 rows per work-item
+    unsigned rblocks = 0;           // blocks of the row-tile sweeps
   };
   std::vector<DL> d;
   Lvl<double> L64{};                // level-0 operator in FP64 (outer residual)
@@ -480,7 +527,7 @@ struct Engine final : EngineBase {
     auto add = [&](int kind, int K) {
       for (int k = 0; k <= K; ++k) {
         h_desc.push_back(kind); h_desc.push_back(l); h_desc.push_back(k);
-        h_cnt.push_back((int)d[l].blocks);
+        h_cnt.push_back((int)d[l].rblocks);
         h_off.push_back(h_off.empty() ? 0 : h_off.back() + h_cnt[h_cnt.size() - 2]);
       }
     };
@@ -503,19 +550,27 @@ struct Engine final : EngineBase {
       DL& x = d[l];
       const int n = H.n;
       x.blocks = nblocks((long)n << lbs);
+      {
+        const long rpb = 256 >> lbs;
+        const long b4 = (n + 4 * rpb - 1) / (4 * rpb);
+        x.rows4 = b4 >= 2048 ? 1 : 0;
+        x.rblocks = (unsigned)(x.rows4 ? b4 : (n + rpb - 1) / rpb);
+      }
+      const int ld = round_up(n, 4);
       x.L.n = n;
+      x.L.ld = ld;
       x.L.w = H.off.w;
-      x.L.col = bp.take<int>((size_t)H.off.w * n);
-      x.L.val = bp.take<C>((size_t)H.off.w * n);
-      x.L.diag = bp.take<C>(n);
-      x.L.invdiag = bp.take<C>(n);
-      x.L.invdeg = bp.take<C>(n);
+      x.L.col = bp.take<int>((size_t)H.off.w * ld);
+      x.L.val = bp.take<C>((size_t)H.off.w * ld);
+      x.L.diag = bp.take<C>(ld);
+      x.L.invdiag = bp.take<C>(ld);
+      x.L.invdeg = bp.take<C>(ld);
       if (H.graph_is_A) {
         x.L.wg = H.off.w;
         x.L.gcol = x.L.col;
       } else {
         x.L.wg = H.graph.w;
-        x.L.gcol = bp.take<int>((size_t)H.graph.w * n);
+        x.L.gcol = bp.take<int>((size_t)H.graph.w * ld);
       }
       const size_t nv = (size_t)n * B;
       if (l > 0) { x.f = bp.take<TU>(nv); x.u = bp.take<TU>(nv); }
@@ -543,9 +598,10 @@ struct Engine final : EngineBase {
     if constexpr (std::is_same<C, double>::value) {
       L64 = d[0].L;
     } else {
-      L64.n = d[0].L.n; L64.w = d[0].L.w; L64.col = d[0].L.col; L64.wg = d[0].L.wg; L64.gcol = d[0].L.gcol;
-      L64.val = bp.take<double>((size_t)pl.lv[0].off.w * pl.lv[0].n);
-      L64.diag = bp.take<double>(pl.lv[0].n);
+      L64.n = d[0].L.n; L64.ld = d[0].L.ld; L64.w = d[0].L.w; L64.col = d[0].L.col; L64.wg = d[0].L.wg;
+      L64.gcol = d[0].L.gcol;
+      L64.val = bp.take<double>((size_t)pl.lv[0].off.w * d[0].L.ld);
+      L64.diag = bp.take<double>(d[0].L.ld);
       L64.invdiag = nullptr;
       L64.invdeg = nullptr;
     }
@@ -632,11 +688,15 @@ struct Engine final : EngineBase {
       DL& x = d[l];
       MG_TRY(upi(x.L.col, H.off.col, st));
       MG_TRY(up(const_cast<C*>(x.L.val), H.off.val, st));
-      MG_TRY(up(const_cast<C*>(x.L.diag), H.diag, st));
-      std::vector<double> inv(H.n);
-      for (int i = 0; i < H.n; ++i) inv[i] = 1.0 / H.diag[i];
+      std::vector<double> dg(x.L.ld, 1.0), inv(x.L.ld, 0.0), ideg(x.L.ld, 0.0);
+      for (int i = 0; i < H.n; ++i) {
+        dg[i] = H.diag[i];
+        inv[i] = 1.0 / H.diag[i];
+        ideg[i] = H.invdeg[i];
+      }
+      MG_TRY(up(const_cast<C*>(x.L.diag), dg, st));
       MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
-      MG_TRY(up(const_cast<C*>(x.L.invdeg), H.invdeg, st));
+      MG_TRY(up(const_cast<C*>(x.L.invdeg), ideg, st));
       if (!H.graph_is_A) MG_TRY(upi(x.L.gcol, H.graph.col, st));
     }
     for (int l = 0; l + 1 < J; ++l) {
@@ -654,7 +714,9 @@ struct Engine final : EngineBase {
     }
     if (!std::is_same<C, double>::value) {
       MG_TRY(up(const_cast<double*>(L64.val), pl.lv[0].off.val, st));
-      MG_TRY(up(const_cast<double*>(L64.diag), pl.lv[0].diag, st));
+      std::vector<double> dg(L64.ld, 1.0);
+      for (int i = 0; i < L64.n; ++i) dg[i] = pl.lv[0].diag[i];
+      MG_TRY(up(const_cast<double*>(L64.diag), dg, st));
     }
     // coarsest inverse: W = [A | I], Gauss-Jordan on the device
     const int nJ = pl.lv[J - 1].n;
@@ -707,7 +769,7 @@ struct Engine final : EngineBase {
     const double bytes = nB * (sizeof(TY) + sizeof(TX) + sizeof(TO) * (mode ? 2 : 1)) +
                          (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C);
     TIMED(MG_KF_HOP, bytes,
-          hipLaunchKernelGGL((k_hop<C, TY, TX, TO>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, yin, (C)a, x,
+          ROWS_LAUNCH_F(D, l == 0, k_hop, (C, TY, TX, TO), D.L, B(), lbs, yin, (C)a, x,
                              (C)c, out, mode, (C)scale, oz));
     return MG_OK;
   }
@@ -744,7 +806,7 @@ struct Engine final : EngineBase {
     const DL& D = d[l];
     TIMED(MG_KF_RESID, nB(l) * (sizeof(TU) * (uz ? 1 : 2) + sizeof(TH)) + (uz ? 0.0 : bytes_A(l)) +
                            (double)D.L.n * sizeof(C),
-          hipLaunchKernelGGL((k_resid<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, u, uz, 1, s));
+          ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TH), D.L, B(), lbs, f, u, uz, 1, s));
     return conv_add(l, cB(l), pl.KB, s, eta(l) * theta(l), u, uz, st);
   }
 
@@ -757,18 +819,18 @@ struct Engine final : EngineBase {
     if (K == 0) {
       TIMED(MG_KF_RESTRICT, nB(l) * sizeof(TU) * (uz ? 1 : 2) + (uz ? 0.0 : bytes_A(l)) + bytes_X(D.R) +
                                 nB(l + 1) * sizeof(TU),
-            hipLaunchKernelGGL((k_restrict<C, TU, TU, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 2,
+            RESTRICT_LAUNCH(cb, (C, TU, TU, TU), D.R, D.L, B(), lbs, 2,
                                (const TU*)nullptr, (C)0, (const TU*)nullptr, (C)0, f, u, uz, (C)c[0], rc));
       return MG_OK;
     }
     TIMED(MG_KF_RESID, nB(l) * sizeof(TU) * (uz ? 2 : 3) + (uz ? 0.0 : bytes_A(l)),
-          hipLaunchKernelGGL((k_resid<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, u, uz, 0,
+          ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TU), D.L, B(), lbs, f, u, uz, 0,
                              D.r));
     const double rbytes = nB(l) * 2 * sizeof(TU) + (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C) +
                           bytes_X(D.R) + nB(l + 1) * sizeof(TU);
     if (K == 1) {
       TIMED(MG_KF_RESTRICT, rbytes,
-            hipLaunchKernelGGL((k_restrict<C, TU, TU, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 1,
+            RESTRICT_LAUNCH(cb, (C, TU, TU, TU), D.R, D.L, B(), lbs, 1,
                                (const TU*)D.r, (C)c[1], (const TU*)D.r, (C)c[0], (const TU*)nullptr,
                                (const TU*)nullptr, 0, (C)1, rc));
       return MG_OK;
@@ -783,7 +845,7 @@ struct Engine final : EngineBase {
       cur ^= 1;
     }
     TIMED(MG_KF_RESTRICT, rbytes - nB(l) * (sizeof(TU) - sizeof(TH)),
-          hipLaunchKernelGGL((k_restrict<C, TU, TH, TU>), dim3(cb), dim3(256), 0, st, D.R, D.L, B(), lbs, 1, y,
+          RESTRICT_LAUNCH(cb, (C, TU, TH, TU), D.R, D.L, B(), lbs, 1, y,
                              (C)1, (const TU*)D.r, (C)c[0], (const TU*)nullptr, (const TU*)nullptr, 0, (C)1, rc));
     return MG_OK;
   }
@@ -793,12 +855,12 @@ struct Engine final : EngineBase {
     const DL& D = d[l];
     if (pl.KP == 0) {
       TIMED(MG_KF_PROLONG, nB(l + 1) * sizeof(TU) + bytes_X(D.P) + nB(l) * sizeof(TU) * (uz ? 1 : 2),
-            hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, u, 1,
+            ROWS_LAUNCH(D, k_prolong, (C, TU, TU), D.P, B(), lbs, ec, u, 1,
                                (C)cP(l)[0], uz));
       return MG_OK;
     }
     TIMED(MG_KF_PROLONG, nB(l + 1) * sizeof(TU) + bytes_X(D.P) + nB(l) * sizeof(TH),
-          hipLaunchKernelGGL((k_prolong<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, xbuf, 0,
+          ROWS_LAUNCH(D, k_prolong, (C, TU, TH), D.P, B(), lbs, ec, xbuf, 0,
                              (C)1, 0));
     return conv_add(l, cP(l), pl.KP, xbuf, 1.0, u, uz, st);
   }
@@ -855,14 +917,18 @@ struct Engine final : EngineBase {
 
   template <class TR>
   mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st) {
+    const int l = 0;   // timing level of the finest-level outer residual
     const unsigned g = outer_blocks();
     const double nb0 = (double)L64.n * B();
     const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
                       (rc ? nb0 * sizeof(TR) : 0.0);
     TIMED(MG_KF_OUTER, ob,
-          hipLaunchKernelGGL((k_outer_resid<TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u, r64, rc, part));
+          if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u,
+                                           r64, rc, part);
+          else hipLaunchKernelGGL((k_outer_resid<false, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u, r64,
+                                  rc, part));
     if (nrm) {
-      hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, (int)g, B(), nrm);
+      hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), nrm);
       LAUNCH_OK();
     }
     return MG_OK;
@@ -956,10 +1022,10 @@ struct Engine final : EngineBase {
       const TU* zin = k == 0 ? nullptr : zprev;
       const TU* zsrc = k == 0 ? src : nullptr;
       if (sdot_is_TH)
-        hipLaunchKernelGGL((k_hopT<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, zin, zsrc, zout,
+        ROWS_LAUNCH(D, k_hopT, (C, TU, TH), D.L, B(), lbs, zin, zsrc, zout,
                            (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TH*>(sdot), pp);
       else
-        hipLaunchKernelGGL((k_hopT<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, zin, zsrc, zout,
+        ROWS_LAUNCH(D, k_hopT, (C, TU, TU), D.L, B(), lbs, zin, zsrc, zout,
                            (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TU*>(sdot), pp);
       LAUNCH_OK();
       ++slot;
@@ -979,7 +1045,7 @@ struct Engine final : EngineBase {
                        (C)(eta(l) * theta(l)), 1, D.q, gf, gfz);
     LAUNCH_OK();
     gfz = 0;
-    hipLaunchKernelGGL((k_sub_Aq<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)g,
+    ROWS_LAUNCH(D, k_sub_Aq, (C, TU), D.L, B(), lbs, (const TU*)g,
                        (const TU*)D.q, g);
     LAUNCH_OK();
     return MG_OK;
@@ -1005,11 +1071,11 @@ struct Engine final : EngineBase {
       MG_TRY(smooth(l, f, D.ut, uz, D.S[j], st));
       uz = 0;
     }
-    hipLaunchKernelGGL((k_resid<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, f, (const TU*)D.ut, uz,
+    ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TU), D.L, B(), lbs, f, (const TU*)D.ut, uz,
                        0, D.Rv);
     LAUNCH_OK();
     const TU* ec = ck.u[l + 1];
-    hipLaunchKernelGGL((k_prolong<C, TU, TH>), dim3(D.blocks), dim3(256), 0, st, D.P, B(), lbs, ec, D.X, 0, (C)1, 0);
+    ROWS_LAUNCH(D, k_prolong, (C, TU, TH), D.P, B(), lbs, ec, D.X, 0, (C)1, 0);
     LAUNCH_OK();
     MG_TRY(prolong(l, ec, D.ut, uz, D.x, st));
     for (int j = 0; j < pl.nu_post; ++j) MG_TRY(smooth(l, f, D.ut, 0, D.S[pl.nu_pre + j], st));
@@ -1020,12 +1086,12 @@ struct Engine final : EngineBase {
     // correction u += Phi_P(P ec):  dL/d ec = P^T Phi_P^T g
     MG_TRY(chainT(l, cP(l), pl.KP, D.g, D.X, true, st));
     DL& Dn = d[l + 1];
-    hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(Dn.blocks), dim3(256), 0, st, D.PT, B(), lbs, (const TU*)D.acc,
+    ROWS_LAUNCH(Dn, k_prolong, (C, TU, TU), D.PT, B(), lbs, (const TU*)D.acc,
                        Dn.gin, 0, (C)1, 0);
     LAUNCH_OK();
     MG_TRY(bwd_level(l + 1, ck.f[l + 1], nullptr, Dn.gin, Dn.gfo, nullptr, ck, st));
     // restriction rc = R Phi_R(r):  r_bar = Phi_R^T R^T rc_bar
-    hipLaunchKernelGGL((k_prolong<C, TU, TU>), dim3(D.blocks), dim3(256), 0, st, D.RT, B(), lbs, (const TU*)Dn.gfo, D.q,
+    ROWS_LAUNCH(D, k_prolong, (C, TU, TU), D.RT, B(), lbs, (const TU*)Dn.gfo, D.q,
                        0, (C)1, 0);
     LAUNCH_OK();
     MG_TRY(chainT(l, cR(l), pl.KR, D.q, D.Rv, false, st));
@@ -1033,7 +1099,7 @@ struct Engine final : EngineBase {
                        0, D.q, gfl, gfz);
     LAUNCH_OK();
     gfz = 0;
-    hipLaunchKernelGGL((k_sub_Aq<C, TU>), dim3(D.blocks), dim3(256), 0, st, D.L, B(), lbs, (const TU*)D.g,
+    ROWS_LAUNCH(D, k_sub_Aq, (C, TU), D.L, B(), lbs, (const TU*)D.g,
                        (const TU*)D.q, D.g);
     LAUNCH_OK();
     for (int j = pl.nu_pre - 1; j >= 0; --j) MG_TRY(smoothT(l, D.S[j], D.g, gfl, gfz, st));
@@ -1079,7 +1145,7 @@ struct Engine final : EngineBase {
     MG_TRY(copy((const TU*)d[0].gfo, dbuf, n0B, st));
     if (gf) MG_TRY(copy((const double*)dbuf, gf, n0B, st));
     if (gin) {
-      hipLaunchKernelGGL((k_sub_Aq<double, double>), dim3(d[0].blocks), dim3(256), 0, st, L64, B(), lbs, gout,
+      ROWS_LAUNCH(d[0], k_sub_Aq, (double, double), L64, B(), lbs, gout,
                          (const double*)dbuf, gin);
       LAUNCH_OK();
     }
@@ -1188,10 +1254,10 @@ mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
   return MG_OK;
 }
 
-mg_status mg_timing_start(mg_ctx* c, int32_t fam) {
+mg_status mg_timing_start(mg_ctx* c, int32_t fam, int32_t level) {
   g_err.clear();
   if (!c || fam < MG_KF_NONE || fam > MG_KF_OUTER) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
-  return c->e->timing_start(fam);
+  return c->e->timing_start(fam, level);
 }
 
 mg_status mg_timing_read(mg_ctx* c, int64_t* n, double* ms, double* bytes) {

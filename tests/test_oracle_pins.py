@@ -339,3 +339,26 @@ def test_proposition_learnable_smoothing_factor_not_worse():
     Dinv = 1.0 / h.A[0].diagonal()
     Sj = I - best_w * Dinv[:, None] * h.A[0].toarray()
     assert abs(np.abs(np.linalg.eigvals(Sj)).max() - min(jac)) < 1e-13
+
+
+def test_given_graph_ignores_diagonal_and_adds_mesh_edges():
+    """A given pattern defines N(i) without i itself (edges join distinct nodes,
+    Sec. 2.1); the mean of node i is over exactly the listed neighbours."""
+    h = H.square_hierarchy(9)
+    A = h.A[0]
+    n = A.shape[0]
+    G = (A != 0).astype(float).tolil()
+    G[0, n - 1] = 1.0
+    G[n - 1, 0] = 1.0
+    lv = O.make_levels(h.A, h.P, h.R, [sp.csr_matrix(G)] + [None] * (h.nlevels - 1))[0]
+    x = np.arange(n, dtype=float)[:, None]
+    nb0 = [j for j in range(n) if j != 0 and (A[0, j] != 0 or j == n - 1)]
+    assert abs(O.neighbour_mean(lv, x)[0, 0] - np.mean(x[nb0, 0])) < 1e-15 * n
+    assert lv.G.diagonal().sum() == 0
+
+
+def test_generated_operators_exactly_symmetric():
+    for h in (H.square_hierarchy(33, H.block_field(C.rng(9, 1, 9), 16, -3, 3)),
+              H.lshape_hierarchy(C.rng(4, 4, 1), target_nodes=150, refinements=2)):
+        for a in h.A:
+            assert (a != a.T).nnz == 0
