@@ -94,7 +94,10 @@ typedef struct {
     const double* values;
 } mg_params;
 
-enum { MG_FLAG_BACKWARD = 1 };   /* reserve buffers for mg_*_backward */
+enum {
+    MG_FLAG_BACKWARD = 1,   /* reserve buffers for mg_*_backward */
+    MG_FLAG_NO_TAIL = 2     /* never run the coarse levels as one LDS-resident kernel */
+};
 
 typedef struct {
     int32_t precision;       /* mg_precision */

@@ -20,6 +20,7 @@ STATUS = {0: "MG_OK", 1: "MG_ERR_INVALID_ARG", 2: "MG_ERR_SHAPE", 3: "MG_ERR_OOM
           5: "MG_ERR_NOT_CONVERGED", 6: "MG_ERR_DIVERGED", 7: "MG_ERR_STATE", 8: "MG_ERR_UNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 FLAG_BACKWARD = 1
+FLAG_NO_TAIL = 2
 
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
             "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
@@ -157,7 +158,7 @@ class Context:
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
-                 backward=False, device=None, stream=None, workspace=True):
+                 backward=False, device=None, stream=None, workspace=True, tail=True):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -176,7 +177,7 @@ class Context:
             raise ValueError(f"expected {self.nparams} parameters, got {self._params.size}")
         self._p = _Params(KB, KR, KP, nu_pre, nu_post, self._params.ctypes.data_as(C.POINTER(C.c_double)))
         self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
-                           FLAG_BACKWARD if backward else 0)
+                           (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL))
         ws, ck = C.c_size_t(), C.c_size_t()
         _check(self.lib.mg_workspace_bytes(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
                                            C.byref(ws), C.byref(ck)), "mg_workspace_bytes")

@@ -489,25 +489,28 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* W, int* in
 // ------------------------------------------------------------------ FP64 outer residual
 // r = f - A u in FP64; writes r64 (optional) and rc = fl(r) in the cycle type
 // (optional); per-block, per-column partial sums of r^2 to part[block][B].
-// Fixed grid; rows are visited grid-stride in a fixed order (deterministic),
-// four independent rows per step.  B <= 256.
+// Block b (XCD-remapped) owns the contiguous rows [b*chunk, (b+1)*chunk) and
+// walks them four rows per work-item at a time, so neighbour rows are reused
+// from L2; the summation order is fixed (deterministic).  B <= 256.
 template <bool WIDE, class TR>
-__global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, const double* __restrict__ f,
-                                                     const double* __restrict__ u, double* __restrict__ r64,
-                                                     TR* __restrict__ rc, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, int chunk,
+                                                     const double* __restrict__ f, const double* __restrict__ u,
+                                                     double* __restrict__ r64, TR* __restrict__ rc,
+                                                     double* __restrict__ part) {
   __shared__ double red[256 * 4];
   const int LB = 1 << lbs, rpb = 256 >> lbs;
   const int lane = threadIdx.x & (LB - 1), rg = uni<WIDE>((int)(threadIdx.x >> lbs));
-  const long step = (long)gridDim.x * rpb;
+  const int blk = xcd_block();
+  const long lo = (long)blk * chunk, hi = lo + chunk < L.n ? lo + chunk : L.n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long i0 = (long)blockIdx.x * rpb + rg; i0 < L.n; i0 += 4 * step) {
+  for (long i0 = lo + (long)rg * 4; i0 < hi; i0 += 4L * rpb) {
     int row[4];
     bool ok[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const long rr = i0 + r * step;
-      ok[r] = rr < L.n;
-      row[r] = ok[r] ? (int)rr : L.n - 1;
+      const long rr = i0 + r;
+      ok[r] = rr < hi;
+      row[r] = ok[r] ? (int)rr : (int)(hi - 1);
     }
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
     for (int b = lane; b < B; b += LB, ++q) {
       double s = 0.0;
       for (int g = 0; g < rpb; ++g) s += red[q * 256 + g * LB + lane];
-      part[(size_t)blockIdx.x * B + b] = s;
+      part[(size_t)blk * B + b] = s;
     }
   }
 }
@@ -612,6 +615,179 @@ template <class T>
 __global__ __launch_bounds__(256) void k_fill0(long cnt, T* out) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < cnt) out[t] = T(0);
+}
+
+// ------------------------------------------------------------------ coarse tail in LDS
+// Levels lt .. J-1 of one V-cycle for CPB right-hand-side columns per
+// workgroup, with every vector of those levels in LDS (the operators are read
+// from global memory and stay in L2).  Columns are independent, so
+// workgroups never synchronise with each other; inside a workgroup the sweeps
+// are separated by barriers.  LDS layout (units of C, column-minor:
+// element (i, c) of a vector at off + i * CPB + c): per tail level u and f,
+// plus four scratch vectors of the largest tail level.
+constexpr int kTailMaxLevels = 12;
+template <class C>
+struct TailLevel {
+  Lvl<C> L;
+  Xfer<C> P;                // n_l x n_{l+1} (levels below the coarsest)
+  Xfer<C> R;                // n_{l+1} x n_l
+  int off_u, off_f;
+};
+template <class C>
+struct TailArgs {
+  int nl;                   // number of tail levels (the last one is the coarsest)
+  TailLevel<C> lv[kTailMaxLevels];
+  int off_s, off_ya, off_yb, off_t;
+  int KB, KR, KP, nu_pre, nu_post, per;
+  const double* prm;        // flat parameters, row `per` per level, first tail level first
+  const double* Ainv;       // coarsest inverse (row-major)
+  int nJ;
+  int lt;                   // global index of the first tail level
+};
+
+template <int CPB, class C>
+__device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u, int uz, int jacobi, C* out) {
+  for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
+    const int i = e / CPB, c = e - i * CPB;
+    C v = f[e];
+    if (!uz) {
+      C au = L.diag[i] * u[e];
+      for (int k = 0; k < L.w; ++k) au += L.val[(size_t)k * L.ld + i] * u[L.col[(size_t)k * L.ld + i] * CPB + c];
+      v -= au;
+    }
+    if (jacobi) v *= L.invdiag[i];
+    out[e] = v;
+  }
+  __syncthreads();
+}
+
+// out = a (M yin) + c x   (mode 0)   |   out = (oz ? 0 : out) + scale (a (M yin) + c x)   (mode 1)
+template <int CPB, class C>
+__device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const C* x, C cc, C* out, int mode,
+                                       C scale, int oz) {
+  for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
+    const int i = e / CPB, c = e - i * CPB;
+    C sm = C(0);
+    for (int k = 0; k < L.wg; ++k) {
+      const int j = L.gcol[(size_t)k * L.ld + i];
+      if (j != i) sm += yin[j * CPB + c];
+    }
+    const C v = a * (L.invdeg[i] * sm) + cc * x[e];
+    out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
+  }
+  __syncthreads();
+}
+
+// out = X v  for an ELL transfer X (rows X.n)
+template <int CPB, class C>
+__device__ __forceinline__ void tl_xfer(const Xfer<C>& X, const C* v, C* out, int add, C scale, int oz) {
+  for (int e = threadIdx.x; e < X.n * CPB; e += blockDim.x) {
+    const int i = e / CPB, c = e - i * CPB;
+    C acc = C(0);
+    for (int k = 0; k < X.w; ++k) {
+      const C w = X.val[(size_t)k * X.n + i];
+      if (w != C(0)) acc += w * v[X.col[(size_t)k * X.n + i] * CPB + c];
+    }
+    out[e] = add ? (oz ? C(0) : out[e]) + scale * acc : scale * acc;
+  }
+  __syncthreads();
+}
+
+// u = (oz ? 0 : u) + scale * sum_k c_k M^k x  (Horner, as the per-level sweeps)
+template <int CPB, class C>
+__device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, int K, const C* x, double scale, C* u,
+                                            int oz, C* ya, C* yb) {
+  if (K == 0) {
+    const C a0 = (C)(scale * c[0]);
+    for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) u[e] = (oz ? C(0) : u[e]) + a0 * x[e];
+    __syncthreads();
+    return;
+  }
+  const C* yin = x;
+  C a = (C)c[K];
+  C* buf[2] = {ya, yb};
+  int cur = 0;
+  for (int k = K - 1; k >= 1; --k) {
+    tl_hop<CPB>(L, yin, a, x, (C)c[k], buf[cur], 0, C(0), 0);
+    yin = buf[cur];
+    cur ^= 1;
+    a = C(1);
+  }
+  tl_hop<CPB>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz);
+}
+
+template <int CPB, class C, class TU>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* __restrict__ fg,
+                                               TU* __restrict__ eg) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  C* sm = reinterpret_cast<C*>(tail_smem);
+  const int col0 = blockIdx.x * CPB;
+  // load the first tail level's right-hand side for this workgroup's columns
+  {
+    const TailLevel<C>& t0 = T.lv[0];
+    for (int e = threadIdx.x; e < t0.L.n * CPB; e += blockDim.x) {
+      const int i = e / CPB, c = e - i * CPB;
+      sm[t0.off_f + e] = (col0 + c < B) ? (C)fg[(size_t)i * B + col0 + c] : C(0);
+    }
+    __syncthreads();
+  }
+  C *s = sm + T.off_s, *ya = sm + T.off_ya, *yb = sm + T.off_yb, *t = sm + T.off_t;
+  // down: pre-smoothing and restriction
+  for (int q = 0; q + 1 < T.nl; ++q) {
+    const TailLevel<C>& tl = T.lv[q];
+    const double* p = T.prm + (size_t)q * T.per;
+    const double *cB = p + 2, *cR = cB + T.KB + 1;
+    C* u = sm + tl.off_u;
+    const C* f = sm + tl.off_f;
+    int uz = 1;
+    for (int j = 0; j < T.nu_pre; ++j) {
+      tl_resid<CPB>(tl.L, f, u, uz, 1, s);
+      tl_conv_add<CPB>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb);
+      uz = 0;
+    }
+    // r = f - A u (u may still be zero when nu_pre == 0), then y = Phi_R r, f_{l+1} = R y
+    tl_resid<CPB>(tl.L, f, u, uz, 0, t);
+    if (uz) {  // u is logically zero: materialise it for the prolongation's update
+      for (int e = threadIdx.x; e < tl.L.n * CPB; e += blockDim.x) u[e] = C(0);
+      __syncthreads();
+    }
+    tl_conv_add<CPB>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb);
+    tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
+  }
+  // coarsest: u = A^{-1} f
+  {
+    const TailLevel<C>& tl = T.lv[T.nl - 1];
+    const C* f = sm + tl.off_f;
+    C* u = sm + tl.off_u;
+    for (int e = threadIdx.x; e < T.nJ * CPB; e += blockDim.x) {
+      const int i = e / CPB, c = e - i * CPB;
+      double acc = 0.0;
+      for (int j = 0; j < T.nJ; ++j) acc += T.Ainv[(size_t)i * T.nJ + j] * (double)f[j * CPB + c];
+      u[e] = (C)acc;
+    }
+    __syncthreads();
+  }
+  // up: prolongation with Phi_P and post-smoothing
+  for (int q = T.nl - 2; q >= 0; --q) {
+    const TailLevel<C>& tl = T.lv[q];
+    const double* p = T.prm + (size_t)q * T.per;
+    const double *cB = p + 2, *cP = cB + T.KB + 1 + T.KR + 1;
+    C* u = sm + tl.off_u;
+    const C* f = sm + tl.off_f;
+    tl_xfer<CPB>(tl.P, sm + T.lv[q + 1].off_u, t, 0, C(1), 0);
+    tl_conv_add<CPB>(tl.L, cP, T.KP, t, 1.0, u, 0, ya, yb);
+    for (int j = 0; j < T.nu_post; ++j) {
+      tl_resid<CPB>(tl.L, f, u, 0, 1, s);
+      tl_conv_add<CPB>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb);
+    }
+  }
+  {
+    const TailLevel<C>& t0 = T.lv[0];
+    for (int e = threadIdx.x; e < t0.L.n * CPB; e += blockDim.x) {
+      const int i = e / CPB, c = e - i * CPB;
+      if (col0 + c < B) put(eg + (size_t)i * B + col0 + c, sm[t0.off_u + e]);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ adjoint sweeps

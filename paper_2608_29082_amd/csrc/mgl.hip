@@ -501,6 +501,10 @@ struct Engine final : EngineBase {
   std::vector<long> h_off;
   std::vector<int> h_cnt, h_desc;
   int* hcount = nullptr;            // pinned host
+  // coarse tail (levels tail_lt .. J-1 in LDS, one workgroup per column)
+  int tail_lt = -1;                 // shallowest level whose tail fits in LDS
+  std::vector<TailArgs<C>> tails;   // launch arguments for start levels tail_lt .. J-2
+  std::vector<size_t> tail_bytes;
   char* wsbase = nullptr;
   bool owns_ws = false;
   int lbs = 0;
@@ -743,9 +747,73 @@ struct Engine final : EngineBase {
     staging.clear();
     staging.shrink_to_fit();
     if (info != 0) return fail(MG_ERR_SHAPE, "coarsest matrix is singular (zero pivot in column " + std::to_string(info - 1) + ")");
+    MG_TRY(setup_tail());
     sizes.resize(J);
     widths.resize(J);
     for (int l = 0; l < J; ++l) { sizes[l] = pl.lv[l].n; widths[l] = pl.lv[l].off.w; }
+    return MG_OK;
+  }
+
+  // Choose the shallowest start level whose coarse tail fits the workgroup's
+  // LDS, and prepare the launch arguments for every start level below it.
+  mg_status setup_tail() {
+    tail_lt = -1;
+    tails.clear();
+    tail_bytes.clear();
+    if (pl.flags & MG_FLAG_NO_TAIL) return MG_OK;
+    int dev = 0, maxlds = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int J = pl.J;
+    auto r4 = [](long x) { return (x + 3) / 4 * 4; };
+    auto bytes_from = [&](int lt) {
+      long elems = 4 * r4(pl.lv[lt].n);
+      for (int l = lt; l < J; ++l) elems += 2 * r4(pl.lv[l].n);
+      return (size_t)elems * sizeof(C);
+    };
+    for (int lt = 0; lt <= J - 2; ++lt)
+      if (J - lt <= kTailMaxLevels && bytes_from(lt) <= (size_t)maxlds) { tail_lt = lt; break; }
+    if (tail_lt < 0) return MG_OK;
+    if (bytes_from(tail_lt) > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<1, C, TU>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_from(tail_lt)) != hipSuccess) {
+      (void)hipGetLastError();
+      tail_lt = -1;   // large dynamic LDS unavailable: keep the per-level sweeps
+      return MG_OK;
+    }
+    for (int lt = tail_lt; lt <= J - 2; ++lt) {
+      TailArgs<C> t{};
+      t.nl = J - lt;
+      long off = 0;
+      for (int q = 0; q < t.nl; ++q) {
+        const int l = lt + q;
+        t.lv[q].L = d[l].L;
+        if (l < J - 1) { t.lv[q].P = d[l].P; t.lv[q].R = d[l].R; }
+        t.lv[q].off_u = (int)off; off += r4(pl.lv[l].n);
+        t.lv[q].off_f = (int)off; off += r4(pl.lv[l].n);
+      }
+      const long ns = r4(pl.lv[lt].n);
+      t.off_s = (int)off; off += ns;
+      t.off_ya = (int)off; off += ns;
+      t.off_yb = (int)off; off += ns;
+      t.off_t = (int)off; off += ns;
+      t.KB = pl.KB; t.KR = pl.KR; t.KP = pl.KP;
+      t.nu_pre = pl.nu_pre; t.nu_post = pl.nu_post; t.per = per();
+      t.prm = dprm + (size_t)lt * per();
+      t.Ainv = Ainv;
+      t.nJ = pl.lv[J - 1].n;
+      t.lt = lt;
+      tails.push_back(t);
+      tail_bytes.push_back(bytes_from(lt));
+    }
+    return MG_OK;
+  }
+
+  // e = LMG(A_l, f, 0) for levels l .. J-1 in one launch (l >= tail_lt)
+  mg_status run_tail(int l, const TU* f, TU* e, hipStream_t st) {
+    const int q = l - tail_lt;
+    hipLaunchKernelGGL((k_tail<1, C, TU>), dim3(B()), dim3(1024), tail_bytes[q], st, tails[q], B(), f, e);
+    LAUNCH_OK();
     return MG_OK;
   }
 
@@ -874,6 +942,7 @@ struct Engine final : EngineBase {
 
   // u = LMG(A_l, f, u) (Alg. 2); uz: u is identically zero on entry
   mg_status fwd(int l, const TU* f, TU* u, int uz, const Ck* ck, hipStream_t st) {
+    if (tail_lt >= 0 && l >= tail_lt && l < pl.J - 1 && uz && !ck) return run_tail(l, f, u, st);
     if (l == pl.J - 1) return coarse(f, u, 0, st);
     DL& D = d[l];
     for (int j = 0; j < pl.nu_pre; ++j) {
@@ -910,9 +979,17 @@ struct Engine final : EngineBase {
     return fwd(0, f, u, 0, nullptr, st);
   }
 
+  // outer residual: contiguous row chunks (a multiple of 4 rows), at most kOuterBlocks blocks
+  int outer_chunk() const {
+    const long n = pl.lv[0].n;
+    const long rows_per_pass = 4L * (256 >> lbs);
+    long chunk = std::max<long>(rows_per_pass, (n + kOuterBlocks - 1) / kOuterBlocks);
+    chunk = (chunk + 3) / 4 * 4;
+    return (int)chunk;
+  }
   unsigned outer_blocks() const {
-    const long rows_per_block = 256 >> lbs;
-    return (unsigned)std::min<long>(kOuterBlocks, (pl.lv[0].n + rows_per_block - 1) / rows_per_block);
+    const long c = outer_chunk();
+    return (unsigned)((pl.lv[0].n + c - 1) / c);
   }
 
   template <class TR>
@@ -923,10 +1000,10 @@ struct Engine final : EngineBase {
     const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
                       (rc ? nb0 * sizeof(TR) : 0.0);
     TIMED(MG_KF_OUTER, ob,
-          if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u,
-                                           r64, rc, part);
-          else hipLaunchKernelGGL((k_outer_resid<false, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, f, u, r64,
-                                  rc, part));
+          if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs,
+                                           outer_chunk(), f, u, r64, rc, part);
+          else hipLaunchKernelGGL((k_outer_resid<false, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, outer_chunk(),
+                                  f, u, r64, rc, part));
     if (nrm) {
       hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), nrm);
       LAUNCH_OK();

@@ -179,3 +179,29 @@ def test_deterministic_and_column_independent():
     ud = to_dev(u[:, 2:3], torch.float32)
     ctx1.vcycle(to_dev(f[:, 2:3], torch.float32), ud)
     assert np.array_equal(to_np(ud)[:, 0], outs[0][:, 2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lds_coarse_tail_matches_per_level_sweeps(precision):
+    """The coarse levels run as one LDS-resident kernel per column; the result
+    must match the per-level sweeps (and the oracle) to the cycle tolerance."""
+    import torch
+    for case in ("poisson33", "blocks65"):
+        hier = dict(small_cases())[case]
+        J = hier.nlevels
+        flat = C.random_params(J, 3, 3, 3, seed=31)
+        g = C.rng(6, 8, 0)
+        f = g.standard_normal((hier.sizes[0], 3))
+        outs = []
+        for tail in (True, False):
+            ctx = ctx_for(hier, flat, 3, 3, precision, tail=tail)
+            fd = to_dev(f, torch.float64)
+            u = torch.zeros_like(fd)
+            ctx.refine_step(fd, torch.zeros_like(fd), u)     # u = LMG(A, f, 0): tail from the finest level
+            v = to_dev(np.zeros_like(f), ctx.cycle_dtype)
+            ctx.vcycle(to_dev(f, ctx.cycle_dtype), v)           # tail below the finest level
+            outs.append((to_np(u), to_np(v)))
+        want = O.lmg(oracle_levels(hier), oracle_params(flat, J, 3), 0, f, np.zeros_like(f))
+        for a, b in zip(outs[0], outs[1]):
+            assert rel(a, b) <= TOL[precision]
+            assert rel(a, want) <= TOL[precision]
