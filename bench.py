@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="requests per serving run (closed loop, then open loop at 0.5x and 0.8x its rate); 0 skips")
     return ap.parse_args()
 
 
@@ -147,7 +149,8 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel_family": args.roofline_family, "level": args.roofline_level,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "launches": launches, "avg_launch_us": 1e3 * avg_ms,
+            "traffic": counter_traffic(args.roofline_family, args.roofline_level),
+            "launches": launches, "avg_launch_us": 1e3 * avg_ms,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
         },
     }
@@ -167,10 +170,56 @@ def main():
         out["speedup_vs_plain_fp64_gmg"] = value / out["plain_fp64_gmg"]["value"]
         pctx.close()
 
+    if args.serving_requests > 0:
+        out["serving"] = serving(args)
+
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, params, args, float(info.iters.mean()))
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def counter_traffic(kernel_family, level):
+    """Calibrated HBM bytes per dispatch of the timed kernel from the committed
+    PMC measurement, or None if the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_hop_level0_diffusion513_traffic.json")
+    if kernel_family != "hop" or level != 0 or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = os.path.join(ROOT, "paper_2608_29082_amd", "csrc", "kernels.hpp")
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    return rec["bytes_per_dispatch"] if rec.get("kernels_hpp_sha256") == digest else None
+
+
+def serving(args):
+    """Request loop over the serving stream (sides 65..1025, log10 a ~ U(-2, 2)
+    on 16 x 16 blocks, f ~ N(0, 1), per-size trained FP32 parameters, FP64
+    refinement to 1e-8): closed loop to find the saturated rate T, then Poisson
+    arrivals at 0.5 T and 0.8 T.  Latency = done - arrival, setup included."""
+    from paper_2608_29082_amd import params as PR
+    from paper_2608_29082_amd import serve as S
+    theta = {}
+    for side in (65, 129, 257, 513, 1025):
+        f = PR.default_file(f"serving-{side}", 3)
+        if f:
+            th, meta = PR.load(f)
+            theta[side] = (th, meta["J"])
+    runs = {}
+    reqs = S.make_stream(args.serving_requests, 0.0, seed=11)
+    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=4).run(reqs, open_loop=False)
+    runs["closed_loop"] = S.summarize(res, wall)
+    T = runs["closed_loop"]["solves_per_s"]
+    for frac in (0.5, 0.8):
+        reqs = S.make_stream(args.serving_requests, frac * T, seed=12)
+        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=4).run(reqs, open_loop=True)
+        runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T)
+    for r in runs.values():
+        r.pop("by_side", None)
+    print(f"# serving: {json.dumps(runs)}", file=sys.stderr, flush=True)
+    return {"requests_per_run": args.serving_requests, "sides": [65, 129, 257, 513, 1025], **runs}
 
 
 def cpu_baseline(w, params, args, cycles_per_solve):

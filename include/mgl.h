@@ -204,6 +204,26 @@ mg_status mg_timing_start(mg_ctx* ctx, int32_t kernel_family, int32_t level);
  * recorded events. */
 mg_status mg_timing_read(mg_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
 
+/* ---------------------------------------------------------------- setup helpers
+ * Host-side builder of structured hierarchies (per-request setup when
+ * serving; the hierarchy is input data of the V-cycle).
+ * -div(a grad u) = f on the unit square, P1 elements on the uniform mesh of
+ * `side` points per direction (side = 2^k + 1) with every cell split along
+ * its south-west/north-east diagonal, homogeneous Dirichlet boundary
+ * eliminated, a piecewise constant on an nb x nb array of square blocks
+ * (blocks[bj * nb + bi] > 0 covers [bi/nb, (bi+1)/nb) x [bj/nb, (bj+1)/nb)),
+ * P = nested linear interpolation, R = P^T and Galerkin coarse operators
+ * A_{l+1} = P^T A_l P (paper Sec. 2.2) symmetrised with off-diagonal
+ * round-off residue (|a_ij| <= 1e-14 sqrt(|a_ii a_jj|)) removed; coarsening
+ * stops at a coarsest x coarsest interior.  Returns MG_ERR_SHAPE when side
+ * does not coarsen to that size.  The object owns its arrays. */
+typedef struct mg_host_hierarchy mg_host_hierarchy;
+mg_status mg_square_hierarchy(int32_t side, int32_t nb, const double* blocks, int32_t coarsest,
+                              mg_host_hierarchy** out);
+/* Fill `view` with pointers into `h` (valid until mg_host_hierarchy_free). */
+mg_status mg_host_hierarchy_view(const mg_host_hierarchy* h, mg_hierarchy* view);
+void mg_host_hierarchy_free(mg_host_hierarchy* h);
+
 /* Release the context (and the workspace if the library allocated it).
  * Waits for the context's work to finish.  NULL is ignored. */
 void mg_destroy(mg_ctx* ctx);

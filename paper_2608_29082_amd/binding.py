@@ -24,7 +24,8 @@ FLAG_NO_TAIL = 2
 
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
             "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
-            "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_destroy", "mg_last_error"]
+            "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
+            "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error"]
 KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5}
 
 
@@ -88,6 +89,12 @@ def load_library(path: str = LIB_PATH):
     lib.mg_level_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.mg_timing_start.argtypes = [vp, C.c_int32, C.c_int32]
     lib.mg_timing_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.mg_square_hierarchy.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(vp)]
+    lib.mg_square_hierarchy.restype = C.c_int
+    lib.mg_host_hierarchy_view.argtypes = [vp, C.POINTER(_Hier)]
+    lib.mg_host_hierarchy_view.restype = C.c_int
+    lib.mg_host_hierarchy_free.argtypes = [vp]
+    lib.mg_host_hierarchy_free.restype = None
     lib.mg_destroy.argtypes = [vp]
     lib.mg_destroy.restype = None
     lib.mg_last_error.restype = C.c_char_p
@@ -137,6 +144,49 @@ class _HostHierarchy:
         return arr
 
 
+class SquareHierarchy:
+    """Native structured hierarchy (mg_square_hierarchy): host CSR levels owned
+    by the library, usable directly by Context(native=...)."""
+
+    def __init__(self, side: int, blocks, coarsest: int = 3):
+        lib = load_library()
+        b = np.ascontiguousarray(blocks, dtype=np.float64)
+        nb = b.shape[0]
+        h = C.c_void_p()
+        st = lib.mg_square_hierarchy(side, nb, b.ctypes.data_as(C.POINTER(C.c_double)), coarsest, C.byref(h))
+        if st != 0:
+            raise MGError(st, f"mg_square_hierarchy(side={side})")
+        self._h = h
+        self._lib = lib
+        self.view = _Hier()
+        _check(lib.mg_host_hierarchy_view(h, C.byref(self.view)), "mg_host_hierarchy_view")
+        self.nlevels = self.view.nlevels
+        self.sizes = [self.view.A[l].nrows for l in range(self.nlevels)]
+
+    def to_scipy(self):
+        """Copies of the levels as scipy CSR matrices (A list, P list)."""
+        import scipy.sparse as sp
+
+        def conv(m):
+            rp = np.ctypeslib.as_array(m.rowptr, shape=(m.nrows + 1,)).copy()
+            ci = np.ctypeslib.as_array(m.col, shape=(max(m.nnz, 1),))[:m.nnz].copy()
+            va = np.ctypeslib.as_array(m.val, shape=(max(m.nnz, 1),))[:m.nnz].copy()
+            return sp.csr_matrix((va, ci, rp), shape=(m.nrows, m.ncols))
+        J = self.nlevels
+        return [conv(self.view.A[l]) for l in range(J)], [conv(self.view.P[l]) for l in range(J - 1)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mg_host_hierarchy_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
 
@@ -158,20 +208,28 @@ class Context:
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
-                 backward=False, device=None, stream=None, workspace=True, tail=True):
+                 backward=False, device=None, stream=None, workspace=True, tail=True, native=None):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device or "cuda")
-        self.J = len(A)
         self.KB, self.KR, self.KP = KB, KR, KP
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.precision = precision
         self.B = nrhs
-        self.n = [a.shape[0] for a in A]
+        if native is not None:
+            self.J = native.nlevels
+            self.n = list(native.sizes)
+
+            class _View:
+                h = native.view
+            self._hh = _View()
+        else:
+            self.J = len(A)
+            self.n = [a.shape[0] for a in A]
+            self._hh = _HostHierarchy(A, P, R, G)
         self.cycle_dtype = torch.float64 if precision == "fp64" else torch.float32
         self.nparams = num_params(self.J, KB, KR, KP)
-        self._hh = _HostHierarchy(A, P, R, G)
         self._params = np.ascontiguousarray(params, dtype=np.float64)
         if self._params.size != self.nparams:
             raise ValueError(f"expected {self.nparams} parameters, got {self._params.size}")

@@ -34,10 +34,10 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = True) -> str:
-    """Compile csrc/mgl.hip into libmgl.so (always recompiles)."""
-    src = os.path.join(CSRC, "mgl.hip")
+    """Compile csrc/mgl.hip and csrc/hierarchy.cpp into libmgl.so (always recompiles)."""
+    srcs = [os.path.join(CSRC, "mgl.hip"), os.path.join(CSRC, "hierarchy.cpp")]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", src, "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

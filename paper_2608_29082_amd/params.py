@@ -27,24 +27,29 @@ def identity(J: int, KB: int, KR: int, KP: int, omega: float = 2.0 / 3.0) -> np.
     return p.ravel()
 
 
-def map_levels(theta: np.ndarray, J_src: int, J_dst: int, KB: int, KR: int, KP: int) -> np.ndarray:
+def map_levels(theta: np.ndarray, J_src: int, J_dst: int, KB: int, KR: int, KP: int,
+               shift: int = 0) -> np.ndarray:
     """Transfer parameters trained on a J_src-level hierarchy to J_dst levels.
 
-    Levels are aligned at the finest level; extra coarse levels of the target
-    copy the deepest source level (the partial-transfer rule of Sec. 4.2.4,
-    where extra coarse levels copy the deepest compatible source weights); a
-    shallower target keeps the finest J_dst - 1 source levels.
+    Target level l takes source level l + shift, clamped to the source's
+    parameterised levels: shift = 0 aligns the finest levels, and a target
+    level past the deepest source level copies it (the partial-transfer rule
+    of Sec. 4.2.4: extra coarse levels copy the deepest compatible source
+    weights).  With shift = J_src - J_dst on nested grids levels of equal mesh
+    size are matched (the paper matches levels by a mesh-size criterion).
     """
     per = per_level(KB, KR, KP)
     src = np.asarray(theta, dtype=np.float64).reshape(J_src - 1, per)
     out = np.empty((J_dst - 1, per))
     for l in range(J_dst - 1):
-        out[l] = src[min(l, J_src - 2)]
+        out[l] = src[min(max(l + shift, 0), J_src - 2)]
     return out.ravel()
 
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULTS = {("diffusion-513", 3): "k3_diffusion513.npy", ("training-257", 3): "k3_diffusion257_4fields.npy"}
+for _side in (65, 129, 257, 513, 1025):
+    DEFAULTS[(f"serving-{_side}", 3)] = f"k3_serving{_side}.npy"
 
 
 def default_file(workload: str, K: int):

@@ -25,6 +25,10 @@ import numpy as np
 
 WORKLOADS = {"training-257": (3, 257, -2.0, 2.0), "diffusion-513": (2, 513, -3.0, 3.0),
              "diffusion-129": (3, 129, -2.0, 2.0)}
+# serving distribution (log10 a ~ U(-2, 2)); training fields use seeds from
+# 900000 on, disjoint from the request streams' fields
+for _side in (65, 129, 257, 513, 1025):
+    WORKLOADS[f"serving-{_side}"] = (5, _side, -2.0, 2.0)
 
 
 def main(argv=None):
@@ -54,7 +58,8 @@ def main(argv=None):
     K = args.K
     hiers = []
     for k in range(args.fields):
-        blocks = H.block_field(C.rng(wid, 1, args.field_seed + k), 16, lo, hi)
+        fseed = args.field_seed + k + (900000 if args.workload.startswith("serving") else 0)
+        blocks = H.block_field(C.rng(wid, 1, fseed), 16, lo, hi)
         hiers.append(H.square_hierarchy(side, blocks))
     J = hiers[0].nlevels
     n0 = hiers[0].sizes[0]
@@ -96,7 +101,7 @@ def main(argv=None):
     evals = []
     eval_fields = [("train", hiers[0])]
     for k in range(args.eval_fields):
-        blocks = H.block_field(C.rng(wid, 1, 900 + k), 16, lo, hi)
+        blocks = H.block_field(C.rng(wid, 1, 950000 + k), 16, lo, hi)
         eval_fields.append((f"heldout{k}", H.square_hierarchy(side, blocks)))
     f_eval = C.rng(wid, 2, 7000).standard_normal((n0, args.eval_B))
     for name, h in eval_fields:

@@ -1,0 +1,60 @@
+"""Request loop: every request reaches 1e-8 (checked in FP64 on the host), a
+request's result is identical alone and in a mix of concurrent requests of
+other sizes, and admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+from mginputs import hierarchy as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _server(**kw):
+    from paper_2608_29082_amd import params as PR
+    from paper_2608_29082_amd import serve as S
+    theta = {}
+    for side in (65, 129):
+        f = PR.default_file(f"serving-{side}", 3)
+        if f:
+            th, meta = PR.load(f)
+            theta[side] = (th, meta["J"])
+    return S.Server(theta, None, keep_solution=True, **kw)
+
+
+def _relres(req, u):
+    A = H.square_hierarchy(req.side, req.blocks).A[0]
+    return np.linalg.norm(req.f - A @ u) / np.linalg.norm(req.f)
+
+
+def test_mixed_stream_converges_and_is_invariant():
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(10, 0.0, seed=3, sides=(33, 65, 129))
+    srv = _server(slots=3, setup_threads=3)
+    res, errs, wall = srv.run(reqs, open_loop=False)
+    assert not errs and len(res) == len(reqs)
+    byid = {r.rid: r for r in res}
+    for q in reqs:
+        r = byid[q.rid]
+        assert r.status == 0 and _relres(q, r.u) <= 1e-8, (q.side, r.relres)
+    # the same requests alone, one at a time
+    for q in reqs[:4]:
+        alone, e2, _ = _server(slots=1, setup_threads=1).run([q], open_loop=False)
+        assert not e2 and alone[0].iters == byid[q.rid].iters
+        assert np.array_equal(alone[0].u, byid[q.rid].u)
+
+
+def test_admission_respects_budget():
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(6, 0.0, seed=4, sides=(65, 129))
+    probe = _server(slots=2, setup_threads=2)
+    res, errs, _ = probe.run(reqs, open_loop=False)
+    assert not errs
+    biggest = max(r.footprint for r in res)
+    srv = _server(slots=2, setup_threads=2, hbm_budget=biggest)
+    res2, errs2, _ = srv.run(reqs, open_loop=False)
+    assert not errs2 and len(res2) == len(reqs)
+    assert srv.peak_used <= biggest
+    # at every admission, the footprints of the requests holding memory fit the budget
+    for r in res2:
+        held = sum(x.footprint for x in res2 if x.t_admitted <= r.t_admitted < x.t_done)
+        assert held <= biggest
