@@ -209,12 +209,12 @@ def serving(args):
             theta[side] = (th, meta["J"])
     runs = {}
     reqs = S.make_stream(args.serving_requests, 0.0, seed=11)
-    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=4).run(reqs, open_loop=False)
+    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8).run(reqs, open_loop=False)
     runs["closed_loop"] = S.summarize(res, wall)
     T = runs["closed_loop"]["solves_per_s"]
     for frac in (0.5, 0.8):
         reqs = S.make_stream(args.serving_requests, frac * T, seed=12)
-        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=4).run(reqs, open_loop=True)
+        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8).run(reqs, open_loop=True)
         runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T)
     for r in runs.values():
         r.pop("by_side", None)
