@@ -177,6 +177,54 @@ mg_status mg_refine_step_backward(mg_ctx* ctx, const void* ckpt, const double* g
  * MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED. */
 mg_status mg_solve(mg_ctx* ctx, const double* f, double* u, mg_rhs_info* info, void* stream);
 
+/* ---------------------------------------------------------------- Krylov and FMG
+ * The trained cycle also serves as a preconditioner of flexible GMRES, either
+ * as one V-cycle or inside full multigrid (paper Sec. 4.2, preconditioner
+ * experiments, and its FMG paragraph). */
+
+/* Full multigrid (nested iteration) with one learnable cycle per level:
+ * f_0 = f, f_{l+1} = R_l Phi_R,l(f_l) (the cycle's own restriction);
+ * u_{J-1} = A_{J-1}^{-1} f_{J-1}; for l = J-2 .. 0:
+ * u_l = LMG(A_l, f_l, Phi_P,l(P_l u_{l+1})) (the cycle's own prolongation).
+ * f, u: cycle-type device vectors [n_0 x B]; u is overwritten (its input
+ * value is not used).  Uses the context's per-level buffers, like mg_vcycle. */
+mg_status mg_fmg(mg_ctx* ctx, const void* f, void* u, void* stream);
+
+typedef enum {
+    MG_PC_NONE = 0,     /* z = fl_p(v): unpreconditioned (up to rounding to the cycle type) */
+    MG_PC_VCYCLE = 1,   /* z = LMG_p(A_0, fl_p(v), 0): one learnable V-cycle */
+    MG_PC_FMG = 2       /* z = FMG_p(fl_p(v)) */
+} mg_preconditioner;
+
+typedef struct {
+    int32_t restart;    /* m: basis vectors per restart cycle, 1..128 */
+    int32_t max_iter;   /* cap on a column's FGMRES iterations (preconditioner calls), >= 1 */
+    double rtol;        /* stop a column when ||f - A u|| <= rtol ||f|| */
+    int32_t precond;    /* mg_preconditioner */
+} mg_krylov_options;
+
+/* Device bytes of the Krylov workspace for these options: (m+1) FP64 basis
+ * vectors, m preconditioned vectors in the cycle type, one FP64 vector and
+ * O(m^2 B) per-column scalars.  No device work. */
+mg_status mg_fgmres_workspace_bytes(const mg_ctx* ctx, const mg_krylov_options* o, size_t* bytes);
+
+/* Solve A_0 u = f by restarted flexible GMRES with right preconditioning
+ * (Saad 1993) per column, from the given u.  The preconditioner runs in the
+ * context precision; A z, the orthonormal basis (classical Gram-Schmidt
+ * applied twice), the Hessenberg least-squares problem and the iterate are
+ * FP64.  Each restart begins with the true FP64 residual; a column stops at
+ * the first iteration whose least-squares residual estimate meets rtol (or
+ * when its Krylov space becomes invariant) and is finished when its true
+ * residual does.  info[b].iters counts the column's iterations.  f, u: device
+ * double [n_0 x B].  work: caller device memory of mg_fgmres_workspace_bytes,
+ * or NULL: the library then allocates it on the first call and keeps it
+ * (growing it when a larger restart needs more) until mg_destroy.  Blocks the
+ * calling thread (reads the active-column count every iteration).  Returns
+ * MG_OK, MG_ERR_NOT_CONVERGED (a column missed rtol in max_iter iterations)
+ * or MG_ERR_DIVERGED (a column's residual is not finite). */
+mg_status mg_fgmres(mg_ctx* ctx, const double* f, double* u, const mg_krylov_options* o,
+                    void* work, size_t work_bytes, mg_rhs_info* info, void* stream);
+
 /* Per-level sizes: n_l for l < J (out: host int64 [J]) plus ELL widths of
  * A_l (wA: host int32 [J], may be NULL). */
 mg_status mg_level_info(const mg_ctx* ctx, int64_t* n, int32_t* wA);
@@ -188,7 +236,8 @@ enum {
     MG_KF_RESID = 2,     /* residual / Jacobi-scaled residual sweeps */
     MG_KF_RESTRICT = 3,  /* restriction (with fused residual or last hop) */
     MG_KF_PROLONG = 4,   /* prolongation (with fused correction) */
-    MG_KF_OUTER = 5      /* FP64 outer residual with column norms */
+    MG_KF_OUTER = 5,     /* FP64 outer residual with column norms */
+    MG_KF_KRYLOV = 6     /* FGMRES Gram-Schmidt sweeps (dot products, basis updates) */
 };
 
 /* Start timing every launch of one kernel family on one level (level -1:

@@ -25,8 +25,10 @@ FLAG_NO_TAIL = 2
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
             "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
             "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
-            "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error"]
-KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5}
+            "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error",
+            "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres"]
+KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6}
+PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
 
 
 class MGError(RuntimeError):
@@ -55,6 +57,10 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nrhs", C.c_int32), ("max_outer", C.c_int32),
                 ("check_every", C.c_int32), ("rtol", C.c_double), ("diverge_factor", C.c_double),
                 ("flags", C.c_int32)]
+
+
+class _KrylovOptions(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double), ("precond", C.c_int32)]
 
 
 class RhsInfo(C.Structure):
@@ -87,6 +93,9 @@ def load_library(path: str = LIB_PATH):
     lib.mg_refine_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.mg_solve.argtypes = [vp, vp, vp, C.POINTER(RhsInfo), vp]
     lib.mg_level_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.mg_fmg.argtypes = [vp, vp, vp, vp]
+    lib.mg_fgmres_workspace_bytes.argtypes = [vp, C.POINTER(_KrylovOptions), C.POINTER(sz)]
+    lib.mg_fgmres.argtypes = [vp, vp, vp, C.POINTER(_KrylovOptions), vp, sz, C.POINTER(RhsInfo), vp]
     lib.mg_timing_start.argtypes = [vp, C.c_int32, C.c_int32]
     lib.mg_timing_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.mg_square_hierarchy.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(vp)]
@@ -329,6 +338,35 @@ class Context:
         st = self.lib.mg_solve(self._h, _ptr(f), _ptr(u), info, self._s())
         if st not in (0, 5, 6) or (raise_on_failure and st != 0):
             _check(st, "mg_solve")
+        return SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
+                         np.array([x.relres for x in info]), st)
+
+    def fmg(self, f, u):
+        """u = FMG(f): nested iteration with one learnable cycle per level (cycle dtype)."""
+        self._vec(f, self.cycle_dtype, "f")
+        self._vec(u, self.cycle_dtype, "u")
+        _check(self.lib.mg_fmg(self._h, _ptr(f), _ptr(u), self._s()), "mg_fmg")
+        return u
+
+    def fgmres_workspace_bytes(self, restart=30, precond="vcycle"):
+        o = _KrylovOptions(restart, 1, 0.0, PRECONDITIONERS[precond])
+        b = C.c_size_t()
+        _check(self.lib.mg_fgmres_workspace_bytes(self._h, C.byref(o), C.byref(b)), "mg_fgmres_workspace_bytes")
+        return b.value
+
+    def fgmres(self, f, u, restart=30, max_iter=500, rtol=None, precond="vcycle", work=None,
+               raise_on_failure=False) -> SolveInfo:
+        """Flexible GMRES(restart) from u with the cycle (or FMG) as right preconditioner;
+        iters counts FGMRES iterations per column.  work: optional uint8 device tensor
+        of fgmres_workspace_bytes (else the library keeps its own)."""
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u, self.torch.float64, "u")
+        o = _KrylovOptions(restart, max_iter, self._o.rtol if rtol is None else rtol, PRECONDITIONERS[precond])
+        info = (RhsInfo * self.B)()
+        st = self.lib.mg_fgmres(self._h, _ptr(f), _ptr(u), C.byref(o), _ptr(work),
+                                0 if work is None else work.numel(), info, self._s())
+        if st not in (0, 5, 6) or (raise_on_failure and st != 0):
+            _check(st, "mg_fgmres")
         return SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
                          np.array([x.relres for x in info]), st)
 

@@ -4,8 +4,10 @@
 // workspace buffer; the V-cycle (paper Alg. 2), the refinement iteration
 // u^m = u^{m-1} + B(f - A u^{m-1}) (Sec. 1), the solver loop and the reverse
 // sweep used for training (Sec. 3.1) are sequences of the kernels of
-// kernels.hpp enqueued on the caller's stream.  Three precisions share the
-// code: FP64 throughout; FP32 cycles; FP32 cycles with BF16 intermediates.
+// kernels.hpp enqueued on the caller's stream; full multigrid and flexible
+// GMRES with the cycle as preconditioner (Sec. 4.2) add the Krylov kernels of
+// krylov.hpp.  Three precisions share the code: FP64 throughout; FP32 cycles;
+// FP32 cycles with BF16 intermediates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +19,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "krylov.hpp"
 #include "mgl.h"
 
 using namespace mgl;
@@ -412,6 +415,10 @@ struct EngineBase {
   virtual mg_status refine(const double* f, const double* uin, double* uout, void* ck, hipStream_t st) = 0;
   virtual mg_status refine_bwd(const void* ck, const double* gout, double* gin, double* gf, double* gp, hipStream_t st) = 0;
   virtual mg_status solve(const double* f, double* u, mg_rhs_info* info, hipStream_t st) = 0;
+  virtual mg_status fmg_entry(const void* f, void* u, hipStream_t st) = 0;
+  virtual mg_status fgmres(const double* f, double* u, const mg_krylov_options* o, void* work, size_t wbytes,
+                           mg_rhs_info* info, hipStream_t st) = 0;
+  virtual size_t fgmres_bytes(int restart) = 0;
   virtual mg_status set_params(const double* v, hipStream_t st) = 0;
   virtual mg_status setup(void* ws, hipStream_t st) = 0;
   virtual size_t ws_bytes() = 0;
@@ -501,6 +508,8 @@ struct Engine final : EngineBase {
   std::vector<long> h_off;
   std::vector<int> h_cnt, h_desc;
   int* hcount = nullptr;            // pinned host
+  char* kr_own = nullptr;           // Krylov workspace allocated by the library
+  size_t kr_own_bytes = 0;
   // coarse tail (levels tail_lt .. J-1 in LDS, one workgroup per column)
   int tail_lt = -1;                 // shallowest level whose tail fits in LDS
   std::vector<TailArgs<C>> tails;   // launch arguments for start levels tail_lt .. J-2
@@ -513,6 +522,7 @@ struct Engine final : EngineBase {
 
   ~Engine() override {
     if (owns_ws && wsbase) (void)hipFree(wsbase);
+    if (kr_own) (void)hipFree(kr_own);
     if (hcount) (void)hipHostFree(hcount);
   }
 
@@ -1083,6 +1093,216 @@ struct Engine final : EngineBase {
   }
   int* st_ptr() { return dstat; }
 
+  // ---------------------------------------------------------------- full multigrid, FGMRES
+  // u = FMG(f) (Sec. 4.2): right-hand sides carried down with the cycle's
+  // restriction f_{l+1} = R_l Phi_R,l(f_l), exact solve on the coarsest level,
+  // then on each finer level u_l = Phi_P,l(P_l u_{l+1}) followed by one
+  // learnable cycle.  Uses the per-level cycle buffers of levels >= 1.
+  mg_status fmg(const TU* f0, TU* u0, hipStream_t st) {
+    const int J = pl.J;
+    const TU* fl = f0;
+    for (int l = 0; l + 1 < J; ++l) {
+      MG_TRY(restrict_(l, fl, fl, 1, d[l + 1].f, st));
+      fl = d[l + 1].f;
+    }
+    MG_TRY(coarse(d[J - 1].f, d[J - 1].u, 0, st));
+    for (int l = J - 2; l >= 0; --l) {
+      const TU* f = l == 0 ? f0 : d[l].f;
+      TU* u = l == 0 ? u0 : d[l].u;
+      MG_TRY(prolong(l, d[l + 1].u, u, 1, d[l].x, st));
+      MG_TRY(fwd(l, f, u, 0, nullptr, st));
+    }
+    return MG_OK;
+  }
+  mg_status fmg_entry(const void* f, void* u, hipStream_t st) override {
+    return fmg(static_cast<const TU*>(f), static_cast<TU*>(u), st);
+  }
+
+  // Krylov workspace (carved from one buffer)
+  struct Kr {
+    int m = 0, chunk = 0, nblk = 0;
+    long vs = 0, zs = 0;           // element strides between basis vectors
+    double* V = nullptr;           // m + 1 orthonormal vectors, FP64
+    TU* Z = nullptr;               // m preconditioned vectors, cycle type
+    double *w = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr, *nrm2 = nullptr, *y = nullptr,
+           *beta = nullptr;
+    KrState S{};
+  };
+  static constexpr int kKrBlocks = 1024;
+  size_t kr_carve(int m, char* base, Kr& k) {
+    Bump bp;
+    bp.base = base;
+    const int n = pl.lv[0].n, Bn = B();
+    const long nB = (long)n * Bn;
+    const long rpb = 256 >> lbs;
+    k.m = m;
+    k.chunk = (int)std::max<long>(rpb, (n + kKrBlocks - 1) / kKrBlocks);
+    k.nblk = (int)((n + k.chunk - 1) / k.chunk);
+    k.vs = (nB + 31) / 32 * 32;
+    k.zs = (nB + 127) / 128 * 128;
+    k.V = bp.take<double>((size_t)(m + 1) * k.vs);
+    k.Z = bp.take<TU>((size_t)m * k.zs);
+    k.w = bp.take<double>(nB);
+    k.part = bp.take<double>((size_t)k.nblk * (m + 1) * Bn);
+    k.h1 = bp.take<double>((size_t)(m + 1) * Bn);
+    k.h2 = bp.take<double>((size_t)(m + 1) * Bn);
+    k.nrm2 = bp.take<double>(Bn);
+    k.y = bp.take<double>((size_t)m * Bn);
+    k.beta = bp.take<double>(Bn);
+    k.S.m = m;
+    k.S.H = bp.take<double>((size_t)(m + 1) * m * Bn);
+    k.S.cs = bp.take<double>((size_t)m * Bn);
+    k.S.sn = bp.take<double>((size_t)m * Bn);
+    k.S.g = bp.take<double>((size_t)(m + 1) * Bn);
+    k.S.s = bp.take<double>(Bn);
+    k.S.fnorm = bp.take<double>(Bn);
+    k.S.act = bp.take<int>(Bn);
+    k.S.jd = bp.take<int>(Bn);
+    k.S.st = bp.take<int>(3 * (size_t)Bn + 1);
+    return bp.off + 256;
+  }
+  size_t fgmres_bytes(int restart) override {
+    Kr k;
+    return kr_carve(restart, nullptr, k);
+  }
+
+  // dots[i] (+)= <w, V_i>, i < nv, per column
+  mg_status kr_dots(const Kr& k, int nv, double* out, int add, hipStream_t st) {
+    const int l = 0;
+    const int n = pl.lv[0].n;
+    TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 1),
+          hipLaunchKernelGGL(k_kr_dots, dim3(k.nblk), dim3(256), 0, st, n, B(), lbs, k.chunk, nv,
+                             (const double*)k.V, k.vs, (const double*)k.w, k.part));
+    hipLaunchKernelGGL(k_kr_reduce, dim3(nv), dim3(256), 0, st, (const double*)k.part, k.nblk, nv, B(), lbs, out,
+                       add);
+    LAUNCH_OK();
+    return MG_OK;
+  }
+  // w -= sum_i h_i V_i (i < nv); norm2: nrm2 = ||w||^2 per column
+  mg_status kr_orth(const Kr& k, int nv, const double* h, int norm2, hipStream_t st) {
+    const int l = 0;
+    const int n = pl.lv[0].n;
+    TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 2),
+          hipLaunchKernelGGL(k_kr_orth, dim3(k.nblk), dim3(256), 0, st, n, B(), lbs, k.chunk, nv,
+                             (const double*)k.V, k.vs, h, k.w, norm2, k.part));
+    if (norm2) {
+      hipLaunchKernelGGL(k_kr_reduce, dim3(1), dim3(256), 0, st, (const double*)k.part, k.nblk, 1, B(), lbs, k.nrm2,
+                         0);
+      LAUNCH_OK();
+    }
+    return MG_OK;
+  }
+  mg_status kr_count(const Kr& k, int* cnt, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(hcount, k.S.st + 3 * B(), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *cnt = hcount[0];
+    return MG_OK;
+  }
+
+  // Flexible GMRES(m) with right preconditioning (Saad 1993), per column, from
+  // the given x.  The preconditioner z = C(v) runs in the cycle precision on
+  // fl(v); A z, the basis and the iterate are FP64, so the Arnoldi relation
+  // A Z_m = V_{m+1} H_m holds to FP64 rounding whatever C does.
+  mg_status fgmres(const double* f, double* x, const mg_krylov_options* o, void* work, size_t wbytes,
+                   mg_rhs_info* info, hipStream_t st) override {
+    const int m = o->restart, Bn = B(), n0 = pl.lv[0].n;
+    const long n0B = (long)n0 * Bn;
+    Kr k;
+    const size_t need = kr_carve(m, nullptr, k);
+    char* base = nullptr;
+    if (work) {
+      if (wbytes < need) return fail(MG_ERR_OOM, "Krylov workspace too small: need " + std::to_string(need) + " bytes");
+      base = static_cast<char*>(work);
+    } else {
+      if (kr_own_bytes < need) {
+        if (kr_own) {
+          HIP_TRY(hipStreamSynchronize(st));
+          HIP_TRY(hipFree(kr_own));
+          kr_own = nullptr;
+          kr_own_bytes = 0;
+        }
+        if (hipMalloc(&kr_own, need) != hipSuccess) {
+          (void)hipGetLastError();
+          kr_own = nullptr;
+          return fail(MG_ERR_OOM, "cannot allocate " + std::to_string(need) + " bytes of Krylov workspace");
+        }
+        kr_own_bytes = need;
+      }
+      base = kr_own;
+    }
+    kr_carve(m, base, k);
+    const unsigned eb = d[0].blocks;
+    // ||f|| (the residual of x = 0) fixes the stopping threshold and clears the totals
+    hipLaunchKernelGGL((k_fill0<double>), dim3(nblocks(n0B)), dim3(256), 0, st, n0B, dbuf);
+    LAUNCH_OK();
+    MG_TRY(outer_resid<TU>(f, dbuf, nullptr, (TU*)nullptr, k.beta, st));
+    hipLaunchKernelGGL(k_kr_start, dim3(1), dim3(256), 0, st, k.S, Bn, (const double*)k.beta, o->rtol, 1);
+    LAUNCH_OK();
+    int total = 0, cnt = 0;
+    for (;;) {
+      MG_TRY(outer_resid<TU>(f, x, k.V, (TU*)nullptr, k.beta, st));
+      hipLaunchKernelGGL(k_kr_start, dim3(1), dim3(256), 0, st, k.S, Bn, (const double*)k.beta, o->rtol, 0);
+      LAUNCH_OK();
+      MG_TRY(kr_count(k, &cnt, st));
+      if (cnt == 0 || total >= o->max_iter) break;
+      hipLaunchKernelGGL((k_kr_scale<TU>), dim3(eb), dim3(256), 0, st, n0, Bn, lbs, (const double*)k.V,
+                         (const double*)k.S.s, k.V, r0);
+      LAUNCH_OK();
+      int j = 0;
+      while (j < m && total < o->max_iter) {
+        TU* zj = k.Z + (size_t)j * k.zs;
+        switch (o->precond) {
+          case MG_PC_NONE: MG_TRY(copy((const TU*)r0, zj, n0B, st)); break;
+          case MG_PC_VCYCLE: MG_TRY(fwd(0, r0, zj, 1, nullptr, st)); break;
+          default: MG_TRY(fmg(r0, zj, st)); break;
+        }
+        ROWS_LAUNCH(d[0], k_kr_amul, (TU), L64, Bn, lbs, (const TU*)zj, k.w);
+        LAUNCH_OK();
+        // classical Gram-Schmidt, twice
+        MG_TRY(kr_dots(k, j + 1, k.h1, 0, st));
+        MG_TRY(kr_orth(k, j + 1, k.h1, 0, st));
+        MG_TRY(kr_dots(k, j + 1, k.h2, 0, st));
+        MG_TRY(kr_orth(k, j + 1, k.h2, 1, st));
+        hipLaunchKernelGGL(k_kr_givens, dim3(1), dim3(256), 0, st, k.S, Bn, j, (const double*)k.h1,
+                           (const double*)k.h2, (const double*)k.nrm2, o->rtol);
+        LAUNCH_OK();
+        ++j;
+        ++total;
+        MG_TRY(kr_count(k, &cnt, st));
+        if (cnt == 0) break;
+        if (j < m && total < o->max_iter) {
+          hipLaunchKernelGGL((k_kr_scale<TU>), dim3(eb), dim3(256), 0, st, n0, Bn, lbs, (const double*)k.w,
+                             (const double*)k.S.s, k.V + (size_t)j * k.vs, r0);
+          LAUNCH_OK();
+        }
+      }
+      hipLaunchKernelGGL(k_kr_lsq, dim3(1), dim3(256), 0, st, k.S, Bn, j, k.y);
+      LAUNCH_OK();
+      hipLaunchKernelGGL((k_kr_xupd<TU>), dim3(eb), dim3(256), 0, st, n0, Bn, lbs, j, (const TU*)k.Z, k.zs,
+                         (const double*)k.y, x);
+      LAUNCH_OK();
+    }
+    std::vector<int> hst(3 * Bn + 1);
+    std::vector<double> hb(Bn), hf(Bn);
+    HIP_TRY(hipMemcpyAsync(hst.data(), k.S.st, hst.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hb.data(), k.beta, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf.data(), k.S.fnorm, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    mg_status ret = MG_OK;
+    for (int b = 0; b < Bn; ++b) {
+      const int s = hst[2 * Bn + b];
+      if (info) {
+        info[b].iters = hst[Bn + b];
+        info[b].status = s;
+        info[b].relres = hf[b] > 0 ? hb[b] / hf[b] : hb[b];
+      }
+      if (s == MG_ERR_DIVERGED) ret = MG_ERR_DIVERGED;
+      else if (s != MG_OK && ret == MG_OK) ret = MG_ERR_NOT_CONVERGED;
+    }
+    if (ret != MG_OK) g_err = ret == MG_ERR_DIVERGED ? "a column's residual is not finite" : "a column did not converge";
+    return ret;
+  }
+
   // ---------------------------------------------------------------- reverse sweep
   int slot = 0;
 
@@ -1321,6 +1541,37 @@ mg_status mg_solve(mg_ctx* c, const double* f, double* u, mg_rhs_info* info, voi
   return c->e->solve(f, u, info, static_cast<hipStream_t>(stream));
 }
 
+mg_status mg_fmg(mg_ctx* c, const void* f, void* u, void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  return c->e->fmg_entry(f, u, static_cast<hipStream_t>(stream));
+}
+
+static mg_status check_krylov(const mg_krylov_options* o) {
+  if (!o) return fail(MG_ERR_INVALID_ARG, "null Krylov options");
+  if (o->restart < 1 || o->restart > 128) return fail(MG_ERR_INVALID_ARG, "restart must be in 1..128");
+  if (o->max_iter < 1) return fail(MG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(o->rtol >= 0.0)) return fail(MG_ERR_INVALID_ARG, "rtol must be >= 0");
+  if (o->precond < MG_PC_NONE || o->precond > MG_PC_FMG) return fail(MG_ERR_INVALID_ARG, "unknown preconditioner");
+  return MG_OK;
+}
+
+mg_status mg_fgmres_workspace_bytes(const mg_ctx* c, const mg_krylov_options* o, size_t* bytes) {
+  g_err.clear();
+  if (!c || !bytes) return fail(MG_ERR_INVALID_ARG, "null argument");
+  MG_TRY(check_krylov(o));
+  *bytes = c->e->fgmres_bytes(o->restart);
+  return MG_OK;
+}
+
+mg_status mg_fgmres(mg_ctx* c, const double* f, double* u, const mg_krylov_options* o, void* work, size_t work_bytes,
+                    mg_rhs_info* info, void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  MG_TRY(check_krylov(o));
+  return c->e->fgmres(f, u, o, work, work_bytes, info, static_cast<hipStream_t>(stream));
+}
+
 mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
   g_err.clear();
   if (!c || !n) return fail(MG_ERR_INVALID_ARG, "null argument");
@@ -1333,7 +1584,7 @@ mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
 
 mg_status mg_timing_start(mg_ctx* c, int32_t fam, int32_t level) {
   g_err.clear();
-  if (!c || fam < MG_KF_NONE || fam > MG_KF_OUTER) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
+  if (!c || fam < MG_KF_NONE || fam > MG_KF_KRYLOV) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
   return c->e->timing_start(fam, level);
 }
 
