@@ -9,8 +9,10 @@ relative residual of 1e-8 per column.  One step = one batched solve of the
 
 Also reported: the plain FP64 GPU V-cycle (classical components, K = 0) on the
 same hierarchy and right-hand sides, the roofline of the dominant kernel
-family (HIP events around each of its launches in the timed region), and the
-CPU FP64 oracle timed on a bounded sample.
+family (HIP events around each of its launches in the timed region), flexible
+GMRES with the learned and the classical cycle (or FMG) as preconditioner on
+the same inputs, the request loop, and the CPU FP64 oracle timed on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--max-outer", type=int, default=20000)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length of the Krylov comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="requests per serving run (closed loop, then open loop at 0.5x and 0.8x its rate); 0 skips")
@@ -118,7 +122,10 @@ def main():
     u_host = u.cpu().numpy()
     relres_host = np.linalg.norm(w.f - h.A[0] @ u_host, axis=0) / np.linalg.norm(w.f, axis=0)
     solves = B * args.steps
-    converged_all = all(i.code == 0 for i in infos) and float(relres_host.max()) <= 1e-8
+    # the library stops each column on its own FP64 residual; the host
+    # recomputation differs from it by cancellation (about eps ||A|| ||u|| / ||f||
+    # relative to ||f||), so the cross-check allows a relative 1e-3 on 1e-8
+    converged_all = all(i.code == 0 for i in infos) and float(relres_host.max()) <= 1e-8 * (1 + 1e-3)
     # a throughput only counts when every column reached the tolerance
     value = solves / elapsed if converged_all else 0.0
     avg_ms = kms / max(launches, 1)
@@ -168,7 +175,11 @@ def main():
         out["plain_fp64_gmg"] = {"value": B / (tb - ta), "unit": "solves/s", "ms_per_solve_batch": 1e3 * (tb - ta),
                                  "iters_max": int(pinfo.iters.max()), "converged": bool(pinfo.code == 0)}
         out["speedup_vs_plain_fp64_gmg"] = value / out["plain_fp64_gmg"]["value"]
+        if not args.no_krylov:
+            out["krylov"] = krylov(args, {"learned_" + args.precision: ctx, "classical_fp64": pctx}, f, w, h, B)
         pctx.close()
+    elif not args.no_krylov:
+        out["krylov"] = krylov(args, {"learned_" + args.precision: ctx}, f, w, h, B)
 
     if args.serving_requests > 0:
         out["serving"] = serving(args)
@@ -177,6 +188,41 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, params, args, float(info.iters.mean()))
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def krylov(args, ctxs, f, w, h, B):
+    """Flexible GMRES(restart) to 1e-8 with the cycle (or FMG) as right
+    preconditioner (the paper's Sec. 4.2 usage), same inputs as the main
+    solve: solves/s, iterations (preconditioner calls) and the host FP64
+    residual.  One untimed call first (it allocates the Krylov basis)."""
+    import torch
+    from paper_2608_29082_amd import binding as Bd
+    out = {"restart": args.restart, "rtol": 1e-8, "reorth": Bd.REORTH_DEFAULT}
+    for name, c in ctxs.items():
+        for pc in ("vcycle", "fmg"):
+            x = torch.zeros_like(f)
+            c.fgmres(f, x, restart=args.restart, max_iter=2, rtol=1e-8, precond=pc)
+            x.zero_()
+            c.timing_start("krylov", 0)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            info = c.fgmres(f, x, restart=args.restart, max_iter=2000, rtol=1e-8, precond=pc)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            kl, kms, kby = c.timing_read()
+            c.timing_start(None)
+            rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / np.linalg.norm(w.f, axis=0)
+            # the library stops on its own FP64 residual; the host recomputation of a
+            # residual 1e8 times smaller than f differs from it by cancellation (about
+            # eps ||A|| ||u|| / ||f||), so the cross-check allows a relative 1e-3
+            ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+            out[f"{name}_{pc}"] = {"value": B / (tb - ta) if ok else 0.0, "unit": "solves/s",
+                                   "ms_per_solve_batch": 1e3 * (tb - ta), "iters_max": int(info.iters.max()),
+                                   "iters_mean": float(info.iters.mean()), "relres_max_fp64_host": float(rr.max()),
+                                   "converged": bool(ok),
+                                   "gram_schmidt_ms": kms, "gram_schmidt_GBps": kby / (kms * 1e-3) / 1e9 if kms else 0.0}
+            print(f"# fgmres {name} {pc}: {out[f'{name}_{pc}']}", file=sys.stderr, flush=True)
+    return out
 
 
 def counter_traffic(kernel_family, level):

@@ -197,10 +197,16 @@ typedef enum {
 } mg_preconditioner;
 
 typedef struct {
-    int32_t restart;    /* m: basis vectors per restart cycle, 1..128 */
+    int32_t restart;    /* m: basis vectors per restart cycle, 1..63 */
     int32_t max_iter;   /* cap on a column's FGMRES iterations (preconditioner calls), >= 1 */
     double rtol;        /* stop a column when ||f - A u|| <= rtol ||f|| */
     int32_t precond;    /* mg_preconditioner */
+    double reorth;      /* second Gram-Schmidt pass for a vector when, in some active column,
+                           ||w after the first pass|| < reorth * ||w||.  The first pass leaves
+                           the new vector orthogonal to about eps / reorth, so 0.1 keeps the
+                           basis orthogonal to about ten units of roundoff per vector and
+                           0.70710678 ("twice is enough") to working precision; 0 never
+                           reorthogonalises (classical Gram-Schmidt), >= 1 always does */
 } mg_krylov_options;
 
 /* Device bytes of the Krylov workspace for these options: (m+1) FP64 basis
@@ -210,9 +216,9 @@ mg_status mg_fgmres_workspace_bytes(const mg_ctx* ctx, const mg_krylov_options* 
 
 /* Solve A_0 u = f by restarted flexible GMRES with right preconditioning
  * (Saad 1993) per column, from the given u.  The preconditioner runs in the
- * context precision; A z, the orthonormal basis (classical Gram-Schmidt
- * applied twice), the Hessenberg least-squares problem and the iterate are
- * FP64.  Each restart begins with the true FP64 residual; a column stops at
+ * context precision; A z, the orthonormal basis (classical Gram-Schmidt with a
+ * second pass as o->reorth selects), the Hessenberg least-squares problem and
+ * the iterate are FP64.  Each restart begins with the true FP64 residual; a column stops at
  * the first iteration whose least-squares residual estimate meets rtol (or
  * when its Krylov space becomes invariant) and is finished when its true
  * residual does.  info[b].iters counts the column's iterations.  f, u: device

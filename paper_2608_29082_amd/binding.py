@@ -29,6 +29,10 @@ EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", 
             "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres"]
 KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6}
 PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
+# default threshold of the second Gram-Schmidt pass: run it for a vector when
+# the first pass left less than a tenth of its norm (orthogonality to about
+# ten units of roundoff per vector; 1/sqrt 2 is the "twice is enough" bound)
+REORTH_DEFAULT = 0.1
 
 
 class MGError(RuntimeError):
@@ -60,7 +64,8 @@ class _Options(C.Structure):
 
 
 class _KrylovOptions(C.Structure):
-    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double), ("precond", C.c_int32)]
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double), ("precond", C.c_int32),
+                ("reorth", C.c_double)]
 
 
 class RhsInfo(C.Structure):
@@ -349,19 +354,22 @@ class Context:
         return u
 
     def fgmres_workspace_bytes(self, restart=30, precond="vcycle"):
-        o = _KrylovOptions(restart, 1, 0.0, PRECONDITIONERS[precond])
+        o = _KrylovOptions(restart, 1, 0.0, PRECONDITIONERS[precond], REORTH_DEFAULT)
         b = C.c_size_t()
         _check(self.lib.mg_fgmres_workspace_bytes(self._h, C.byref(o), C.byref(b)), "mg_fgmres_workspace_bytes")
         return b.value
 
-    def fgmres(self, f, u, restart=30, max_iter=500, rtol=None, precond="vcycle", work=None,
+    def fgmres(self, f, u, restart=30, max_iter=500, rtol=None, precond="vcycle", work=None, reorth=None,
                raise_on_failure=False) -> SolveInfo:
         """Flexible GMRES(restart) from u with the cycle (or FMG) as right preconditioner;
         iters counts FGMRES iterations per column.  work: optional uint8 device tensor
-        of fgmres_workspace_bytes (else the library keeps its own)."""
+        of fgmres_workspace_bytes (else the library keeps its own).  reorth: second
+        Gram-Schmidt pass threshold (default 0.1; 1/sqrt 2 "twice is enough"; 0 never,
+        >= 1 always)."""
         self._vec(f, self.torch.float64, "f")
         self._vec(u, self.torch.float64, "u")
-        o = _KrylovOptions(restart, max_iter, self._o.rtol if rtol is None else rtol, PRECONDITIONERS[precond])
+        o = _KrylovOptions(restart, max_iter, self._o.rtol if rtol is None else rtol, PRECONDITIONERS[precond],
+                           REORTH_DEFAULT if reorth is None else reorth)
         info = (RhsInfo * self.B)()
         st = self.lib.mg_fgmres(self._h, _ptr(f), _ptr(u), C.byref(o), _ptr(work),
                                 0 if work is None else work.numel(), info, self._s())

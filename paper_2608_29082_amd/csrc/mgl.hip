@@ -1120,12 +1120,12 @@ struct Engine final : EngineBase {
 
   // Krylov workspace (carved from one buffer)
   struct Kr {
-    int m = 0, chunk = 0, nblk = 0;
-    long vs = 0, zs = 0;           // element strides between basis vectors
-    double* V = nullptr;           // m + 1 orthonormal vectors, FP64
-    TU* Z = nullptr;               // m preconditioned vectors, cycle type
-    double *w = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr, *nrm2 = nullptr, *y = nullptr,
-           *beta = nullptr;
+    int m = 0, chunk = 0, nblk = 0, lbk = 0;
+    long zs = 0;                   // element stride between preconditioned vectors
+    double* V = nullptr;           // m + 1 unnormalised basis vectors vt_i, FP64, [n][m + 1][B]
+    TU* Z = nullptr;               // m preconditioned vectors zt_j = C(fl(vt_j)), cycle type, [m][n][B]
+    double *w = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr, *n2 = nullptr, *n4 = nullptr,
+           *y = nullptr, *beta = nullptr;
     KrState S{};
   };
   static constexpr int kKrBlocks = 1024;
@@ -1134,19 +1134,21 @@ struct Engine final : EngineBase {
     bp.base = base;
     const int n = pl.lv[0].n, Bn = B();
     const long nB = (long)n * Bn;
-    const long rpb = 256 >> lbs;
+    k.lbk = 0;
+    while ((1 << k.lbk) < Bn) ++k.lbk;
+    const long rpb = 256 >> k.lbk;
     k.m = m;
     k.chunk = (int)std::max<long>(rpb, (n + kKrBlocks - 1) / kKrBlocks);
     k.nblk = (int)((n + k.chunk - 1) / k.chunk);
-    k.vs = (nB + 31) / 32 * 32;
     k.zs = (nB + 127) / 128 * 128;
-    k.V = bp.take<double>((size_t)(m + 1) * k.vs);
+    k.V = bp.take<double>((size_t)(m + 1) * nB);
     k.Z = bp.take<TU>((size_t)m * k.zs);
     k.w = bp.take<double>(nB);
-    k.part = bp.take<double>((size_t)k.nblk * (m + 1) * Bn);
-    k.h1 = bp.take<double>((size_t)(m + 1) * Bn);
-    k.h2 = bp.take<double>((size_t)(m + 1) * Bn);
-    k.nrm2 = bp.take<double>(Bn);
+    k.part = bp.take<double>((size_t)k.nblk * (m + 2) * Bn);
+    k.h1 = bp.take<double>((size_t)(m + 2) * Bn);
+    k.h2 = bp.take<double>((size_t)(m + 2) * Bn);
+    k.n2 = bp.take<double>(Bn);
+    k.n4 = bp.take<double>(Bn);
     k.y = bp.take<double>((size_t)m * Bn);
     k.beta = bp.take<double>(Bn);
     k.S.m = m;
@@ -1154,10 +1156,11 @@ struct Engine final : EngineBase {
     k.S.cs = bp.take<double>((size_t)m * Bn);
     k.S.sn = bp.take<double>((size_t)m * Bn);
     k.S.g = bp.take<double>((size_t)(m + 1) * Bn);
-    k.S.s = bp.take<double>(Bn);
+    k.S.sig = bp.take<double>((size_t)(m + 1) * Bn);
     k.S.fnorm = bp.take<double>(Bn);
     k.S.act = bp.take<int>(Bn);
     k.S.jd = bp.take<int>(Bn);
+    k.S.flag = bp.take<int>(1);
     k.S.st = bp.take<int>(3 * (size_t)Bn + 1);
     return bp.off + 256;
   }
@@ -1166,30 +1169,70 @@ struct Engine final : EngineBase {
     return kr_carve(restart, nullptr, k);
   }
 
-  // dots[i] (+)= <w, V_i>, i < nv, per column
-  mg_status kr_dots(const Kr& k, int nv, double* out, int add, hipStream_t st) {
+  // Gram-Schmidt sweeps over nv basis vectors with NG >= nv register accumulators;
+  // the update sweep forms the next pass's dot products while nv <= kKrFuse
+  static constexpr int kKrFuse = 32;
+  // call fn with std::integral_constant<int, NG>, NG the register block for nv
+  // basis vectors: nv rounded up to a multiple of 4 (of 8 above 32)
+  template <class F>
+  static void kr_ng(int nv, F&& fn) {
+    using std::integral_constant;
+    switch ((nv + 3) / 4) {
+      case 1: fn(integral_constant<int, 4>{}); break;
+      case 2: fn(integral_constant<int, 8>{}); break;
+      case 3: fn(integral_constant<int, 12>{}); break;
+      case 4: fn(integral_constant<int, 16>{}); break;
+      case 5: fn(integral_constant<int, 20>{}); break;
+      case 6: fn(integral_constant<int, 24>{}); break;
+      case 7: fn(integral_constant<int, 28>{}); break;
+      case 8: fn(integral_constant<int, 32>{}); break;
+      case 9: case 10: fn(integral_constant<int, 40>{}); break;
+      case 11: case 12: fn(integral_constant<int, 48>{}); break;
+      case 13: case 14: fn(integral_constant<int, 56>{}); break;
+      default: fn(integral_constant<int, 64>{}); break;
+    }
+  }
+  template <int NG>
+  void kr_dot_ng(const Kr& k, int nv, const double* w, long wrs, const int* skip, hipStream_t st) {
+    hipLaunchKernelGGL((k_kr_dot<NG>), dim3(k.nblk), dim3(256), 0, st, pl.lv[0].n, B(), k.lbk, k.chunk, nv,
+                       (const double*)k.V, k.m + 1, (const double*)k.S.sig, w, wrs, k.part, skip);
+  }
+  template <int NG, bool DOTS>
+  void kr_upd_ng(const Kr& k, int nv, const double* h, const double* wi, long wis, double* wo, long wos,
+                 const int* skip, hipStream_t st) {
+    hipLaunchKernelGGL((k_kr_upd<NG, TU, DOTS>), dim3(k.nblk), dim3(256), 0, st, pl.lv[0].n, B(), k.lbk, k.chunk,
+                       nv, (const double*)k.V, k.m + 1, (const double*)k.S.sig, h, wi, wis, wo, wos, r0, k.part,
+                       skip);
+  }
+  // out[0..nv) = <w, v_t>, out[nv] = ||w||^2 (per column; zero when skipped)
+  mg_status kr_dot(const Kr& k, int nv, const double* w, long wrs, double* out, const int* skip, hipStream_t st) {
     const int l = 0;
-    const int n = pl.lv[0].n;
-    TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 1),
-          hipLaunchKernelGGL(k_kr_dots, dim3(k.nblk), dim3(256), 0, st, n, B(), lbs, k.chunk, nv,
-                             (const double*)k.V, k.vs, (const double*)k.w, k.part));
-    hipLaunchKernelGGL(k_kr_reduce, dim3(nv), dim3(256), 0, st, (const double*)k.part, k.nblk, nv, B(), lbs, out,
-                       add);
+    TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 1), kr_ng(nv, [&](auto ng) {
+            kr_dot_ng<decltype(ng)::value>(k, nv, w, wrs, skip, st);
+          }));
+    hipLaunchKernelGGL(k_kr_reduce, dim3(nv + 1), dim3(1024), 0, st, (const double*)k.part, k.nblk, nv + 1, B(),
+                       k.lbk, out, skip);
     LAUNCH_OK();
     return MG_OK;
   }
-  // w -= sum_i h_i V_i (i < nv); norm2: nrm2 = ||w||^2 per column
-  mg_status kr_orth(const Kr& k, int nv, const double* h, int norm2, hipStream_t st) {
+  // wo = wi - sum_t h_t v_t, r0 = fl(wo); dots: out[0..nv) = <wo, v_t>, out[nv] = ||wo||^2,
+  // else out[0] = ||wo||^2 (zero when skipped)
+  mg_status kr_upd(const Kr& k, int nv, const double* h, const double* wi, long wis, double* wo, long wos,
+                   bool dots, double* out, const int* skip, hipStream_t st) {
     const int l = 0;
-    const int n = pl.lv[0].n;
-    TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 2),
-          hipLaunchKernelGGL(k_kr_orth, dim3(k.nblk), dim3(256), 0, st, n, B(), lbs, k.chunk, nv,
-                             (const double*)k.V, k.vs, h, k.w, norm2, k.part));
-    if (norm2) {
-      hipLaunchKernelGGL(k_kr_reduce, dim3(1), dim3(256), 0, st, (const double*)k.part, k.nblk, 1, B(), lbs, k.nrm2,
-                         0);
-      LAUNCH_OK();
-    }
+    TIMED(MG_KF_KRYLOV, nB(0) * (8.0 * (nv + 2) + sizeof(TU)), kr_ng(nv, [&](auto ng) {
+            constexpr int NG = decltype(ng)::value;
+            if constexpr (NG <= kKrFuse) {
+              if (dots) kr_upd_ng<NG, true>(k, nv, h, wi, wis, wo, wos, skip, st);
+              else kr_upd_ng<NG, false>(k, nv, h, wi, wis, wo, wos, skip, st);
+            } else {
+              kr_upd_ng<NG, false>(k, nv, h, wi, wis, wo, wos, skip, st);
+            }
+          }));
+    const int rows = dots ? nv + 1 : 1;
+    hipLaunchKernelGGL(k_kr_reduce, dim3(rows), dim3(1024), 0, st, (const double*)k.part, k.nblk, rows, B(), k.lbk,
+                       out, skip);
+    LAUNCH_OK();
     return MG_OK;
   }
   mg_status kr_count(const Kr& k, int* cnt, hipStream_t st) {
@@ -1240,14 +1283,14 @@ struct Engine final : EngineBase {
     LAUNCH_OK();
     int total = 0, cnt = 0;
     for (;;) {
-      MG_TRY(outer_resid<TU>(f, x, k.V, (TU*)nullptr, k.beta, st));
+      // vt_0 = f - A x (FP64) and its cycle-type copy, the first preconditioner input
+      MG_TRY(outer_resid<TU>(f, x, k.w, r0, k.beta, st));
+      hipLaunchKernelGGL(k_kr_put0, dim3(eb), dim3(256), 0, st, n0, Bn, lbs, (const double*)k.w, k.V, m + 1);
+      LAUNCH_OK();
       hipLaunchKernelGGL(k_kr_start, dim3(1), dim3(256), 0, st, k.S, Bn, (const double*)k.beta, o->rtol, 0);
       LAUNCH_OK();
       MG_TRY(kr_count(k, &cnt, st));
       if (cnt == 0 || total >= o->max_iter) break;
-      hipLaunchKernelGGL((k_kr_scale<TU>), dim3(eb), dim3(256), 0, st, n0, Bn, lbs, (const double*)k.V,
-                         (const double*)k.S.s, k.V, r0);
-      LAUNCH_OK();
       int j = 0;
       while (j < m && total < o->max_iter) {
         TU* zj = k.Z + (size_t)j * k.zs;
@@ -1256,25 +1299,30 @@ struct Engine final : EngineBase {
           case MG_PC_VCYCLE: MG_TRY(fwd(0, r0, zj, 1, nullptr, st)); break;
           default: MG_TRY(fmg(r0, zj, st)); break;
         }
-        ROWS_LAUNCH(d[0], k_kr_amul, (TU), L64, Bn, lbs, (const TU*)zj, k.w);
+        // w = A z_j with z_j = sig_j zt_j
+        ROWS_LAUNCH(d[0], k_kr_amul, (TU), L64, Bn, lbs, (const TU*)zj, (const double*)(k.S.sig + (size_t)j * Bn),
+                    k.w);
         LAUNCH_OK();
-        // classical Gram-Schmidt, twice
-        MG_TRY(kr_dots(k, j + 1, k.h1, 0, st));
-        MG_TRY(kr_orth(k, j + 1, k.h1, 0, st));
-        MG_TRY(kr_dots(k, j + 1, k.h2, 0, st));
-        MG_TRY(kr_orth(k, j + 1, k.h2, 1, st));
+        const int nv = j + 1;
+        double* vn = k.V + (size_t)(j + 1) * Bn;     // basis slot j + 1 (row stride (m + 1) B)
+        const long vrs = (long)(m + 1) * Bn;
+        // classical Gram-Schmidt; the second pass is applied only where needed
+        MG_TRY(kr_dot(k, nv, k.w, Bn, k.h1, nullptr, st));
+        const bool fuse = nv <= kKrFuse;
+        const double* n2 = fuse ? k.h2 + (size_t)nv * Bn : k.n2;
+        MG_TRY(kr_upd(k, nv, k.h1, k.w, Bn, vn, vrs, fuse, fuse ? k.h2 : k.n2, nullptr, st));
+        hipLaunchKernelGGL(k_kr_reorth, dim3(1), dim3(256), 0, st, k.S, Bn, (const double*)(k.h1 + (size_t)nv * Bn),
+                           n2, o->reorth * o->reorth);
+        LAUNCH_OK();
+        if (!fuse) MG_TRY(kr_dot(k, nv, vn, vrs, k.h2, k.S.flag, st));
+        MG_TRY(kr_upd(k, nv, k.h2, vn, vrs, vn, vrs, false, k.n4, k.S.flag, st));
         hipLaunchKernelGGL(k_kr_givens, dim3(1), dim3(256), 0, st, k.S, Bn, j, (const double*)k.h1,
-                           (const double*)k.h2, (const double*)k.nrm2, o->rtol);
+                           (const double*)k.h2, n2, (const double*)k.n4, o->rtol);
         LAUNCH_OK();
         ++j;
         ++total;
         MG_TRY(kr_count(k, &cnt, st));
         if (cnt == 0) break;
-        if (j < m && total < o->max_iter) {
-          hipLaunchKernelGGL((k_kr_scale<TU>), dim3(eb), dim3(256), 0, st, n0, Bn, lbs, (const double*)k.w,
-                             (const double*)k.S.s, k.V + (size_t)j * k.vs, r0);
-          LAUNCH_OK();
-        }
       }
       hipLaunchKernelGGL(k_kr_lsq, dim3(1), dim3(256), 0, st, k.S, Bn, j, k.y);
       LAUNCH_OK();
@@ -1549,10 +1597,11 @@ mg_status mg_fmg(mg_ctx* c, const void* f, void* u, void* stream) {
 
 static mg_status check_krylov(const mg_krylov_options* o) {
   if (!o) return fail(MG_ERR_INVALID_ARG, "null Krylov options");
-  if (o->restart < 1 || o->restart > 128) return fail(MG_ERR_INVALID_ARG, "restart must be in 1..128");
+  if (o->restart < 1 || o->restart > 63) return fail(MG_ERR_INVALID_ARG, "restart must be in 1..63");
   if (o->max_iter < 1) return fail(MG_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(o->rtol >= 0.0)) return fail(MG_ERR_INVALID_ARG, "rtol must be >= 0");
   if (o->precond < MG_PC_NONE || o->precond > MG_PC_FMG) return fail(MG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!(o->reorth >= 0.0)) return fail(MG_ERR_INVALID_ARG, "reorth must be >= 0");
   return MG_OK;
 }
 

@@ -56,6 +56,48 @@ def test_fgmres_fixed_iterations_match_oracle(precond, name, hier):
         assert err <= 1e-9
 
 
+@pytest.mark.parametrize("reorth", [0.0, 1.0])
+def test_fgmres_reorthogonalisation_policies_match_oracle(reorth):
+    """Classical Gram-Schmidt without (0) and always with (1) the second pass
+    give the oracle's (modified Gram-Schmidt) iterate after 7 iterations."""
+    import torch
+    name, hier = CASES[1]
+    J = hier.nlevels
+    B = 3
+    flat = C.random_params(J, 2, 2, 2, seed=70, spread=0.2)
+    f = C.rng(6, 2, 0).standard_normal((hier.sizes[0], B))
+    want, it, _, _ = KR.fgmres(oracle_levels(hier), oracle_params(flat, J, 2), f, restart=4, rtol=0.0, max_iter=7,
+                               precond="vcycle")
+    ctx = ctx_for(hier, flat, 2, B, "fp64")
+    x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
+    info = ctx.fgmres(to_dev(f, torch.float64), x, restart=4, max_iter=7, rtol=0.0, precond="vcycle", reorth=reorth)
+    err = rel(to_np(x), want)
+    print(f"fgmres reorth={reorth}: rel {err:.2e}", flush=True)
+    assert list(info.iters) == [7] * B
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("restart,k", [(40, 45), (63, 63)])
+def test_fgmres_long_restart_matches_oracle(restart, k):
+    """More than 32 basis vectors (separate second-pass dot sweep) and the
+    largest restart: the FP64 iterate after k iterations against the oracle."""
+    import torch
+    name, hier = CASES[1]
+    J = hier.nlevels
+    B = 2
+    flat = C.random_params(J, 2, 2, 2, seed=73, spread=0.2)
+    f = C.rng(6, 5, 0).standard_normal((hier.sizes[0], B))
+    want, it, _, _ = KR.fgmres(oracle_levels(hier), oracle_params(flat, J, 2), f, restart=restart, rtol=0.0,
+                               max_iter=k, precond="none")
+    ctx = ctx_for(hier, flat, 2, B, "fp64")
+    x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
+    info = ctx.fgmres(to_dev(f, torch.float64), x, restart=restart, max_iter=k, rtol=0.0, precond="none")
+    err = rel(to_np(x), want)
+    print(f"fgmres none m={restart} k={k}: rel {err:.2e}", flush=True)
+    assert list(info.iters) == list(it) == [k] * B
+    assert err <= 1e-9
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("precond", ["vcycle", "fmg"])
 def test_fgmres_converges_like_oracle(prec, precond):
