@@ -123,6 +123,21 @@ def lshape_aniso(seed: int = 0, B: int = 1, K: int = 3, refinements: int = 4,
     return Workload("lshape-aniso", h, f, identity_params(J, K, K, K), K, K, K, precision="fp32")
 
 
+def darcy_inclusion(seed: int = 0, n: int = 100, nlevels: int = 7, B: int = 8, K: int = 3) -> tuple:
+    """Darcy pressure equation (Sec. 4.1): n x n cells, k = 1e-6 on [0.4, 0.6]^2
+    and 1 elsewhere, p = 1 / 0 on the left / right, no flow on top and bottom,
+    f = 0, piecewise constant interpolation, Galerkin coarsening, nu = 4.
+    Returns (Workload with f = the boundary right-hand side in every column,
+    u0: seeded random initial iterates (n^2, B))."""
+    from . import darcy as D
+    h, b = D.darcy_hierarchy(D.inclusion_field(n), nlevels)
+    f = np.repeat(b[:, None], B, axis=1)
+    u0 = rng(9, _RHS, seed).standard_normal((h.sizes[0], B))
+    w = Workload(f"darcy-{n}", h, f, identity_params(nlevels, K, K, K), K, K, K, nu_pre=4, nu_post=4,
+                 precision="fp32")
+    return w, u0
+
+
 SERVING_SIDES = (65, 129, 257, 513, 1025)
 
 

@@ -113,10 +113,11 @@ def cycle_vjp(levels, prm: OParams, f, u, g):
     return fbar, ubar, grads
 
 
-def unrolled_loss(levels, prm: OParams, f, cycles: int = 10):
-    """Alg. 3 forward unrolled: u^0 = 0, u^m = LMG(A, f, u^{m-1});
+def unrolled_loss(levels, prm: OParams, f, cycles: int = 10, u0=None):
+    """Alg. 3 forward unrolled: u^0 = 0 (or a given start, e.g. the random
+    initial guess of Sec. 4.1), u^m = LMG(A, f, u^{m-1});
     L = mean_b ||f_b - A u_b^{cycles}||^2 / ||f_b||^2."""
-    u = np.zeros_like(f)
+    u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64)
     for _ in range(cycles):
         u = lmg(levels, prm, 0, f, u)
     r = residual(levels[0], f, u)
@@ -124,9 +125,9 @@ def unrolled_loss(levels, prm: OParams, f, cycles: int = 10):
     return float(np.mean(np.sum(r * r, axis=0) / fn2))
 
 
-def unrolled_loss_and_grad(levels, prm: OParams, f, cycles: int = 10):
+def unrolled_loss_and_grad(levels, prm: OParams, f, cycles: int = 10, u0=None):
     """Loss of `unrolled_loss` and its gradient w.r.t. the parameters."""
-    us = [np.zeros_like(f)]
+    us = [np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64)]
     for _ in range(cycles):
         us.append(lmg(levels, prm, 0, f, us[-1]))
     A = levels[0].A
