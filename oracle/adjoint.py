@@ -25,13 +25,32 @@ from .lmg import OLevel, OParams, graph_conv, neighbour_mean, residual, smooth, 
 
 
 def neighbour_mean_T(lv: OLevel, y: np.ndarray) -> np.ndarray:
-    """M^T y = A_g^T (D_g^{-1} y)."""
+    """M^T y = A_g^T (D_g^{-1} y) (the aggregation operator's transpose)."""
+    if lv.Gw is not None:
+        return lv.Gw.T @ y
     return lv.G.T @ (lv.inv_deg[:, None] * y)
 
 
-def graph_conv_vjp(c: np.ndarray, lv: OLevel, x: np.ndarray, ybar: np.ndarray):
-    """For y = sum_k c_k M^k x: returns (x_bar, c_bar)."""
+def _cheb_terms(op, x, K):
+    """[T_0(-op) x, ..., T_K(-op) x] by the three-term recurrence."""
+    ts = [x]
+    if K >= 1:
+        ts.append(-op(x))
+    for _ in range(1, K):
+        ts.append(-2.0 * op(ts[-1]) - ts[-2])
+    return ts
+
+
+def graph_conv_vjp(c: np.ndarray, lv: OLevel, x: np.ndarray, ybar: np.ndarray, basis: str = "monomial"):
+    """For y = sum_k c_k M^k x (or sum_k c_k T_k(-M) x): returns (x_bar, c_bar).
+    The transpose of a polynomial in M is the same polynomial in M^T."""
     K = len(c) - 1
+    if basis == "chebyshev":
+        tx = _cheb_terms(lambda v: neighbour_mean(lv, v), x, K)
+        cbar = np.array([np.sum(ybar * t) for t in tx])
+        tg = _cheb_terms(lambda v: neighbour_mean_T(lv, v), ybar, K)
+        xbar = sum(c[k] * tg[k] for k in range(K + 1))
+        return xbar, cbar
     cbar = np.zeros(K + 1)
     w = x
     for k in range(K + 1):
@@ -49,16 +68,16 @@ def graph_conv_vjp(c: np.ndarray, lv: OLevel, x: np.ndarray, ybar: np.ndarray):
 
 def zero_grads(prm: OParams) -> OParams:
     return OParams(np.zeros_like(prm.theta), np.zeros_like(prm.eta), np.zeros_like(prm.cB),
-                   np.zeros_like(prm.cR), np.zeros_like(prm.cP), prm.nu_pre, prm.nu_post)
+                   np.zeros_like(prm.cR), np.zeros_like(prm.cP), prm.nu_pre, prm.nu_post, prm.basis)
 
 
 def _smooth_vjp(lv, l, prm, f, u, g, grads):
     rs = lv.Dinv[:, None] * residual(lv, f, u)         # D^{-1}(f - A u)
     delta = prm.theta[l] * rs
-    phi = graph_conv(prm.cB[l], lv, delta)
+    phi = graph_conv(prm.cB[l], lv, delta, prm.basis)
     grads.eta[l] += np.sum(g * phi)
     phibar = prm.eta[l] * g
-    dbar, cbar = graph_conv_vjp(prm.cB[l], lv, delta, phibar)
+    dbar, cbar = graph_conv_vjp(prm.cB[l], lv, delta, phibar, prm.basis)
     grads.cB[l] += cbar
     grads.theta[l] += np.sum(dbar * rs)
     s = prm.theta[l] * (lv.Dinv[:, None] * dbar)
@@ -79,10 +98,10 @@ def lmg_vjp(levels, prm: OParams, l: int, f, u, g, grads: OParams):
         pre.append(u)
         u = smooth(lv, l, prm, f, u)
     r = residual(lv, f, u)
-    rc = lv.R @ graph_conv(prm.cR[l], lv, r)
+    rc = lv.R @ graph_conv(prm.cR[l], lv, r, prm.basis)
     ec = lmg(levels, prm, l + 1, rc, np.zeros((levels[l + 1].A.shape[0], f.shape[1])))
     pe = lv.P @ ec
-    u = u + graph_conv(prm.cP[l], lv, pe)
+    u = u + graph_conv(prm.cP[l], lv, pe, prm.basis)
     post = []
     for _ in range(prm.nu_post):
         post.append(u)
@@ -92,11 +111,11 @@ def lmg_vjp(levels, prm: OParams, l: int, f, u, g, grads: OParams):
     for up in reversed(post):
         s, g = _smooth_vjp(lv, l, prm, f, up, g, grads)
         fbar += s
-    xbar, cbar = graph_conv_vjp(prm.cP[l], lv, pe, g)
+    xbar, cbar = graph_conv_vjp(prm.cP[l], lv, pe, g, prm.basis)
     grads.cP[l] += cbar
     ecbar = lv.P.T @ xbar
     rcbar, _ = lmg_vjp(levels, prm, l + 1, rc, np.zeros_like(ec), ecbar, grads)
-    rbar, cbar = graph_conv_vjp(prm.cR[l], lv, r, lv.R.T @ rcbar)
+    rbar, cbar = graph_conv_vjp(prm.cR[l], lv, r, lv.R.T @ rcbar, prm.basis)
     grads.cR[l] += cbar
     fbar += rbar
     g = g - lv.A.T @ rbar

@@ -25,10 +25,10 @@ def fmg(levels: list[OLevel], prm: OParams, f: np.ndarray) -> np.ndarray:
     J = len(levels)
     fs = [f]
     for l in range(J - 1):
-        fs.append(levels[l].R @ graph_conv(prm.cR[l], levels[l], fs[-1]))
+        fs.append(levels[l].R @ graph_conv(prm.cR[l], levels[l], fs[-1], prm.basis))
     u = coarse_solve(levels[J - 1], fs[J - 1])
     for l in range(J - 2, -1, -1):
-        u = graph_conv(prm.cP[l], levels[l], levels[l].P @ u)
+        u = graph_conv(prm.cP[l], levels[l], levels[l].P @ u, prm.basis)
         u = lmg(levels, prm, l, fs[l], u)
     return u
 

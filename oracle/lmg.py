@@ -14,6 +14,15 @@ Plain, slow, obviously-correct NumPy/SciPy code written from the paper:
   * the classical V-cycle MG (Alg. 1), written separately,
   * the stationary iteration u^m = u^{m-1} + B (f - A u^{m-1}) with per-column
     stopping (Sec. 1).
+Variants of the convolution (Sec. 3.3, other operators such as ChebConv;
+Sec. 2.1, edge weights that encode matrix entries):
+  * aggregation "weighted": G = D_w^{-1} W with W_ij = |A_ij| on the graph
+    (|G_ij| for a given weighted graph), D_w = diag(sum_j W_ij);
+  * aggregation "sym": G = D_g^{-1/2} A_g D_g^{-1/2} (the symmetric
+    normalisation of the ChebConv layer);
+  * basis "chebyshev": Phi(x) = sum_k c_k T_k(-G) x, T_k the Chebyshev
+    polynomials evaluated by their three-term recurrence (the ChebConv layer
+    with the rescaled Laplacian 2 L / lambda_max - I, L = I - G, lambda_max = 2).
 Vectors are (n, B) arrays: B independent right-hand sides side by side.
 """
 from __future__ import annotations
@@ -35,6 +44,7 @@ class OLevel:
     P: sp.csr_matrix | None   # prolongation to this level from the next coarser one
     R: sp.csr_matrix | None   # restriction from this level to the next coarser one
     lu: tuple | None = None   # dense LU factors (coarsest level only)
+    Gw: sp.csr_matrix | None = None   # aggregation operator for "weighted" / "sym" (None: mean)
 
 
 def algebraic_graph(A: sp.csr_matrix) -> sp.csr_matrix:
@@ -45,10 +55,28 @@ def algebraic_graph(A: sp.csr_matrix) -> sp.csr_matrix:
     return sp.csr_matrix((np.ones(int(keep.sum())), (C.row[keep], C.col[keep])), shape=(n, n))
 
 
-def make_levels(A_list, P_list, R_list=None, G_list=None, ghost_degree=None) -> list[OLevel]:
+def aggregation_operator(A: sp.csr_matrix, G: sp.csr_matrix, Graw, aggregation: str):
+    """The explicit operator G for the non-mean aggregations (see module doc)."""
+    n = A.shape[0]
+    if aggregation == "weighted":
+        src = sp.coo_matrix(A if Graw is None else Graw)
+        keep = (src.row != src.col) & (src.data != 0.0)
+        W = sp.csr_matrix((np.abs(src.data[keep]), (src.row[keep], src.col[keep])), shape=(n, n))
+        rs = np.asarray(W.sum(axis=1)).ravel()
+        return sp.csr_matrix(sp.diags(np.where(rs > 0, 1.0 / np.where(rs > 0, rs, 1.0), 0.0)) @ W)
+    if aggregation == "sym":
+        deg = np.asarray(G.sum(axis=1)).ravel()
+        isd = np.where(deg > 0, 1.0 / np.sqrt(np.where(deg > 0, deg, 1.0)), 0.0)
+        return sp.csr_matrix(sp.diags(isd) @ G @ sp.diags(isd))
+    raise ValueError(aggregation)
+
+
+def make_levels(A_list, P_list, R_list=None, G_list=None, ghost_degree=None,
+                aggregation: str = "mean") -> list[OLevel]:
     """Bundle a hierarchy.  R defaults to P^T (Sec. 2.2).  G defaults to the
     algebraic graph of A_l.  ghost_degree, if given, overrides |N(i)| by a
-    constant (used only by the closed-form eigenvalue check)."""
+    constant (used only by the closed-form eigenvalue check).  aggregation:
+    "mean" (default), "weighted" or "sym" (module doc)."""
     J = len(A_list)
     levels = []
     for l in range(J):
@@ -71,7 +99,11 @@ def make_levels(A_list, P_list, R_list=None, G_list=None, ghost_degree=None) -> 
         else:
             R = None
         lu = sla.lu_factor(A.toarray()) if l == J - 1 else None
-        levels.append(OLevel(A, 1.0 / A.diagonal(), G, inv_deg, P, R, lu))
+        Gw = None
+        if aggregation != "mean":
+            Graw = None if G_list is None or G_list[l] is None else sp.csr_matrix(G_list[l], dtype=np.float64)
+            Gw = aggregation_operator(A, G, Graw, aggregation)
+        levels.append(OLevel(A, 1.0 / A.diagonal(), G, inv_deg, P, R, lu, Gw))
     return levels
 
 
@@ -85,9 +117,11 @@ class OParams:
     cP: np.ndarray      # [J-1, KP+1]
     nu_pre: int = 2
     nu_post: int = 2
+    basis: str = "monomial"   # or "chebyshev"
 
 
-def unpack(flat, J: int, KB: int, KR: int, KP: int, nu_pre: int = 2, nu_post: int = 2) -> OParams:
+def unpack(flat, J: int, KB: int, KR: int, KP: int, nu_pre: int = 2, nu_post: int = 2,
+           basis: str = "monomial") -> OParams:
     """Flat layout per level l: [theta, eta, cB[0..KB], cR[0..KR], cP[0..KP]]."""
     per = 2 + KB + 1 + KR + 1 + KP + 1
     p = np.asarray(flat, dtype=np.float64).reshape(J - 1, per)
@@ -95,7 +129,7 @@ def unpack(flat, J: int, KB: int, KR: int, KP: int, nu_pre: int = 2, nu_post: in
     cB = p[:, o:o + KB + 1]; o += KB + 1
     cR = p[:, o:o + KR + 1]; o += KR + 1
     cP = p[:, o:o + KP + 1]
-    return OParams(p[:, 0].copy(), p[:, 1].copy(), cB.copy(), cR.copy(), cP.copy(), nu_pre, nu_post)
+    return OParams(p[:, 0].copy(), p[:, 1].copy(), cB.copy(), cR.copy(), cP.copy(), nu_pre, nu_post, basis)
 
 
 def pack(p: OParams) -> np.ndarray:
@@ -104,13 +138,25 @@ def pack(p: OParams) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- operators
 def neighbour_mean(lv: OLevel, x: np.ndarray) -> np.ndarray:
-    """(M x)_i = mean of x_j over j in N(i); 0 when N(i) is empty."""
+    """(M x)_i = mean of x_j over j in N(i); 0 when N(i) is empty.  With a
+    non-mean aggregation, the level's aggregation operator applied to x."""
+    if lv.Gw is not None:
+        return lv.Gw @ x
     return lv.inv_deg[:, None] * (lv.G @ x)
 
 
-def graph_conv(c: np.ndarray, lv: OLevel, x: np.ndarray) -> np.ndarray:
-    """Phi(x) = sum_{k=0..K} c_k M^k x, by Horner: y = c_K x; y = M y + c_k x."""
+def graph_conv(c: np.ndarray, lv: OLevel, x: np.ndarray, basis: str = "monomial") -> np.ndarray:
+    """Phi(x) = sum_{k=0..K} c_k M^k x, by Horner: y = c_K x; y = M y + c_k x.
+    basis "chebyshev": Phi(x) = sum_k c_k T_k(-M) x with T_0 x = x,
+    T_1 = -M x, T_{k+1} = -2 M T_k - T_{k-1}."""
     K = len(c) - 1
+    if basis == "chebyshev":
+        t_prev, t = x, -neighbour_mean(lv, x)
+        y = c[0] * t_prev + (c[1] * t if K >= 1 else 0.0)
+        for k in range(1, K):
+            t_prev, t = t, -2.0 * neighbour_mean(lv, t) - t_prev
+            y = y + c[k + 1] * t
+        return y
     y = c[K] * x
     for k in range(K - 1, -1, -1):
         y = neighbour_mean(lv, y) + c[k] * x
@@ -129,7 +175,7 @@ def coarse_solve(lv: OLevel, f: np.ndarray) -> np.ndarray:
 def smooth(lv: OLevel, l: int, prm: OParams, f, u):
     """delta = theta_l D_A^{-1} (f - A_l u);  u <- u + eta_l Phi_B(delta)."""
     delta = prm.theta[l] * (lv.Dinv[:, None] * residual(lv, f, u))
-    return u + prm.eta[l] * graph_conv(prm.cB[l], lv, delta)
+    return u + prm.eta[l] * graph_conv(prm.cB[l], lv, delta, prm.basis)
 
 
 def lmg(levels: list[OLevel], prm: OParams, l: int, f: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -141,10 +187,10 @@ def lmg(levels: list[OLevel], prm: OParams, l: int, f: np.ndarray, u: np.ndarray
     for _ in range(prm.nu_pre):
         u = smooth(lv, l, prm, f, u)
     r = residual(lv, f, u)
-    rc = lv.R @ graph_conv(prm.cR[l], lv, r)
+    rc = lv.R @ graph_conv(prm.cR[l], lv, r, prm.basis)
     ec = np.zeros((levels[l + 1].A.shape[0], f.shape[1]))
     ec = lmg(levels, prm, l + 1, rc, ec)
-    e = graph_conv(prm.cP[l], lv, lv.P @ ec)
+    e = graph_conv(prm.cP[l], lv, lv.P @ ec, prm.basis)
     u = u + e
     for _ in range(prm.nu_post):
         u = smooth(lv, l, prm, f, u)

@@ -60,7 +60,7 @@ def expand(name: str, phi, J: int, KB: int, KR: int, KP: int, omega: float = 2.0
     assert pos == phi.size, "phi has the wrong length"
     cR = np.array([cR_shared for _ in range(L)])
     cP = np.array([cP_shared for _ in range(L)])
-    return OParams(theta, eta, cB, cR, cP, nu_pre, nu_post)
+    return OParams(theta, eta, cB, cR, cP, nu_pre, nu_post)  # monomial basis
 
 
 def grad_phi(name: str, g: OParams, J: int, KB: int, KR: int, KP: int) -> np.ndarray:

@@ -26,7 +26,7 @@ def _transposed_mean(lv, x):
     return lv.G.T @ (lv.inv_deg[:, None] * x)
 
 
-def _reversed_horner(c, lv, x):
+def _reversed_horner(c, lv, x, basis="monomial"):
     K = len(c) - 1
     y = c[0] * x
     for k in range(1, K + 1):
