@@ -16,6 +16,8 @@
  * polynomial-smoother remark of Sec. 3.5):
  *     Phi(x) = sum_{k=0..K} c_k M^k x .
  * The graph of level l is {(i, j): A_ij != 0, i != j} unless given (Sec. 2.1).
+ * mg_params selects the aggregation operator G in place of M (weighted or
+ * symmetric normalisation) and a Chebyshev basis for the coefficients.
  *
  * Conventions for every entry point:
  *  - Return an mg_status; they never abort and never throw.  On failure a
@@ -87,11 +89,31 @@ typedef struct {
  * l = 0 .. J-2 as
  *     [theta_l, eta_l, cB_l[0..KB], cR_l[0..KR], cP_l[0..KP]] .
  * Identity initialisation (Sec. 3.4): theta = omega, eta = 1, c_0 = 1,
- * c_k = 0 for k > 0, which is the classical V-cycle (Alg. 1). */
+ * c_k = 0 for k > 0, which is the classical V-cycle (Alg. 1), in either basis
+ * (T_0 = 1).  The library evaluates every convolution as a polynomial in G by
+ * Horner's rule; Chebyshev coefficients are converted to power-series
+ * coefficients once (at setup and in mg_set_params), and parameter gradients
+ * are returned with respect to the coefficients in the chosen basis. */
+typedef enum {
+    MG_BASIS_MONOMIAL = 0,   /* Phi(x) = sum_k c_k G^k x (SAGEConv for K = 1) */
+    MG_BASIS_CHEBYSHEV = 1   /* Phi(x) = sum_k c_k T_k(-G) x: the ChebConv layer (Sec. 3.3) with the
+                                rescaled Laplacian 2 (I - G) / lambda_max - I, lambda_max = 2 */
+} mg_basis;
+
+typedef enum {
+    MG_AGG_MEAN = 0,         /* G = D_g^{-1} A_g, the neighbour mean (Sec. 3.3) */
+    MG_AGG_WEIGHTED = 1,     /* G = D_w^{-1} W, W_ij = |A_ij| on the graph of A (|G_ij| for a given
+                                graph, which then needs values); D_w = diag(sum_j W_ij): edge
+                                weights from matrix entries (Sec. 2.1) */
+    MG_AGG_SYM = 2           /* G = D_g^{-1/2} A_g D_g^{-1/2}, the symmetric normalisation of ChebConv */
+} mg_aggregation;
+
 typedef struct {
     int32_t KB, KR, KP;      /* orders of Phi_B, Phi_R, Phi_P (0..8) */
     int32_t nu_pre, nu_post; /* smoothing steps per level (0..8) */
     const double* values;
+    int32_t basis;           /* mg_basis of the coefficients c in values */
+    int32_t aggregation;     /* mg_aggregation: the graph operator G the convolutions use */
 } mg_params;
 
 enum {

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmgl.so")
 STATUS = {0: "MG_OK", 1: "MG_ERR_INVALID_ARG", 2: "MG_ERR_SHAPE", 3: "MG_ERR_OOM", 4: "MG_ERR_HIP",
           5: "MG_ERR_NOT_CONVERGED", 6: "MG_ERR_DIVERGED", 7: "MG_ERR_STATE", 8: "MG_ERR_UNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+BASES = {"monomial": 0, "chebyshev": 1}
+AGGREGATIONS = {"mean": 0, "weighted": 1, "sym": 2}
 FLAG_BACKWARD = 1
 FLAG_NO_TAIL = 2
 
@@ -54,7 +56,8 @@ class _Hier(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("KB", C.c_int32), ("KR", C.c_int32), ("KP", C.c_int32), ("nu_pre", C.c_int32),
-                ("nu_post", C.c_int32), ("values", C.POINTER(C.c_double))]
+                ("nu_post", C.c_int32), ("values", C.POINTER(C.c_double)), ("basis", C.c_int32),
+                ("aggregation", C.c_int32)]
 
 
 class _Options(C.Structure):
@@ -217,12 +220,16 @@ class Context:
     """A set-up learnable V-cycle on one GPU (wraps mg_ctx).
 
     A, P: lists of scipy sparse matrices (levels 0..J-1, 0 finest);
-    params: flat float64 parameter vector; precision: "fp64", "fp32" or "bf16".
+    params: flat float64 parameter vector; precision: "fp64", "fp32" or "bf16";
+    basis: "monomial" or "chebyshev" (meaning of the convolution coefficients);
+    aggregation: "mean", "weighted" (|a_ij| edge weights) or "sym" (symmetric
+    normalisation), the graph operator of the convolutions.
     """
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
-                 backward=False, device=None, stream=None, workspace=True, tail=True, native=None):
+                 backward=False, device=None, stream=None, workspace=True, tail=True, native=None,
+                 basis="monomial", aggregation="mean"):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -247,7 +254,9 @@ class Context:
         self._params = np.ascontiguousarray(params, dtype=np.float64)
         if self._params.size != self.nparams:
             raise ValueError(f"expected {self.nparams} parameters, got {self._params.size}")
-        self._p = _Params(KB, KR, KP, nu_pre, nu_post, self._params.ctypes.data_as(C.POINTER(C.c_double)))
+        self.basis, self.aggregation = basis, aggregation
+        self._p = _Params(KB, KR, KP, nu_pre, nu_post, self._params.ctypes.data_as(C.POINTER(C.c_double)),
+                          BASES[basis], AGGREGATIONS[aggregation])
         self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
                            (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL))
         ws, ck = C.c_size_t(), C.c_size_t()

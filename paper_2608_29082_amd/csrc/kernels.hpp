@@ -58,7 +58,10 @@ template <class C> struct Lvl {
   const C* invdiag;
   int wg;                   // ELL width of the graph
   const int* gcol;          // graph neighbours (padding col == i)
-  const C* invdeg;          // 1/|N(i)|, 0 for an isolated node
+  const C* invdeg;          // row scale r_i of the aggregation: 1/|N(i)| (0 for an isolated
+                            // node) for the mean, 1/sum_j w_ij for weighted, 1 for symmetric
+  const C* gval;            // edge weights w_ij in the graph's slots (padding 0), or null
+                            // for the unweighted mean
 };
 
 // Transfer operator (P, R or their transposes) in ELL form, padding val == 0.
@@ -185,26 +188,37 @@ __device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ c
 }
 
 // Neighbour sums over the graph (W multiple of 4, padding col == row):
-//   TRANS = false: s[r] += sum_{j in N(row)} y_j            ((M y) = invdeg_row * s)
-//   TRANS = true:  s[r] += sum_{j in N(row)} invdeg_j y_j   ((M^T y) = s, symmetric pattern)
-// The padding test uses the unclamped row (row0 + r under CONSEC).
-template <bool WIDE, bool CONSEC, int NR, bool TRANS, class C, class TY>
+//   TRANS = false: s[r] += sum_{j in N(row)} [w_{row,j}] y_j         ((G y) = r_row * s)
+//   TRANS = true:  s[r] += sum_{j in N(row)} [w_{row,j}] r_j y_j     ((G^T y) = s, symmetric
+//                                                                       pattern and weights)
+// with r the row scale (Lvl::invdeg) and the edge weights w (Lvl::gval) when
+// WG.  The padding test uses the unclamped row (row0 + r under CONSEC).
+template <bool WIDE, bool CONSEC, int NR, bool TRANS, bool WG, class C, class TY>
 __device__ __forceinline__ void graph_sum(const Lvl<C>& L, const int (&row)[NR], int row0, const TY* __restrict__ y,
                                           int B, int b, C (&s)[NR]) {
   for (int k = 0; k < L.wg; k += 4) {
     int j[NR][4];
+    C ew[NR][4];
     if constexpr (CONSEC && NR == 4) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const V4<int> jj = ld4(L.gcol + (size_t)(k + q) * L.ld + row0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) j[r][q] = uni<WIDE>(jj.v[r]);
+        if constexpr (WG) {
+          const V4<C> ww = ld4(L.gval + (size_t)(k + q) * L.ld + row0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ew[r][q] = uni<WIDE>(ww.v[r]);
+        }
       }
     } else {
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) j[r][q] = uni<WIDE>(L.gcol[(size_t)(k + q) * L.ld + row[r]]);
+        for (int q = 0; q < 4; ++q) {
+          j[r][q] = uni<WIDE>(L.gcol[(size_t)(k + q) * L.ld + row[r]]);
+          if constexpr (WG) ew[r][q] = uni<WIDE>(L.gval[(size_t)(k + q) * L.ld + row[r]]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -213,6 +227,7 @@ __device__ __forceinline__ void graph_sum(const Lvl<C>& L, const int (&row)[NR],
       for (int q = 0; q < 4; ++q) {
         C v = ldc<C>(y + (size_t)j[r][q] * B + b);
         if (TRANS) v *= uni<WIDE>(L.invdeg[j[r][q]]);
+        if constexpr (WG) v *= ew[r][q];
         s[r] += (j[r][q] != self) ? v : C(0);
       }
     }
@@ -279,7 +294,7 @@ __global__ __launch_bounds__(256) void k_resid(Lvl<C> L, int B, int lbs, const T
 // Horner hop v = a * (M yin)_i + c * x_i.
 //   mode 0: out = v (type TO)
 //   mode 1: out = (oz ? 0 : out) + scale * v
-template <int ROWS, bool WIDE, bool FINE, class C, class TY, class TX, class TO>
+template <int ROWS, bool WIDE, bool FINE, bool WG, class C, class TY, class TX, class TO>
 __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY* __restrict__ yin, C a,
                                              const TX* __restrict__ x, C c, TO* __restrict__ out, int mode, C scale,
                                              int oz) {
@@ -297,7 +312,7 @@ __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY*
       ov[r] = (mode == 1 && !oz) ? ldc<C>(out + o) : C(0);
       s[r] = C(0);
     }
-    graph_sum<WIDE, CS, ROWS, false>(L, t.row, t.row0, yin, B, b, s);
+    graph_sum<WIDE, CS, ROWS, false, WG>(L, t.row, t.row0, yin, B, b, s);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (!t.ok[r]) continue;
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(256) void k_axpy(int n, int B, int lbs, const TX* _
 //   mode 2: v = f_j - (A u)_j           (residual fused; uz: u == 0)
 // R's ELL width is a multiple of 4 (padding val == 0); the four fine rows of
 // a slot chunk are processed together.
-template <bool WIDE, class C, class TU, class TY, class TX>
+template <bool WIDE, bool WG, class C, class TU, class TY, class TX>
 __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, int lbs, int mode,
                                                   const TY* __restrict__ y, C a, const TX* __restrict__ x,
                                                   C c, const TU* __restrict__ f, const TU* __restrict__ u,
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, in
         C sm[4] = {C(0), C(0), C(0), C(0)}, xv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) xv[q] = ldc<C>(x + (size_t)jr[q] * B + b);
-        graph_sum<WIDE, false, 4, false>(L, jr, 0, y, B, b, sm);
+        graph_sum<WIDE, false, 4, false, WG>(L, jr, 0, y, B, b, sm);
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = a * (uni<WIDE>(L.invdeg[jr[q]]) * sm[q]) + c * xv[q];
       } else {
@@ -662,7 +677,7 @@ __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u
 }
 
 // out = a (M yin) + c x   (mode 0)   |   out = (oz ? 0 : out) + scale (a (M yin) + c x)   (mode 1)
-template <int CPB, class C>
+template <int CPB, bool WG, class C>
 __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const C* x, C cc, C* out, int mode,
                                        C scale, int oz) {
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
@@ -670,7 +685,9 @@ __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const
     C sm = C(0);
     for (int k = 0; k < L.wg; ++k) {
       const int j = L.gcol[(size_t)k * L.ld + i];
-      if (j != i) sm += yin[j * CPB + c];
+      C v = yin[j * CPB + c];
+      if constexpr (WG) v *= L.gval[(size_t)k * L.ld + i];
+      if (j != i) sm += v;
     }
     const C v = a * (L.invdeg[i] * sm) + cc * x[e];
     out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
@@ -694,7 +711,7 @@ __device__ __forceinline__ void tl_xfer(const Xfer<C>& X, const C* v, C* out, in
 }
 
 // u = (oz ? 0 : u) + scale * sum_k c_k M^k x  (Horner, as the per-level sweeps)
-template <int CPB, class C>
+template <int CPB, bool WG, class C>
 __device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, int K, const C* x, double scale, C* u,
                                             int oz, C* ya, C* yb) {
   if (K == 0) {
@@ -708,15 +725,15 @@ __device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, in
   C* buf[2] = {ya, yb};
   int cur = 0;
   for (int k = K - 1; k >= 1; --k) {
-    tl_hop<CPB>(L, yin, a, x, (C)c[k], buf[cur], 0, C(0), 0);
+    tl_hop<CPB, WG>(L, yin, a, x, (C)c[k], buf[cur], 0, C(0), 0);
     yin = buf[cur];
     cur ^= 1;
     a = C(1);
   }
-  tl_hop<CPB>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz);
+  tl_hop<CPB, WG>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz);
 }
 
-template <int CPB, class C, class TU>
+template <int CPB, bool WG, class C, class TU>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* __restrict__ fg,
                                                TU* __restrict__ eg) {
   extern __shared__ __align__(16) unsigned char tail_smem[];
@@ -742,7 +759,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
     int uz = 1;
     for (int j = 0; j < T.nu_pre; ++j) {
       tl_resid<CPB>(tl.L, f, u, uz, 1, s);
-      tl_conv_add<CPB>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb);
+      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb);
       uz = 0;
     }
     // r = f - A u (u may still be zero when nu_pre == 0), then y = Phi_R r, f_{l+1} = R y
@@ -751,7 +768,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
       for (int e = threadIdx.x; e < tl.L.n * CPB; e += blockDim.x) u[e] = C(0);
       __syncthreads();
     }
-    tl_conv_add<CPB>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb);
+    tl_conv_add<CPB, WG>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb);
     tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
   }
   // coarsest: u = A^{-1} f
@@ -775,10 +792,10 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
     C* u = sm + tl.off_u;
     const C* f = sm + tl.off_f;
     tl_xfer<CPB>(tl.P, sm + T.lv[q + 1].off_u, t, 0, C(1), 0);
-    tl_conv_add<CPB>(tl.L, cP, T.KP, t, 1.0, u, 0, ya, yb);
+    tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, u, 0, ya, yb);
     for (int j = 0; j < T.nu_post; ++j) {
       tl_resid<CPB>(tl.L, f, u, 0, 1, s);
-      tl_conv_add<CPB>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb);
+      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb);
     }
   }
   {
@@ -806,7 +823,7 @@ __device__ __forceinline__ void block_sum_store(double v, double* part, double* 
 //   zin == nullptr: z = zsrc (k = 0);  else z = M^T zin
 //   acc = (first ? 0 : acc) + c * z;  zout = z (if zout);  part <- sum(z * s)
 // Every work-item reaches the block sum (no early return).
-template <int ROWS, bool WIDE, class C, class TZ, class TS>
+template <int ROWS, bool WIDE, bool WG, class C, class TZ, class TS>
 __global__ __launch_bounds__(256) void k_hopT(Lvl<C> L, int B, int lbs, const TZ* __restrict__ zin,
                                               const TZ* __restrict__ zsrc, TZ* __restrict__ zout, C c,
                                               TZ* __restrict__ acc, int first, const TS* __restrict__ s,
@@ -823,7 +840,7 @@ __global__ __launch_bounds__(256) void k_hopT(Lvl<C> L, int B, int lbs, const TZ
       av[r] = first ? C(0) : ldc<C>(acc + o);
       sv[r] = ldc<C>(s + o);
     }
-    if (zin) graph_sum<WIDE, false, ROWS, true>(L, t.row, t.row0, zin, B, b, z);
+    if (zin) graph_sum<WIDE, false, ROWS, true, WG>(L, t.row, t.row0, zin, B, b, z);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (!t.ok[r]) continue;
@@ -912,6 +929,34 @@ __global__ void k_grad_combine(const double* __restrict__ dots, const int* __res
     } else {
       gl[2 + KB + 1 + KR + 1 + k] += e;
     }
+  }
+}
+
+// Power-series coefficients of the Chebyshev polynomials,
+// T_k(t) = sum_m t[k][m] t^m for k, m <= 8.
+struct ChebTab {
+  double t[9][9];
+};
+
+// Gradients with respect to Chebyshev coefficients from those with respect to
+// the power-series coefficients the cycle ran with:
+//   a_m = sum_k c_k (-1)^k T_k[m]   =>   dL/dc_k = (-1)^k sum_m T_k[m] dL/da_m
+// for every convolution of every level (one work-item per level).
+__global__ void k_cheb_grad(double* __restrict__ g, int L, int per, int KB, int KR, int KP, ChebTab T) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  double* gl = g + (size_t)l * per + 2;
+  const int Ks[3] = {KB, KR, KP};
+  for (int q = 0; q < 3; ++q) {
+    const int K = Ks[q];
+    double out[9];
+    for (int k = 0; k <= K; ++k) {
+      double v = 0.0;
+      for (int m = 0; m <= k; ++m) v += T.t[k][m] * gl[m];
+      out[k] = (k & 1) ? -v : v;
+    }
+    for (int k = 0; k <= K; ++k) gl[k] = out[k];
+    gl += K + 1;
   }
 }
 

@@ -60,6 +60,17 @@ mg_status fail(mg_status s, const std::string& m) {
   } while (0)
 
 #define MGL_UNPAREN(...) __VA_ARGS__
+// run `...` with the compile-time flag WGv = (the aggregation uses edge weights)
+#define WG_SPLIT(...)                      \
+  do {                                     \
+    if (wgt()) {                           \
+      constexpr bool WGv = true;           \
+      __VA_ARGS__;                         \
+    } else {                               \
+      constexpr bool WGv = false;          \
+      __VA_ARGS__;                         \
+    }                                      \
+  } while (0)
 // launch row-tile kernel KERN<ROWS, TARGS...> over the rows of level record D
 #define ROWS_LAUNCH(D, KERN, TARGS, ...)                                                                        \
   do {                                                                                                          \
@@ -108,7 +119,8 @@ struct HLevel {
   HEll off;            // off-diagonal nonzeros of A
   bool graph_is_A = true;
   HEll graph;          // only when a separate graph was given
-  std::vector<double> invdeg;
+  std::vector<double> invdeg;   // row scale of the aggregation operator
+  std::vector<double> gval;     // edge weights in the graph's slots (weighted / symmetric aggregation)
   bool sym_graph = false, sym_A = false;
 };
 
@@ -137,7 +149,7 @@ bool has_entry(const mg_csr* m, int i, int j, double* v) {
   return true;
 }
 
-mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
+mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int agg) {
   const int n = A->nrows;
   L.n = n;
   L.diag.assign(n, 0.0);
@@ -199,6 +211,34 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
   }
   L.invdeg.assign(n, 0.0);
   for (int i = 0; i < n; ++i) L.invdeg[i] = deg[i] > 0 ? 1.0 / deg[i] : 0.0;
+  // aggregation operator G = diag(r) W: weights in the graph's slots, r in invdeg
+  if (agg != MG_AGG_MEAN) {
+    const HEll& ge = L.graph_is_A ? L.off : L.graph;
+    L.gval.assign((size_t)ge.w * ge.ld, 0.0);
+    for (int i = 0; i < n; ++i) {
+      double rsum = 0.0;
+      for (int k = 0; k < ge.w; ++k) {
+        const int j = ge.col[(size_t)k * ge.ld + i];
+        if (j == i) continue;   // padding slot
+        double wv = 0.0;
+        if (agg == MG_AGG_WEIGHTED) {
+          if (L.graph_is_A) {
+            wv = std::fabs(L.off.val[(size_t)k * ge.ld + i]);
+          } else {
+            if (!G->val) return fail(MG_ERR_INVALID_ARG, "weighted aggregation over a given graph needs its values");
+            double gv = 0.0;
+            has_entry(G, i, j, &gv);
+            wv = std::fabs(gv);
+          }
+        } else {
+          wv = 1.0 / std::sqrt((double)deg[i] * (double)deg[j]);
+        }
+        L.gval[(size_t)k * ge.ld + i] = wv;
+        rsum += wv;
+      }
+      L.invdeg[i] = agg == MG_AGG_SYM ? 1.0 : (rsum > 0.0 ? 1.0 / rsum : 0.0);
+    }
+  }
   // symmetry of the graph and of A (needed by the reverse sweep)
   L.sym_A = true;
   for (int i = 0; i < n && L.sym_A; ++i)
@@ -216,8 +256,14 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l) {
   } else {
     L.sym_graph = true;
     for (int i = 0; i < n && L.sym_graph; ++i)
-      for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p)
-        if (G->col[p] != i && !has_entry(G, G->col[p], i, nullptr)) { L.sym_graph = false; break; }
+      for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p) {
+        double v = 0.0;
+        if (G->col[p] != i && (!has_entry(G, G->col[p], i, &v) ||
+                               (agg == MG_AGG_WEIGHTED && G->val && std::fabs(v) != std::fabs(G->val[p])))) {
+          L.sym_graph = false;
+          break;
+        }
+      }
   }
   return MG_OK;
 }
@@ -265,15 +311,44 @@ HEll ell_transpose(const mg_csr* m, int mult) {
 
 struct HostPlan {
   int J = 0, B = 1, prec = 0, KB = 0, KR = 0, KP = 0, nu_pre = 0, nu_post = 0, flags = 0;
+  int basis = MG_BASIS_MONOMIAL, agg = MG_AGG_MEAN;
   int max_outer = 1, check_every = 1;
   double rtol = 1e-8, divf = 1e6;
   std::vector<HLevel> lv;
   std::vector<HEll> P, R, PT, RT;
   bool R_is_PT = true;
   std::vector<double> Acoarse;   // dense n_J x n_J row-major
-  std::vector<double> params;
+  std::vector<double> params;   // power-series coefficients (converted from the caller's basis)
   bool sym_all = true;
 };
+
+// Coefficients of the Chebyshev polynomials, T_k(t) = sum_m t[k][m] t^m, k, m <= 8.
+ChebTab cheb_table() {
+  ChebTab c{};
+  c.t[0][0] = 1.0;
+  c.t[1][1] = 1.0;
+  for (int k = 1; k < 8; ++k)
+    for (int m = 0; m <= 8; ++m) c.t[k + 1][m] = (m > 0 ? 2.0 * c.t[k][m - 1] : 0.0) - c.t[k - 1][m];
+  return c;
+}
+
+// Parameters in the caller's basis -> power-series coefficients of each
+// convolution in G: sum_k c_k T_k(-G) = sum_m a_m G^m, a_m = sum_k c_k (-1)^k T_k[m].
+void to_power_series(std::vector<double>& v, int J, int KB, int KR, int KP, int basis) {
+  if (basis != MG_BASIS_CHEBYSHEV) return;
+  const ChebTab T = cheb_table();
+  const int per = 2 + (KB + 1) + (KR + 1) + (KP + 1);
+  for (int l = 0; l + 1 < J; ++l) {
+    int off = l * per + 2;
+    for (int K : {KB, KR, KP}) {
+      double a[9] = {};
+      for (int m = 0; m <= K; ++m)
+        for (int k = m; k <= K; ++k) a[m] += v[off + k] * ((k & 1) ? -1.0 : 1.0) * T.t[k][m];
+      for (int m = 0; m <= K; ++m) v[off + m] = a[m];
+      off += K + 1;
+    }
+  }
+}
 
 int64_t num_params(int J, int KB, int KR, int KP) { return (int64_t)(J - 1) * (2 + (KB + 1) + (KR + 1) + (KP + 1)); }
 
@@ -291,6 +366,11 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
   const int J = h->nlevels;
   pl.J = J; pl.B = o->nrhs; pl.prec = o->precision; pl.KB = p->KB; pl.KR = p->KR; pl.KP = p->KP;
   pl.nu_pre = p->nu_pre; pl.nu_post = p->nu_post; pl.flags = o->flags;
+  if (p->basis < MG_BASIS_MONOMIAL || p->basis > MG_BASIS_CHEBYSHEV) return fail(MG_ERR_INVALID_ARG, "unknown basis");
+  if (p->aggregation < MG_AGG_MEAN || p->aggregation > MG_AGG_SYM)
+    return fail(MG_ERR_INVALID_ARG, "unknown aggregation");
+  pl.basis = p->basis;
+  pl.agg = p->aggregation;
   pl.max_outer = o->max_outer; pl.check_every = o->check_every; pl.rtol = o->rtol; pl.divf = o->diverge_factor;
   for (int l = 0; l < J; ++l) {
     MG_TRY(check_csr(&h->A[l], "A", l));
@@ -319,10 +399,11 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
   pl.params.assign(p->values, p->values + np);
   for (double v : pl.params)
     if (!std::isfinite(v)) return fail(MG_ERR_INVALID_ARG, "non-finite parameter");
+  to_power_series(pl.params, J, p->KB, p->KR, p->KP, p->basis);
   pl.lv.resize(J);
   for (int l = 0; l < J; ++l) {
     if (full) {
-      MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l));
+      MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l, p->aggregation));
       pl.sym_all = pl.sym_all && pl.lv[l].sym_A && pl.lv[l].sym_graph;
     } else {
       // sizes only: widths from row counts
@@ -527,6 +608,7 @@ struct Engine final : EngineBase {
   }
 
   bool bwd() const { return (pl.flags & MG_FLAG_BACKWARD) != 0; }
+  bool wgt() const { return pl.agg != MG_AGG_MEAN; }
   int per() const { return 2 + (pl.KB + 1) + (pl.KR + 1) + (pl.KP + 1); }
   double theta(int l) const { return pl.params[(size_t)l * per()]; }
   double eta(int l) const { return pl.params[(size_t)l * per() + 1]; }
@@ -586,6 +668,7 @@ struct Engine final : EngineBase {
         x.L.wg = H.graph.w;
         x.L.gcol = bp.take<int>((size_t)H.graph.w * ld);
       }
+      x.L.gval = pl.agg != MG_AGG_MEAN ? bp.take<C>((size_t)x.L.wg * ld) : nullptr;
       const size_t nv = (size_t)n * B;
       if (l > 0) { x.f = bp.take<TU>(nv); x.u = bp.take<TU>(nv); }
       x.s = bp.take<TH>(nv); x.ya = bp.take<TH>(nv); x.yb = bp.take<TH>(nv); x.x = bp.take<TH>(nv);
@@ -618,6 +701,7 @@ struct Engine final : EngineBase {
       L64.diag = bp.take<double>(d[0].L.ld);
       L64.invdiag = nullptr;
       L64.invdeg = nullptr;
+      L64.gval = nullptr;
     }
     const int nJ = pl.lv[J - 1].n;
     Ainv = bp.take<double>((size_t)nJ * nJ);
@@ -712,6 +796,7 @@ struct Engine final : EngineBase {
       MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
       MG_TRY(up(const_cast<C*>(x.L.invdeg), ideg, st));
       if (!H.graph_is_A) MG_TRY(upi(x.L.gcol, H.graph.col, st));
+      if (x.L.gval) MG_TRY(up(const_cast<C*>(x.L.gval), H.gval, st));
     }
     for (int l = 0; l + 1 < J; ++l) {
       DL& x = d[l];
@@ -784,9 +869,11 @@ struct Engine final : EngineBase {
     for (int lt = 0; lt <= J - 2; ++lt)
       if (J - lt <= kTailMaxLevels && bytes_from(lt) <= (size_t)maxlds) { tail_lt = lt; break; }
     if (tail_lt < 0) return MG_OK;
+    const void* tail_fn = wgt() ? reinterpret_cast<const void*>(&k_tail<1, true, C, TU>)
+                                : reinterpret_cast<const void*>(&k_tail<1, false, C, TU>);
     if (bytes_from(tail_lt) > 65536 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<1, C, TU>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_from(tail_lt)) != hipSuccess) {
+        hipFuncSetAttribute(tail_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_from(tail_lt)) !=
+            hipSuccess) {
       (void)hipGetLastError();
       tail_lt = -1;   // large dynamic LDS unavailable: keep the per-level sweeps
       return MG_OK;
@@ -822,7 +909,8 @@ struct Engine final : EngineBase {
   // e = LMG(A_l, f, 0) for levels l .. J-1 in one launch (l >= tail_lt)
   mg_status run_tail(int l, const TU* f, TU* e, hipStream_t st) {
     const int q = l - tail_lt;
-    hipLaunchKernelGGL((k_tail<1, C, TU>), dim3(B()), dim3(1024), tail_bytes[q], st, tails[q], B(), f, e);
+    WG_SPLIT(hipLaunchKernelGGL((k_tail<1, WGv, C, TU>), dim3(B()), dim3(1024), tail_bytes[q], st, tails[q], B(),
+                                f, e));
     LAUNCH_OK();
     return MG_OK;
   }
@@ -831,6 +919,7 @@ struct Engine final : EngineBase {
     for (size_t i = 0; i < pl.params.size(); ++i)
       if (!std::isfinite(v[i])) return fail(MG_ERR_INVALID_ARG, "non-finite parameter");
     pl.params.assign(v, v + pl.params.size());
+    to_power_series(pl.params, pl.J, pl.KB, pl.KR, pl.KP, pl.basis);
     HIP_TRY(hipMemcpyAsync(dprm, pl.params.data(), pl.params.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MG_OK;
@@ -845,10 +934,10 @@ struct Engine final : EngineBase {
     const DL& D = d[l];
     const double nB = (double)D.L.n * B();
     const double bytes = nB * (sizeof(TY) + sizeof(TX) + sizeof(TO) * (mode ? 2 : 1)) +
-                         (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C);
+                         (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C);
     TIMED(MG_KF_HOP, bytes,
-          ROWS_LAUNCH_F(D, l == 0, k_hop, (C, TY, TX, TO), D.L, B(), lbs, yin, (C)a, x,
-                             (C)c, out, mode, (C)scale, oz));
+          WG_SPLIT(ROWS_LAUNCH_F(D, l == 0, k_hop, (WGv, C, TY, TX, TO), D.L, B(), lbs, yin, (C)a, x,
+                                 (C)c, out, mode, (C)scale, oz)));
     return MG_OK;
   }
 
@@ -897,7 +986,7 @@ struct Engine final : EngineBase {
     if (K == 0) {
       TIMED(MG_KF_RESTRICT, nB(l) * sizeof(TU) * (uz ? 1 : 2) + (uz ? 0.0 : bytes_A(l)) + bytes_X(D.R) +
                                 nB(l + 1) * sizeof(TU),
-            RESTRICT_LAUNCH(cb, (C, TU, TU, TU), D.R, D.L, B(), lbs, 2,
+            RESTRICT_LAUNCH(cb, (false, C, TU, TU, TU), D.R, D.L, B(), lbs, 2,
                                (const TU*)nullptr, (C)0, (const TU*)nullptr, (C)0, f, u, uz, (C)c[0], rc));
       return MG_OK;
     }
@@ -908,9 +997,9 @@ struct Engine final : EngineBase {
                           bytes_X(D.R) + nB(l + 1) * sizeof(TU);
     if (K == 1) {
       TIMED(MG_KF_RESTRICT, rbytes,
-            RESTRICT_LAUNCH(cb, (C, TU, TU, TU), D.R, D.L, B(), lbs, 1,
+            WG_SPLIT(RESTRICT_LAUNCH(cb, (WGv, C, TU, TU, TU), D.R, D.L, B(), lbs, 1,
                                (const TU*)D.r, (C)c[1], (const TU*)D.r, (C)c[0], (const TU*)nullptr,
-                               (const TU*)nullptr, 0, (C)1, rc));
+                               (const TU*)nullptr, 0, (C)1, rc)));
       return MG_OK;
     }
     MG_TRY(hop<TU, TU, TH>(l, D.r, c[K], D.r, c[K - 1], D.ya, 0, 0.0, 0, st));
@@ -923,8 +1012,8 @@ struct Engine final : EngineBase {
       cur ^= 1;
     }
     TIMED(MG_KF_RESTRICT, rbytes - nB(l) * (sizeof(TU) - sizeof(TH)),
-          RESTRICT_LAUNCH(cb, (C, TU, TH, TU), D.R, D.L, B(), lbs, 1, y,
-                             (C)1, (const TU*)D.r, (C)c[0], (const TU*)nullptr, (const TU*)nullptr, 0, (C)1, rc));
+          WG_SPLIT(RESTRICT_LAUNCH(cb, (WGv, C, TU, TH, TU), D.R, D.L, B(), lbs, 1, y,
+                             (C)1, (const TU*)D.r, (C)c[0], (const TU*)nullptr, (const TU*)nullptr, 0, (C)1, rc)));
     return MG_OK;
   }
 
@@ -1367,11 +1456,11 @@ struct Engine final : EngineBase {
       const TU* zin = k == 0 ? nullptr : zprev;
       const TU* zsrc = k == 0 ? src : nullptr;
       if (sdot_is_TH)
-        ROWS_LAUNCH(D, k_hopT, (C, TU, TH), D.L, B(), lbs, zin, zsrc, zout,
-                           (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TH*>(sdot), pp);
+        WG_SPLIT(ROWS_LAUNCH(D, k_hopT, (WGv, C, TU, TH), D.L, B(), lbs, zin, zsrc, zout,
+                             (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TH*>(sdot), pp));
       else
-        ROWS_LAUNCH(D, k_hopT, (C, TU, TU), D.L, B(), lbs, zin, zsrc, zout,
-                           (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TU*>(sdot), pp);
+        WG_SPLIT(ROWS_LAUNCH(D, k_hopT, (WGv, C, TU, TU), D.L, B(), lbs, zin, zsrc, zout,
+                             (C)c[k], D.acc, k == 0 ? 1 : 0, static_cast<const TU*>(sdot), pp));
       LAUNCH_OK();
       ++slot;
       if (zout) {
@@ -1460,6 +1549,11 @@ struct Engine final : EngineBase {
     hipLaunchKernelGGL(k_grad_combine, dim3(1), dim3(1), 0, st, dots, ddesc, nslots, dprm, per(), pl.KB, pl.KR, gp,
                        (int)pl.params.size());
     LAUNCH_OK();
+    if (pl.basis == MG_BASIS_CHEBYSHEV) {
+      hipLaunchKernelGGL(k_cheb_grad, dim3(1), dim3(64), 0, st, gp, pl.J - 1, per(), pl.KB, pl.KR, pl.KP,
+                         cheb_table());
+      LAUNCH_OK();
+    }
     return MG_OK;
   }
 
