@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the convolution-variant and Darcy sections")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length of the Krylov comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=60,
@@ -181,6 +182,10 @@ def main():
     elif not args.no_krylov:
         out["krylov"] = krylov(args, {"learned_" + args.precision: ctx}, f, w, h, B)
 
+    if not args.no_variants:
+        out["conv_variants"] = conv_variants(args, h, f, B, stream)
+        out["darcy"] = darcy(args)
+
     if args.serving_requests > 0:
         out["serving"] = serving(args)
 
@@ -222,6 +227,74 @@ def krylov(args, ctxs, f, w, h, B):
                                    "converged": bool(ok),
                                    "gram_schmidt_ms": kms, "gram_schmidt_GBps": kby / (kms * 1e-3) / 1e9 if kms else 0.0}
             print(f"# fgmres {name} {pc}: {out[f'{name}_{pc}']}", file=sys.stderr, flush=True)
+    return out
+
+
+def conv_variants(args, h, f, B, stream):
+    """Per-cycle cost of the convolution variants on the same hierarchy and
+    right-hand sides (identity parameters, so every variant runs the same
+    number of hops): ms per refinement step and the finest-level hop's
+    achieved bandwidth (algorithmic bytes over HIP-event time)."""
+    import torch
+    from paper_2608_29082_amd import binding as Bd
+    from paper_2608_29082_amd import params as PR
+    J = h.nlevels
+    out = {}
+    for agg, basis in (("mean", "monomial"), ("weighted", "monomial"), ("sym", "chebyshev")):
+        ctx = Bd.Context(h.A, h.P, PR.identity(J, args.K, args.K, args.K), args.K, args.K, args.K,
+                         precision=args.precision, nrhs=B, stream=stream, basis=basis, aggregation=agg)
+        u = torch.zeros_like(f)
+        ctx.refine_step(f, u, u)
+        ctx.timing_start("hop", 0)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(10):
+            ctx.refine_step(f, u, u)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        n, ms, by = ctx.timing_read()
+        ctx.close()
+        out[f"{agg}_{basis}"] = {"ms_per_cycle": 1e2 * (tb - ta), "hop_level0_GBps": by / (ms * 1e-3) / 1e9,
+                                 "hop_level0_us": 1e3 * ms / max(n, 1)}
+        print(f"# variant {agg}/{basis}: {out[f'{agg}_{basis}']}", file=sys.stderr, flush=True)
+    return out
+
+
+def darcy(args):
+    """Darcy pressure equation of Sec. 4.1 (100 x 100 cells, 1e-6 inclusion,
+    piecewise constant interpolation, 7 levels, V(4,4), 8 seeded random
+    starts, FP32 cycles in FP64 refinement to 1e-8): the classical cycle and
+    the shipped LMG-RP / LMG-RPS parameters."""
+    import torch
+    from mginputs import configs as C
+    from paper_2608_29082_amd import binding as Bd
+    from paper_2608_29082_amd import params as PR
+    w, u0 = C.darcy_inclusion(B=8)
+    h = w.hier
+    J = h.nlevels
+    f = torch.tensor(w.f, dtype=torch.float64, device="cuda")
+    out = {"workload": "darcy-100: 10000 cells, 7 levels, 1e-6 inclusion, 8 random starts"}
+    sets = {"classical": PR.identity(J, 3, 3, 3)}
+    for v in ("rp", "rps"):
+        pf = PR.default_file(f"darcy-100-{v}", 3)
+        if pf:
+            sets[f"lmg_{v}"] = PR.load(pf)[0]
+    for name, theta in sets.items():
+        ctx = Bd.Context(h.A, h.P, theta, 3, 3, 3, nu_pre=4, nu_post=4, precision="fp32", nrhs=8, max_outer=5000)
+        u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        ctx.solve(f, u)
+        u.copy_(torch.tensor(u0, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        info = ctx.solve(f, u)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        rr = np.linalg.norm(w.f - h.A[0] @ u.cpu().numpy(), axis=0) / np.linalg.norm(w.f, axis=0)
+        ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+        out[name] = {"solves_per_s": 8 / (tb - ta) if ok else 0.0, "cycles_max": int(info.iters.max()),
+                     "ms": 1e3 * (tb - ta), "relres_max_fp64_host": float(rr.max()), "converged": bool(ok)}
+        ctx.close()
+        print(f"# darcy {name}: {out[name]}", file=sys.stderr, flush=True)
     return out
 
 

@@ -526,7 +526,8 @@ struct EngineBase {
   }
   // record one event of the pair for launch family `fam`; returns false when not timed
   mg_status tmark(int fam, int level, bool stop, double bytes, hipStream_t st) {
-    if (fam != tfam || tfam == MG_KF_NONE || (tlevel >= 0 && level != tlevel)) return MG_OK;
+    // level -2 marks launches that are never timed (their work is data-dependent)
+    if (fam != tfam || tfam == MG_KF_NONE || level < -1 || (tlevel >= 0 && level != tlevel)) return MG_OK;
     const size_t k = 2 * tn + (stop ? 1 : 0);
     while (tev.size() <= k) {
       hipEvent_t e;
@@ -933,7 +934,7 @@ struct Engine final : EngineBase {
                 hipStream_t st) {
     const DL& D = d[l];
     const double nB = (double)D.L.n * B();
-    const double bytes = nB * (sizeof(TY) + sizeof(TX) + sizeof(TO) * (mode ? 2 : 1)) +
+    const double bytes = nB * (sizeof(TY) + sizeof(TX) + sizeof(TO) * ((mode && !oz) ? 2 : 1)) +
                          (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C);
     TIMED(MG_KF_HOP, bytes,
           WG_SPLIT(ROWS_LAUNCH_F(D, l == 0, k_hop, (WGv, C, TY, TX, TO), D.L, B(), lbs, yin, (C)a, x,
@@ -1295,7 +1296,7 @@ struct Engine final : EngineBase {
   }
   // out[0..nv) = <w, v_t>, out[nv] = ||w||^2 (per column; zero when skipped)
   mg_status kr_dot(const Kr& k, int nv, const double* w, long wrs, double* out, const int* skip, hipStream_t st) {
-    const int l = 0;
+    const int l = skip ? -2 : 0;
     TIMED(MG_KF_KRYLOV, nB(0) * 8.0 * (nv + 1), kr_ng(nv, [&](auto ng) {
             kr_dot_ng<decltype(ng)::value>(k, nv, w, wrs, skip, st);
           }));
@@ -1306,9 +1307,10 @@ struct Engine final : EngineBase {
   }
   // wo = wi - sum_t h_t v_t, r0 = fl(wo); dots: out[0..nv) = <wo, v_t>, out[nv] = ||wo||^2,
   // else out[0] = ||wo||^2 (zero when skipped)
+  // (the conditional second pass is not timed: whether it ran is known only on the device)
   mg_status kr_upd(const Kr& k, int nv, const double* h, const double* wi, long wis, double* wo, long wos,
                    bool dots, double* out, const int* skip, hipStream_t st) {
-    const int l = 0;
+    const int l = skip ? -2 : 0;
     TIMED(MG_KF_KRYLOV, nB(0) * (8.0 * (nv + 2) + sizeof(TU)), kr_ng(nv, [&](auto ng) {
             constexpr int NG = decltype(ng)::value;
             if constexpr (NG <= kKrFuse) {
