@@ -317,7 +317,9 @@ def serving(args):
     """Request loop over the serving stream (sides 65..1025, log10 a ~ U(-2, 2)
     on 16 x 16 blocks, f ~ N(0, 1), per-size trained FP32 parameters, FP64
     refinement to 1e-8): closed loop to find the saturated rate T, then Poisson
-    arrivals at 0.5 T and 0.8 T.  Latency = done - arrival, setup included."""
+    arrivals at 0.5 T and 0.8 T; then the same with flexible GMRES(30) around
+    the learned cycle (closed loop and 0.5 T).  Latency = done - arrival, setup
+    included."""
     from paper_2608_29082_amd import params as PR
     from paper_2608_29082_amd import serve as S
     theta = {}
@@ -335,6 +337,14 @@ def serving(args):
         reqs = S.make_stream(args.serving_requests, frac * T, seed=12)
         res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8).run(reqs, open_loop=True)
         runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T)
+    # the same streams with flexible GMRES around the learned cycle (Sec. 4.2)
+    reqs = S.make_stream(args.serving_requests, 0.0, seed=11)
+    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, solver="fgmres").run(reqs, open_loop=False)
+    runs["fgmres_closed_loop"] = S.summarize(res, wall)
+    Tf = runs["fgmres_closed_loop"]["solves_per_s"]
+    reqs = S.make_stream(args.serving_requests, 0.5 * Tf, seed=12)
+    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, solver="fgmres").run(reqs, open_loop=True)
+    runs["fgmres_open_loop_0.5T"] = dict(S.summarize(res, wall), qps=0.5 * Tf)
     for r in runs.values():
         r.pop("by_side", None)
     print(f"# serving: {json.dumps(runs)}", file=sys.stderr, flush=True)

@@ -7,8 +7,10 @@ A request is (side, coefficient blocks, right-hand side).  The loop:
      of the HBM budget to be free (admission by footprint), then set the
      context up (mg_setup) on their own stream;
   2. solve slots (threads, one HIP stream each) take admitted requests in
-     arrival order and run mg_solve (FP32 or BF16 cycles, FP64 refinement);
-     the slots' kernels overlap on the GPU;
+     arrival order and run mg_solve (FP32 or BF16 cycles, FP64 refinement) or,
+     with solver="fgmres", mg_fgmres (flexible GMRES with the cycle as
+     preconditioner, Sec. 4.2; its Krylov workspace is part of the request's
+     footprint); the slots' kernels overlap on the GPU;
   3. a finished request releases its context and its budget; latency is
      done - arrival.
 Requests that arrive while others run are admitted as budget and slots free
@@ -81,7 +83,8 @@ class Server:
     is solved again with the classical parameters (counted in `fallbacks`)."""
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", slots=4, setup_threads=4,
-                 hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0"):
+                 hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0",
+                 solver="refine", restart=30):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -93,6 +96,9 @@ class Server:
         self.device = torch.device(device)
         self.peak_used = 0
         self.fallbacks = 0
+        if solver not in ("refine", "fgmres"):
+            raise ValueError("solver must be 'refine' or 'fgmres'")
+        self.solver, self.restart = solver, restart
 
     def _params(self, J, side):
         K = self.K
@@ -115,7 +121,7 @@ class Server:
         ws, ck = Cc.c_size_t(), Cc.c_size_t()
         Bd._check(lib.mg_workspace_bytes(Cc.byref(hier.view), Cc.byref(pr), Cc.byref(o), Cc.byref(ws),
                                          Cc.byref(ck)), "mg_workspace_bytes")
-        return int(ws.value) + 2 * n * 8
+        return int(ws.value) + 2 * n * 8 + (krylov_bytes_bound(n, 1, self.restart) if self.solver == "fgmres" else 0)
 
     def run(self, requests, open_loop=True):
         """Serve `requests` (sorted by arrival).  open_loop: each request enters
@@ -149,9 +155,15 @@ class Server:
                                          nrhs=1, max_outer=self.max_outer, check_every=10, rtol=self.rtol,
                                          stream=stream, device=self.device, native=hier)
                         f = torch.tensor(req.f, dtype=torch.float64, device=self.device)
+                        work = None
+                        if self.solver == "fgmres":
+                            kb = ctx.fgmres_workspace_bytes(self.restart)
+                            if kb > krylov_bytes_bound(hier.sizes[0], 1, self.restart):
+                                raise RuntimeError("Krylov workspace exceeds its admission bound")
+                            work = torch.empty(kb, dtype=torch.uint8, device=self.device)
                     stream.synchronize()
                     hier.close()
-                    ready.put((t_arr, req.rid, (req, ctx, f, fp, t_arr, t_adm)))
+                    ready.put((t_arr, req.rid, (req, ctx, f, fp, t_arr, t_adm, work)))
                 except Exception as e:  # report and keep serving
                     with lock:
                         errors.append((req.rid, repr(e)))
@@ -167,24 +179,26 @@ class Server:
                     with lock:
                         results.append(None)
                     continue
-                req, ctx, f, fp, t_arr, t_adm = job
+                req, ctx, f, fp, t_arr, t_adm, work = job
                 t_start = now()
                 ctx.stream = stream
                 with torch.cuda.stream(stream):
                     u = torch.zeros_like(f)
-                    info = ctx.solve(f, u)
-                    if info.status[0] == 6 and self.theta is not None:
-                        # learned parameters diverged on this request: classical cycle
+                    run = (lambda: ctx.fgmres(f, u, restart=self.restart, max_iter=self.max_outer, rtol=self.rtol,
+                                              work=work)) if self.solver == "fgmres" else (lambda: ctx.solve(f, u))
+                    info = run()
+                    if info.status[0] != 0 and self.theta is not None:
+                        # learned parameters failed on this request: classical cycle
                         ctx.set_params(self.PR.identity(ctx.J, self.K, self.K, self.K))
                         u.zero_()
-                        info = ctx.solve(f, u)
+                        info = run()
                         with lock:
                             self.fallbacks += 1
                     u_host = u.cpu().numpy() if self.keep else None
                 stream.synchronize()
                 t_done = now()
                 ctx.close()
-                del ctx, f, u
+                del ctx, f, u, work
                 self.budget.release(fp)
                 with lock:
                     results.append(Result(req.rid, req.side, req.f.shape[0], int(info.iters[0]),
@@ -213,6 +227,16 @@ class Server:
         wall = now()
         done = [r for r in results if r is not None]
         return done, errors, wall
+
+
+def krylov_bytes_bound(n: int, B: int, m: int) -> int:
+    """Upper bound of mg_fgmres_workspace_bytes for n unknowns, B columns and
+    restart m: (m+1) FP64 basis vectors, m preconditioned vectors (counted at
+    8 bytes), one FP64 vector, per-block partial sums for at most 1024 blocks
+    and the per-column Hessenberg state, plus alignment padding."""
+    nB = n * B
+    return (nB * ((m + 1) * 8 + m * 8 + 8) + 128 * m * 8
+            + B * 8 * (1024 * (m + 2) + (m + 1) * m + 10 * (m + 2)) + (1 << 16))
 
 
 def summarize(results, wall):
@@ -263,6 +287,8 @@ def main(argv=None):
     ap.add_argument("--sides", default=None, help="comma-separated grid sides")
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--solver", default="refine", choices=["refine", "fgmres"])
+    ap.add_argument("--restart", type=int, default=30)
     args = ap.parse_args(argv)
     path = None
     if args.params == "identity":
@@ -282,10 +308,10 @@ def main(argv=None):
     sides = [int(s) for s in args.sides.split(",")] if args.sides else None
     reqs = make_stream(args.requests, args.qps, args.seed, sides)
     srv = Server(theta, J_src, precision=args.precision, slots=args.slots, setup_threads=args.setup_threads,
-                 hbm_budget=int(args.budget_gb * (1 << 30)))
+                 hbm_budget=int(args.budget_gb * (1 << 30)), solver=args.solver, restart=args.restart)
     res, errs, wall = srv.run(reqs, open_loop=args.qps > 0)
     out = summarize(res, wall)
-    out.update({"qps": args.qps, "wall_s": wall, "errors": errs[:5], "peak_budget_bytes": srv.peak_used,
+    out.update({"solver": args.solver, "qps": args.qps, "wall_s": wall, "errors": errs[:5], "peak_budget_bytes": srv.peak_used,
                 "fallbacks": srv.fallbacks, "params": os.path.basename(path) if path else "identity"})
     print(json.dumps(out), flush=True)
 

@@ -58,3 +58,25 @@ def test_admission_respects_budget():
     for r in res2:
         held = sum(x.footprint for x in res2 if x.t_admitted <= r.t_admitted < x.t_done)
         assert held <= biggest
+
+
+def test_fgmres_serving_converges_and_is_invariant():
+    """solver="fgmres": every request reaches 1e-8 in far fewer
+    preconditioner calls than stationary cycles, the Krylov workspace stays
+    within its admission bound, and results are the same alone and mixed."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(8, 0.0, seed=5, sides=(33, 65, 129))
+    srv = _server(slots=3, setup_threads=3, solver="fgmres")
+    res, errs, wall = srv.run(reqs, open_loop=False)
+    assert not errs and len(res) == len(reqs)
+    ref, _, _ = _server(slots=3, setup_threads=3).run(reqs, open_loop=False)
+    iters_ref = {r.rid: r.iters for r in ref}
+    byid = {r.rid: r for r in res}
+    for q in reqs:
+        r = byid[q.rid]
+        assert r.status == 0 and _relres(q, r.u) <= 1e-8 * (1 + 1e-3), (q.side, r.relres)
+        assert r.iters < iters_ref[q.rid]
+    for q in reqs[:3]:
+        alone, e2, _ = _server(slots=1, setup_threads=1, solver="fgmres").run([q], open_loop=False)
+        assert not e2 and alone[0].iters == byid[q.rid].iters
+        assert np.array_equal(alone[0].u, byid[q.rid].u)
