@@ -527,15 +527,21 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
       ok[r] = rr < hi;
       row[r] = ok[r] ? (int)rr : (int)(hi - 1);
     }
+    // WIDE: the four rows are i0 .. i0+3 (i0 a multiple of 4, rows past the
+    // chunk computed but not stored), so each slot's indices and values and
+    // the diagonal are one 16-byte scalar load per row quadruple
+    const int r0 = uni<WIDE>((int)i0);
+    double dg[4];
+    row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
       double fv[4], s[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         fv[r] = f[(size_t)row[r] * B + b];
-        s[r] = uni<WIDE>(L.diag[row[r]]) * u[(size_t)row[r] * B + b];
+        s[r] = dg[r] * u[(size_t)row[r] * B + b];
       }
-      ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, row, 0, u, B, b, s);
+      ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (!ok[r]) continue;
@@ -733,30 +739,34 @@ __device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, in
   tl_hop<CPB, WG>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz);
 }
 
-template <int CPB, bool WG, class C, class TU>
-__global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* __restrict__ fg,
-                                               TU* __restrict__ eg) {
-  extern __shared__ __align__(16) unsigned char tail_smem[];
-  C* sm = reinterpret_cast<C*>(tail_smem);
-  const int col0 = blockIdx.x * CPB;
-  // load the first tail level's right-hand side for this workgroup's columns
-  {
-    const TailLevel<C>& t0 = T.lv[0];
-    for (int e = threadIdx.x; e < t0.L.n * CPB; e += blockDim.x) {
-      const int i = e / CPB, c = e - i * CPB;
-      sm[t0.off_f + e] = (col0 + c < B) ? (C)fg[(size_t)i * B + col0 + c] : C(0);
-    }
-    __syncthreads();
+// the coarsest tail level: u = A^{-1} f (FP64 accumulation)
+template <int CPB, class C>
+__device__ __forceinline__ void tl_coarse(const TailArgs<C>& T, C* sm) {
+  const TailLevel<C>& tl = T.lv[T.nl - 1];
+  const C* f = sm + tl.off_f;
+  C* u = sm + tl.off_u;
+  for (int e = threadIdx.x; e < T.nJ * CPB; e += blockDim.x) {
+    const int i = e / CPB, c = e - i * CPB;
+    double acc = 0.0;
+    for (int j = 0; j < T.nJ; ++j) acc += T.Ainv[(size_t)i * T.nJ + j] * (double)f[j * CPB + c];
+    u[e] = (C)acc;
   }
+  __syncthreads();
+}
+
+// One learnable cycle over tail levels q0 .. nl-1 in LDS: u_q0 <- LMG(f_q0, u_q0)
+// (uz0: u_q0 is logically zero on entry; deeper levels always start from zero).
+template <int CPB, bool WG, class C>
+__device__ __forceinline__ void tl_cycle(const TailArgs<C>& T, C* sm, int q0, int uz0) {
   C *s = sm + T.off_s, *ya = sm + T.off_ya, *yb = sm + T.off_yb, *t = sm + T.off_t;
   // down: pre-smoothing and restriction
-  for (int q = 0; q + 1 < T.nl; ++q) {
+  for (int q = q0; q + 1 < T.nl; ++q) {
     const TailLevel<C>& tl = T.lv[q];
     const double* p = T.prm + (size_t)q * T.per;
     const double *cB = p + 2, *cR = cB + T.KB + 1;
     C* u = sm + tl.off_u;
     const C* f = sm + tl.off_f;
-    int uz = 1;
+    int uz = q == q0 ? uz0 : 1;
     for (int j = 0; j < T.nu_pre; ++j) {
       tl_resid<CPB>(tl.L, f, u, uz, 1, s);
       tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb);
@@ -771,21 +781,9 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
     tl_conv_add<CPB, WG>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb);
     tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
   }
-  // coarsest: u = A^{-1} f
-  {
-    const TailLevel<C>& tl = T.lv[T.nl - 1];
-    const C* f = sm + tl.off_f;
-    C* u = sm + tl.off_u;
-    for (int e = threadIdx.x; e < T.nJ * CPB; e += blockDim.x) {
-      const int i = e / CPB, c = e - i * CPB;
-      double acc = 0.0;
-      for (int j = 0; j < T.nJ; ++j) acc += T.Ainv[(size_t)i * T.nJ + j] * (double)f[j * CPB + c];
-      u[e] = (C)acc;
-    }
-    __syncthreads();
-  }
+  tl_coarse<CPB>(T, sm);
   // up: prolongation with Phi_P and post-smoothing
-  for (int q = T.nl - 2; q >= 0; --q) {
+  for (int q = T.nl - 2; q >= q0; --q) {
     const TailLevel<C>& tl = T.lv[q];
     const double* p = T.prm + (size_t)q * T.per;
     const double *cB = p + 2, *cP = cB + T.KB + 1 + T.KR + 1;
@@ -796,6 +794,45 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
     for (int j = 0; j < T.nu_post; ++j) {
       tl_resid<CPB>(tl.L, f, u, 0, 1, s);
       tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb);
+    }
+  }
+}
+
+// fmg == 0: e = LMG(A_lt, f, 0) over the tail levels lt .. J-1.
+// fmg == 1: e = FMG(f) over the same levels: f_{q+1} = R Phi_R(f_q), exact
+//           coarsest solve, then per level u_q = Phi_P(P u_{q+1}) and one cycle.
+template <int CPB, bool WG, class C, class TU>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* __restrict__ fg,
+                                               TU* __restrict__ eg, int fmg) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  C* sm = reinterpret_cast<C*>(tail_smem);
+  const int col0 = blockIdx.x * CPB;
+  // load the first tail level's right-hand side for this workgroup's columns
+  {
+    const TailLevel<C>& t0 = T.lv[0];
+    for (int e = threadIdx.x; e < t0.L.n * CPB; e += blockDim.x) {
+      const int i = e / CPB, c = e - i * CPB;
+      sm[t0.off_f + e] = (col0 + c < B) ? (C)fg[(size_t)i * B + col0 + c] : C(0);
+    }
+    __syncthreads();
+  }
+  if (!fmg) {
+    tl_cycle<CPB, WG>(T, sm, 0, 1);
+  } else {
+    C *s = sm + T.off_s, *ya = sm + T.off_ya, *yb = sm + T.off_yb, *t = sm + T.off_t;
+    for (int q = 0; q + 1 < T.nl; ++q) {
+      const TailLevel<C>& tl = T.lv[q];
+      const double* cR = T.prm + (size_t)q * T.per + 2 + T.KB + 1;
+      tl_conv_add<CPB, WG>(tl.L, cR, T.KR, sm + tl.off_f, 1.0, s, 1, ya, yb);
+      tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
+    }
+    tl_coarse<CPB>(T, sm);
+    for (int q = T.nl - 2; q >= 0; --q) {
+      const TailLevel<C>& tl = T.lv[q];
+      const double* cP = T.prm + (size_t)q * T.per + 2 + T.KB + 1 + T.KR + 1;
+      tl_xfer<CPB>(tl.P, sm + T.lv[q + 1].off_u, t, 0, C(1), 0);
+      tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, sm + tl.off_u, 1, ya, yb);
+      tl_cycle<CPB, WG>(T, sm, q, 0);
     }
   }
   {

@@ -907,11 +907,11 @@ struct Engine final : EngineBase {
     return MG_OK;
   }
 
-  // e = LMG(A_l, f, 0) for levels l .. J-1 in one launch (l >= tail_lt)
-  mg_status run_tail(int l, const TU* f, TU* e, hipStream_t st) {
+  // e = LMG(A_l, f, 0) (fmg: e = FMG(f)) for levels l .. J-1 in one launch (l >= tail_lt)
+  mg_status run_tail(int l, const TU* f, TU* e, hipStream_t st, int fmg = 0) {
     const int q = l - tail_lt;
     WG_SPLIT(hipLaunchKernelGGL((k_tail<1, WGv, C, TU>), dim3(B()), dim3(1024), tail_bytes[q], st, tails[q], B(),
-                                f, e));
+                                f, e, fmg));
     LAUNCH_OK();
     return MG_OK;
   }
@@ -1188,15 +1188,19 @@ struct Engine final : EngineBase {
   // restriction f_{l+1} = R_l Phi_R,l(f_l), exact solve on the coarsest level,
   // then on each finer level u_l = Phi_P,l(P_l u_{l+1}) followed by one
   // learnable cycle.  Uses the per-level cycle buffers of levels >= 1.
+  // Levels from the LDS tail's start down run as one FMG launch of the tail kernel.
   mg_status fmg(const TU* f0, TU* u0, hipStream_t st) {
     const int J = pl.J;
+    const int lt = tail_lt >= 0 ? tail_lt : J - 1;   // first level handled in one piece
     const TU* fl = f0;
-    for (int l = 0; l + 1 < J; ++l) {
+    for (int l = 0; l < lt; ++l) {
       MG_TRY(restrict_(l, fl, fl, 1, d[l + 1].f, st));
       fl = d[l + 1].f;
     }
-    MG_TRY(coarse(d[J - 1].f, d[J - 1].u, 0, st));
-    for (int l = J - 2; l >= 0; --l) {
+    TU* ult = lt == 0 ? u0 : d[lt].u;
+    if (lt < J - 1) MG_TRY(run_tail(lt, fl, ult, st, 1));
+    else MG_TRY(coarse(fl, ult, 0, st));
+    for (int l = lt - 1; l >= 0; --l) {
       const TU* f = l == 0 ? f0 : d[l].f;
       TU* u = l == 0 ? u0 : d[l].u;
       MG_TRY(prolong(l, d[l + 1].u, u, 1, d[l].x, st));

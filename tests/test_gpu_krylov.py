@@ -15,21 +15,24 @@ TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16": 3e-2}
 CASES = small_cases()
 
 
+@pytest.mark.parametrize("tail", [True, False], ids=["tail", "levels"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("name,hier", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("B", [1, 3, 64])
-def test_fmg_matches_oracle(prec, name, hier, B):
+def test_fmg_matches_oracle(prec, name, hier, B, tail):
+    """FMG with the LDS tail (the coarse levels' nested iteration in one
+    launch) and with per-level sweeps only."""
     import torch
     J = hier.nlevels
     flat = C.random_params(J, 2, 2, 2, seed=60 + B, spread=0.2)
     f = C.rng(6, 1, B).standard_normal((hier.sizes[0], B))
     want = KR.fmg(oracle_levels(hier), oracle_params(flat, J, 2), f)
-    ctx = ctx_for(hier, flat, 2, B, prec)
+    ctx = ctx_for(hier, flat, 2, B, prec, tail=tail)
     u = ctx.empty()
     u.fill_(float("nan"))             # the input value of u must not be used
     ctx.fmg(to_dev(f, ctx.cycle_dtype), u)
     err = rel(to_np(u), want)
-    print(f"fmg {name} {prec} B={B}: rel {err:.2e}", flush=True)
+    print(f"fmg {name} {prec} B={B} tail={tail}: rel {err:.2e}", flush=True)
     assert err <= TOL[prec]
 
 
@@ -54,6 +57,28 @@ def test_fgmres_fixed_iterations_match_oracle(precond, name, hier):
         assert list(info.iters) == list(it) == [k] * B
         assert info.code == 5 and np.all(info.status == 5)
         assert err <= 1e-9
+
+
+@pytest.mark.parametrize("B", [100, 256])
+def test_fgmres_wide_batches_match_oracle(B):
+    """More than 64 columns (two and four lanes per work-item in the cycle
+    sweeps, 128 / 256 lanes per row in the Krylov sweeps): the FP64 iterate
+    after 6 iterations (restarts every 4) against the oracle's, on sampled
+    columns, and every column's iteration count."""
+    import torch
+    name, hier = CASES[0]
+    J = hier.nlevels
+    flat = C.random_params(J, 2, 2, 2, seed=74, spread=0.2)
+    f = C.rng(6, 6, B).standard_normal((hier.sizes[0], B))
+    cols = [0, 1, B // 2, B - 1]
+    want, it, _, _ = KR.fgmres(oracle_levels(hier), oracle_params(flat, J, 2), np.ascontiguousarray(f[:, cols]),
+                               restart=4, rtol=0.0, max_iter=6, precond="vcycle")
+    ctx = ctx_for(hier, flat, 2, B, "fp64")
+    x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
+    info = ctx.fgmres(to_dev(f, torch.float64), x, restart=4, max_iter=6, rtol=0.0, precond="vcycle")
+    err = rel(to_np(x)[:, cols], want)
+    print(f"fgmres B={B}: rel {err:.2e}", flush=True)
+    assert np.all(info.iters == 6) and err <= 1e-9
 
 
 @pytest.mark.parametrize("reorth", [0.0, 1.0])
