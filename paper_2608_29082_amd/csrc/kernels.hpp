@@ -274,17 +274,20 @@ __global__ __launch_bounds__(256) void k_resid(Lvl<C> L, int B, int lbs, const T
   C dg[ROWS];
   row_vals<WIDE, CS>(L.diag, t.row, t.row0, dg);
   for (int b = t.lane; b < B; b += t.LB) {
-    C fv[ROWS], s[ROWS];
+    // the row's own f and u are loaded first but consumed only at the end, so
+    // their loads overlap the index loads and the off-diagonal gathers
+    C fv[ROWS], uv[ROWS], s[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       fv[r] = ldc<C>(f + (size_t)t.row[r] * B + b);
-      s[r] = dg[r] * ldc<C>(u + (size_t)t.row[r] * B + b);
+      uv[r] = ldc<C>(u + (size_t)t.row[r] * B + b);
+      s[r] = C(0);
     }
     ell_dot<WIDE, CS>(L.w, L.ld, L.col, L.val, t.row, t.row0, u, B, b, s);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (!t.ok[r]) continue;
-      C v = fv[r] - s[r];
+      C v = fv[r] - (s[r] + dg[r] * uv[r]);
       if (jacobi) v *= dinv[r];
       put(out + (size_t)t.row[r] * B + b, v);
     }
@@ -535,18 +538,20 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
     row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
-      double fv[4], s[4];
+      // own f and u loaded first, consumed after the off-diagonal gathers
+      double fv[4], uv[4], s[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         fv[r] = f[(size_t)row[r] * B + b];
-        s[r] = dg[r] * u[(size_t)row[r] * B + b];
+        uv[r] = u[(size_t)row[r] * B + b];
+        s[r] = 0.0;
       }
       ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (!ok[r]) continue;
         const size_t o = (size_t)row[r] * B + b;
-        const double v = fv[r] - s[r];
+        const double v = fv[r] - (s[r] + dg[r] * uv[r]);
         if (r64) r64[o] = v;
         if (rc) put(rc + o, v);
         acc[q] += v * v;
@@ -911,16 +916,17 @@ __global__ __launch_bounds__(256) void k_sub_Aq(Lvl<C> L, int B, int lbs, const 
                                                 const TZ* __restrict__ q, TZ* gout) {
   const Tile<ROWS, WIDE> t(L.n, lbs);
   for (int b = t.lane; b < B; b += t.LB) {
-    C gv[ROWS], s[ROWS];
+    C gv[ROWS], qv[ROWS], s[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       gv[r] = ldc<C>(gin + (size_t)t.row[r] * B + b);
-      s[r] = uni<WIDE>(L.diag[t.row[r]]) * ldc<C>(q + (size_t)t.row[r] * B + b);
+      qv[r] = ldc<C>(q + (size_t)t.row[r] * B + b);
+      s[r] = C(0);
     }
     ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, t.row, t.row0, q, B, b, s);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
-      if (t.ok[r]) put(gout + (size_t)t.row[r] * B + b, gv[r] - s[r]);
+      if (t.ok[r]) put(gout + (size_t)t.row[r] * B + b, gv[r] - (s[r] + uni<WIDE>(L.diag[t.row[r]]) * qv[r]));
   }
 }
 

@@ -194,14 +194,17 @@ __global__ __launch_bounds__(256) void k_kr_amul(Lvl<double> L, int B, int lbs, 
   double dg[ROWS];
   row_vals<WIDE, CS>(L.diag, t.row, t.row0, dg);
   for (int b = t.lane; b < B; b += t.LB) {
-    double s[ROWS];
+    double zv[ROWS], s[ROWS];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) s[r] = dg[r] * ldc<double>(z + (size_t)t.row[r] * B + b);
+    for (int r = 0; r < ROWS; ++r) {
+      zv[r] = ldc<double>(z + (size_t)t.row[r] * B + b);
+      s[r] = 0.0;
+    }
     ell_dot<WIDE, CS>(L.w, L.ld, L.col, L.val, t.row, t.row0, z, B, b, s);
     const double sc = sig[b];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
-      if (t.ok[r]) w[(size_t)t.row[r] * B + b] = sc * s[r];
+      if (t.ok[r]) w[(size_t)t.row[r] * B + b] = sc * (s[r] + dg[r] * zv[r]);
   }
 }
 
