@@ -11,18 +11,40 @@
 // matrix graph {(i, j): A_ij != 0} (Sec. 2.1).  Used for per-request setup
 // when serving; it builds inputs of the V-cycle, not the V-cycle itself.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mgl.h"
 
 namespace {
 
+// Array whose elements start uninitialised (filled in parallel by the
+// builders, so the pages are first touched by the threads that write them).
+template <class T>
+struct Buf {
+  std::unique_ptr<T[]> p;
+  size_t n = 0;
+  void resize(size_t m) {
+    p.reset(new T[std::max<size_t>(m, 1)]);
+    n = m;
+  }
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+  T* data() { return p.get(); }
+  const T* data() const { return p.get(); }
+  size_t size() const { return n; }
+  const T* begin() const { return p.get(); }
+  const T* end() const { return p.get() + n; }
+};
+
 struct Csr {
   int nrows = 0, ncols = 0;
-  std::vector<int> rowptr, col;
-  std::vector<double> val;
+  Buf<int> rowptr, col;
+  Buf<double> val;
 };
 
 // Interior unknown of grid point (i, j) of a side x side grid, or -1.
@@ -45,26 +67,53 @@ struct RowAcc {
     }
     acc[c] += v;
   }
-  void flush(Csr& out, bool drop_zero) {
-    std::sort(cols.begin(), cols.end());
-    for (int c : cols)
-      if (!drop_zero || acc[c] != 0.0) {
-        out.col.push_back(c);
-        out.val.push_back(acc[c]);
-      }
-    cols.clear();
-    out.rowptr.push_back((int)out.col.size());
-  }
 };
 
+// fn(r0, r1) over a split of [0, n) into at most 8 contiguous ranges, one thread each.
+// Calls of this library building setup data at the same time (serving runs
+// several); their per-row loops share the host's threads between them.
+std::atomic<int> g_active_calls{0};
+struct ActiveCall {
+  ActiveCall() { ++g_active_calls; }
+  ~ActiveCall() { --g_active_calls; }
+};
+
+template <class F>
+void par_rows(int n, F&& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int share = std::max(1, hw / std::max(1, g_active_calls.load()));
+  const int nt = std::max(1, std::min({share, 8, n / 8192 + 1}));
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back([&, t] { fn((int)((long long)n * t / nt), (int)((long long)n * (t + 1) / nt)); });
+  fn(0, (int)((long long)n / nt));
+  for (auto& x : th) x.join();
+}
+
+// CSR with known row lengths: rowptr from the counts, arrays sized once.
+Csr alloc_csr(int nrows, int ncols, const std::vector<int>& cnt) {
+  Csr c;
+  c.nrows = nrows;
+  c.ncols = ncols;
+  c.rowptr.resize((size_t)nrows + 1);
+  c.rowptr[0] = 0;
+  for (int i = 0; i < nrows; ++i) c.rowptr[i + 1] = c.rowptr[i] + cnt[i];
+  c.col.resize(c.rowptr[nrows]);
+  c.val.resize(c.rowptr[nrows]);
+  return c;
+}
+
+// Five-point rows of the P1 "/" mesh: the triangles around vertex (i, j) are the
+// lower-right (v00, v10, v11) and upper-left (v00, v11, v01) triangles of the
+// cells (i, j), (i-1, j), (i-1, j-1), (i, j-1), with element matrices
+// a/2 [[1,-1,0],[-1,2,-1],[0,-1,1]] and a/2 [[1,0,-1],[0,1,-1],[-1,-1,2]]; the
+// diagonal couplings cancel, leaving west, south, east and north neighbours.
 Csr assemble(int side, int nb, const double* blocks) {
   const int m = side - 2, n = m * m, cells = side - 1;
-  Csr A;
-  A.nrows = A.ncols = n;
-  A.rowptr.assign(1, 0);
-  RowAcc ra(n);
-  // block of the centroid (ci + 2/3, cj + 1/3) (lower-right triangle) or
-  // (ci + 1/3, cj + 2/3) (upper-left), exactly in integers
+  // coefficient of the block containing each triangle's centroid
+  // (ci + 2/3, cj + 1/3) (lower-right) and (ci + 1/3, cj + 2/3) (upper-left),
+  // exactly in integers
+  std::vector<double> lr((size_t)cells * cells), ul((size_t)cells * cells);
   auto blk = [&](int c3, int d3) {   // coordinates times 3*cells
     int bi = (int)((long long)c3 * nb / (3LL * cells));
     int bj = (int)((long long)d3 * nb / (3LL * cells));
@@ -72,135 +121,163 @@ Csr assemble(int side, int nb, const double* blocks) {
     bj = std::min(bj, nb - 1);
     return blocks[(size_t)bj * nb + bi];
   };
-  for (int j = 1; j <= m; ++j)
-    for (int i = 1; i <= m; ++i) {
-      const int row = unk(side, i, j);
-      // the six triangles around vertex (i, j); element matrices of the
-      // lower-right triangle (v00, v10, v11): a/2 [[1,-1,0],[-1,2,-1],[0,-1,1]]
-      // and of the upper-left triangle (v00, v11, v01): a/2 [[1,0,-1],[0,1,-1],[-1,-1,2]]
-      double diag = 0.0;
-      // cell (i, j): vertex is v00 of both triangles
-      if (i < cells && j < cells) {
-        const double a1 = blk(3 * i + 2, 3 * j + 1), a2 = blk(3 * i + 1, 3 * j + 2);
-        diag += 0.5 * a1 + 0.5 * a2;
-        const int e = unk(side, i + 1, j), nn = unk(side, i, j + 1);
-        if (e >= 0) ra.add(row, e, -0.5 * a1);
-        if (nn >= 0) ra.add(row, nn, -0.5 * a2);
+  par_rows(cells, [&](int j0, int j1) {
+    for (int cj = j0; cj < j1; ++cj)
+      for (int ci = 0; ci < cells; ++ci) {
+        lr[(size_t)cj * cells + ci] = blk(3 * ci + 2, 3 * cj + 1);
+        ul[(size_t)cj * cells + ci] = blk(3 * ci + 1, 3 * cj + 2);
       }
-      // cell (i-1, j): vertex is v10 of the lower-right triangle only
-      if (i - 1 >= 0 && j < cells) {
-        const double a1 = blk(3 * (i - 1) + 2, 3 * j + 1);
-        diag += a1;
-        const int w = unk(side, i - 1, j), ne = unk(side, i, j + 1);
-        if (w >= 0) ra.add(row, w, -0.5 * a1);
-        if (ne >= 0) ra.add(row, ne, -0.5 * a1);
-      }
-      // cell (i-1, j-1): vertex is v11 of both triangles
-      if (i - 1 >= 0 && j - 1 >= 0) {
-        const double a1 = blk(3 * (i - 1) + 2, 3 * (j - 1) + 1), a2 = blk(3 * (i - 1) + 1, 3 * (j - 1) + 2);
-        diag += 0.5 * a1 + 0.5 * a2;
-        const int s = unk(side, i, j - 1), w = unk(side, i - 1, j);
-        if (s >= 0) ra.add(row, s, -0.5 * a1);
-        if (w >= 0) ra.add(row, w, -0.5 * a2);
-      }
-      // cell (i, j-1): vertex is v01 of the upper-left triangle only
-      if (i < cells && j - 1 >= 0) {
-        const double a2 = blk(3 * i + 1, 3 * (j - 1) + 2);
-        diag += a2;
-        const int s = unk(side, i, j - 1), e = unk(side, i + 1, j);
-        if (s >= 0) ra.add(row, s, -0.5 * a2);
-        if (e >= 0) ra.add(row, e, -0.5 * a2);
-      }
-      ra.add(row, row, diag);
-      ra.flush(A, true);
+  });
+  auto L = [&](int ci, int cj) { return lr[(size_t)cj * cells + ci]; };
+  auto U = [&](int ci, int cj) { return ul[(size_t)cj * cells + ci]; };
+  std::vector<int> cnt(n);
+  par_rows(n, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      const int i = r % m + 1, j = r / m + 1;
+      cnt[r] = 1 + (i > 1) + (j > 1) + (i < m) + (j < m);
     }
+  });
+  Csr A = alloc_csr(n, n, cnt);
+  par_rows(n, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      const int i = r % m + 1, j = r / m + 1;
+      const double a1 = L(i, j), a2 = U(i, j), b1 = L(i - 1, j), c1 = L(i - 1, j - 1), c2 = U(i - 1, j - 1),
+                   d2 = U(i, j - 1);
+      const double diag = 0.5 * a1 + 0.5 * a2 + b1 + 0.5 * c1 + 0.5 * c2 + d2;
+      int p = A.rowptr[r];
+      auto put = [&](int c, double v) { A.col[p] = c; A.val[p] = v; ++p; };
+      if (j > 1) put(r - m, -0.5 * c1 - 0.5 * d2);   // south (i, j-1)
+      if (i > 1) put(r - 1, -0.5 * b1 - 0.5 * c2);   // west (i-1, j)
+      put(r, diag);
+      if (i < m) put(r + 1, -0.5 * a1 - 0.5 * d2);   // east (i+1, j)
+      if (j < m) put(r + m, -0.5 * a2 - 0.5 * b1);   // north (i, j+1)
+    }
+  });
   return A;
 }
 
+// Nested linear interpolation: a fine vertex at an even position is a coarse
+// vertex (weight 1); otherwise it is the midpoint of a coarse edge of the "/"
+// mesh (weights 1/2 at its two ends, boundary ends dropped).
 Csr prolongation(int side_f) {
   const int side_c = (side_f + 1) / 2, mf = side_f - 2;
-  Csr P;
-  P.nrows = mf * mf;
-  P.ncols = (side_c - 2) * (side_c - 2);
-  P.rowptr.assign(1, 0);
-  RowAcc ra(P.ncols);
-  for (int j = 1; j <= mf; ++j)
-    for (int i = 1; i <= mf; ++i) {
-      const int row = unk(side_f, i, j);
-      const int c1 = unk(side_c, i / 2, j / 2), c2 = unk(side_c, (i + 1) / 2, (j + 1) / 2);
-      if (c1 >= 0) ra.add(row, c1, 0.5);
-      if (c2 >= 0) ra.add(row, c2, 0.5);
-      ra.flush(P, true);
+  const int nf = mf * mf, nc = (side_c - 2) * (side_c - 2);
+  auto ends = [&](int r, int& c1, int& c2) {
+    const int i = r % mf + 1, j = r / mf + 1;
+    c1 = unk(side_c, i / 2, j / 2);
+    c2 = unk(side_c, (i + 1) / 2, (j + 1) / 2);
+  };
+  std::vector<int> cnt(nf);
+  par_rows(nf, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      int c1, c2;
+      ends(r, c1, c2);
+      cnt[r] = c1 == c2 ? (c1 >= 0) : (c1 >= 0) + (c2 >= 0);
     }
+  });
+  Csr P = alloc_csr(nf, nc, cnt);
+  par_rows(nf, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      int c1, c2, p = P.rowptr[r];
+      ends(r, c1, c2);
+      if (c1 == c2) {
+        if (c1 >= 0) { P.col[p] = c1; P.val[p] = 1.0; }
+        continue;
+      }
+      if (c1 >= 0) { P.col[p] = c1; P.val[p] = 0.5; ++p; }
+      if (c2 >= 0) { P.col[p] = c2; P.val[p] = 0.5; }
+    }
+  });
   return P;
 }
 
-Csr transpose(const Csr& a) {
-  Csr t;
-  t.nrows = a.ncols;
-  t.ncols = a.nrows;
-  std::vector<int> cnt(a.ncols + 1, 0);
-  for (int c : a.col) cnt[c + 1]++;
-  for (int i = 0; i < a.ncols; ++i) cnt[i + 1] += cnt[i];
-  t.rowptr = cnt;
-  t.col.resize(a.col.size());
-  t.val.resize(a.val.size());
-  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-  for (int i = 0; i < a.nrows; ++i)
-    for (int p = a.rowptr[i]; p < a.rowptr[i + 1]; ++p) {
-      const int q = pos[a.col[p]]++;
-      t.col[q] = i;
-      t.val[q] = a.val[p];
-    }
-  return t;
-}
-
-Csr spgemm(const Csr& a, const Csr& b) {
-  Csr c;
-  c.nrows = a.nrows;
-  c.ncols = b.ncols;
-  c.rowptr.assign(1, 0);
-  RowAcc ra(b.ncols);
-  for (int i = 0; i < a.nrows; ++i) {
-    for (int p = a.rowptr[i]; p < a.rowptr[i + 1]; ++p)
-      for (int q = b.rowptr[a.col[p]]; q < b.rowptr[a.col[p] + 1]; ++q) ra.add(i, b.col[q], a.val[p] * b.val[q]);
-    ra.flush(c, false);
-  }
-  return c;
-}
-
-// 0.5 (C + C^T), then drop off-diagonal residue and exact zeros
-Csr sym_drop(const Csr& c) {
-  const Csr t = transpose(c);
-  Csr s;
-  s.nrows = s.ncols = c.nrows;
-  s.rowptr.assign(1, 0);
-  RowAcc ra(c.ncols);
-  for (int i = 0; i < c.nrows; ++i) {
-    for (int p = c.rowptr[i]; p < c.rowptr[i + 1]; ++p) ra.add(i, c.col[p], c.val[p]);
-    for (int p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) ra.add(i, t.col[p], t.val[p]);
-    for (int cc : ra.cols) ra.acc[cc] *= 0.5;
-    ra.flush(s, false);
-  }
-  std::vector<double> d(s.nrows, 0.0);
-  for (int i = 0; i < s.nrows; ++i)
-    for (int p = s.rowptr[i]; p < s.rowptr[i + 1]; ++p)
-      if (s.col[p] == i) d[i] = std::fabs(s.val[p]);
-  Csr o;
-  o.nrows = o.ncols = s.nrows;
-  o.rowptr.assign(1, 0);
-  for (int i = 0; i < s.nrows; ++i) {
-    for (int p = s.rowptr[i]; p < s.rowptr[i + 1]; ++p) {
-      const int j = s.col[p];
-      double v = s.val[p];
-      if (j != i && std::fabs(v) <= 1e-14 * std::sqrt(d[i] * d[j])) v = 0.0;
-      if (v != 0.0) {
-        o.col.push_back(j);
-        o.val.push_back(v);
+// R = P^T of the nested interpolation, row by row: coarse vertex (ci, cj) sits
+// at fine (2ci, 2cj) with weight 1 and is an end of the six fine edge
+// midpoints around it (horizontal, vertical and the south-west/north-east
+// diagonal of the "/" mesh) with weight 1/2; all seven are interior.
+Csr restriction(int side_f) {
+  const int side_c = (side_f + 1) / 2, mc = side_c - 2, nc = mc * mc, nf = (side_f - 2) * (side_f - 2);
+  Csr R = alloc_csr(nc, nf, std::vector<int>(nc, 7));
+  par_rows(nc, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      const int i0 = 2 * (r % mc + 1), j0 = 2 * (r / mc + 1);
+      const int di[7] = {-1, 0, -1, 0, 1, 0, 1}, dj[7] = {-1, -1, 0, 0, 0, 1, 1};
+      int p = R.rowptr[r];
+      for (int k = 0; k < 7; ++k) {
+        R.col[p] = unk(side_f, i0 + di[k], j0 + dj[k]);
+        R.val[p] = (di[k] == 0 && dj[k] == 0) ? 1.0 : 0.5;
+        ++p;
       }
     }
-    o.rowptr.push_back((int)o.col.size());
-  }
+  });
+  return R;
+}
+
+// Galerkin product A_c = R A P, row by row: for coarse row I,
+//   A_c(I, :) = sum_{i in R(I, :)} R_Ii (A P)(i, :),  (A P)(i, :) = sum_{j in A(i, :)} A_ij P(j, :)
+// (each row of A P formed on the fly, the sums taken in the order of R (A P)), symmetrised,
+// 0.5 (A_c + A_c^T), with off-diagonal round-off residue
+// |a_IJ| <= 1e-14 sqrt(|a_II a_JJ|) and exact zeros removed.
+Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
+  const int nc = R.nrows;
+  // pass 1: the sorted column pattern and values of every row of R A P
+  std::vector<std::vector<int>> pc(nc);
+  std::vector<std::vector<double>> pv(nc);
+  par_rows(nc, [&](int r0, int r1) {
+    RowAcc ap(P.ncols), ai(P.ncols);
+    int tag = 0;
+    for (int I = r0; I < r1; ++I) {
+      for (int p = R.rowptr[I]; p < R.rowptr[I + 1]; ++p) {
+        const int i = R.col[p];
+        for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+          const int j = A.col[q];
+          for (int s = P.rowptr[j]; s < P.rowptr[j + 1]; ++s) ai.add(tag, P.col[s], A.val[q] * P.val[s]);
+        }
+        std::sort(ai.cols.begin(), ai.cols.end());
+        for (int J : ai.cols) ap.add(I, J, R.val[p] * ai.acc[J]);
+        ai.cols.clear();
+        ++tag;
+      }
+      std::sort(ap.cols.begin(), ap.cols.end());
+      pc[I] = ap.cols;
+      pv[I].resize(ap.cols.size());
+      for (size_t k = 0; k < ap.cols.size(); ++k) pv[I][k] = ap.acc[ap.cols[k]];
+      ap.cols.clear();
+    }
+  });
+  // pass 2: symmetrise by merging each row with the matching column
+  // (value of (J, I) looked up in row J, whose pattern contains I by symmetry
+  // of the pattern), then drop residue
+  std::vector<double> d(nc, 0.0);
+  for (int I = 0; I < nc; ++I)
+    for (size_t k = 0; k < pc[I].size(); ++k)
+      if (pc[I][k] == I) d[I] = std::fabs(pv[I][k]);
+  auto at = [&](int r, int c) {
+    const auto it = std::lower_bound(pc[r].begin(), pc[r].end(), c);
+    return (it != pc[r].end() && *it == c) ? pv[r][it - pc[r].begin()] : 0.0;
+  };
+  std::vector<int> cnt(nc, 0);
+  std::vector<std::vector<double>> sv(nc);
+  par_rows(nc, [&](int r0, int r1) {
+    for (int I = r0; I < r1; ++I) {
+      sv[I].resize(pc[I].size());
+      for (size_t k = 0; k < pc[I].size(); ++k) {
+        const int J = pc[I][k];
+        double v = 0.5 * (pv[I][k] + at(J, I));
+        if (J != I && std::fabs(v) <= 1e-14 * std::sqrt(d[I] * d[J])) v = 0.0;
+        sv[I][k] = v;
+        cnt[I] += v != 0.0;
+      }
+    }
+  });
+  Csr o = alloc_csr(nc, nc, cnt);
+  par_rows(nc, [&](int r0, int r1) {
+    for (int I = r0; I < r1; ++I) {
+      int p = o.rowptr[I];
+      for (size_t k = 0; k < pc[I].size(); ++k)
+        if (sv[I][k] != 0.0) { o.col[p] = pc[I][k]; o.val[p] = sv[I][k]; ++p; }
+    }
+  });
   return o;
 }
 
@@ -229,13 +306,14 @@ mg_status mg_square_hierarchy(int32_t side, int32_t nb, const double* blocks, in
   if (s - 2 != coarsest || J < 2) return MG_ERR_SHAPE;
   for (int k = 0; k < nb * nb; ++k)
     if (!(blocks[k] > 0.0) || !std::isfinite(blocks[k])) return MG_ERR_INVALID_ARG;
+  const ActiveCall guard;
   auto* h = new mg_host_hierarchy;
   h->A.push_back(assemble(side, nb, blocks));
   s = side;
   for (int l = 0; l + 1 < J; ++l) {
     h->P.push_back(prolongation(s));
-    const Csr R = transpose(h->P.back());
-    h->A.push_back(sym_drop(spgemm(R, spgemm(h->A.back(), h->P.back()))));
+    const Csr R = restriction(s);
+    h->A.push_back(galerkin(h->A.back(), h->P.back(), R));
     s = (s + 1) / 2;
   }
   auto view = [](const Csr& c) {

@@ -11,10 +11,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -106,11 +108,28 @@ constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 409
 inline int round_up(int w, int m) { return (w + m - 1) / m * m; }
 
 // ------------------------------------------------------------------ host-side structures
+// Allocator that leaves int / double elements uninitialised, so the large
+// setup arrays are written once, in parallel, by the loops that fill them.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind { using other = NoInit<U>; };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept { ::new ((void*)p) U; }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... a) { ::new ((void*)p) U(std::forward<Args>(a)...); }
+};
+template <class T>
+using uvector = std::vector<T, NoInit<T>>;
+
 struct HEll {          // slot-major ELL
   int n = 0, w = 0;
   int ld = 0;          // slot stride (level operators: n rounded up to 4; transfers: n)
-  std::vector<int> col;
-  std::vector<double> val;
+  uvector<int> col;
+  uvector<double> val;
 };
 
 struct HLevel {
@@ -123,6 +142,28 @@ struct HLevel {
   std::vector<double> gval;     // edge weights in the graph's slots (weighted / symmetric aggregation)
   bool sym_graph = false, sym_A = false;
 };
+
+// fn(r0, r1) over a split of [0, n) into contiguous ranges, one host thread
+// each (at most 8; one for small n).  Used by the setup's per-row loops.
+// Calls of this library building setup data at the same time (serving runs
+// several); their per-row loops share the host's threads between them.
+std::atomic<int> g_active_calls{0};
+struct ActiveCall {
+  ActiveCall() { ++g_active_calls; }
+  ~ActiveCall() { --g_active_calls; }
+};
+
+template <class F>
+void par_rows(int n, F&& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int share = std::max(1, hw / std::max(1, g_active_calls.load()));
+  const int nt = std::max(1, std::min({share, 8, n / 16384 + 1}));
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back([&, t] { fn((int)((long long)n * t / nt), (int)((long long)n * (t + 1) / nt)); });
+  fn(0, (int)((long long)n / nt));
+  for (auto& x : th) x.join();
+}
 
 mg_status check_csr(const mg_csr* m, const char* what, int l) {
   const std::string w = std::string(what) + "[" + std::to_string(l) + "]";
@@ -149,20 +190,24 @@ bool has_entry(const mg_csr* m, int i, int j, double* v) {
   return true;
 }
 
-mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int agg) {
+// check_sym: determine whether A and the graph are symmetric (only the
+// reverse sweep needs it; forward-only contexts skip the check).
+mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int agg, bool check_sym) {
   const int n = A->nrows;
   L.n = n;
   L.diag.assign(n, 0.0);
   if (!A->val) return fail(MG_ERR_INVALID_ARG, "A values missing");
   std::vector<int> cnt(n, 0);
-  for (int i = 0; i < n; ++i) {
-    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
-      if (A->col[p] == i) L.diag[i] = A->val[p];
-      else if (A->val[p] != 0.0) cnt[i]++;
-    }
+  par_rows(n, [&](int r0, int r1) {
+    for (int i = r0; i < r1; ++i)
+      for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+        if (A->col[p] == i) L.diag[i] = A->val[p];
+        else if (A->val[p] != 0.0) cnt[i]++;
+      }
+  });
+  for (int i = 0; i < n; ++i)
     if (!(L.diag[i] != 0.0) || !std::isfinite(L.diag[i]))
       return fail(MG_ERR_SHAPE, "A[" + std::to_string(l) + "]: zero or non-finite diagonal at row " + std::to_string(i));
-  }
   int w = 0;
   for (int c : cnt) w = std::max(w, c);
   if (w > kMaxW) return fail(MG_ERR_UNSUPPORTED, "A[" + std::to_string(l) + "]: more than 64 off-diagonal entries in a row");
@@ -171,18 +216,25 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int ag
   L.off.n = n;
   L.off.w = w;
   L.off.ld = ld;
-  L.off.col.assign((size_t)w * ld, n - 1);   // rows [n, ld): padding with a valid column
-  L.off.val.assign((size_t)w * ld, 0.0);
-  for (int i = 0; i < n; ++i) {
-    int k = 0;
-    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
-      if (A->col[p] != i && A->val[p] != 0.0) {
-        L.off.col[(size_t)k * ld + i] = A->col[p];
-        L.off.val[(size_t)k * ld + i] = A->val[p];
-        ++k;
+  L.off.col.resize((size_t)w * ld);
+  L.off.val.resize((size_t)w * ld);
+  par_rows(ld, [&](int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+      int k = 0;
+      if (i < n)
+        for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
+          if (A->col[p] != i && A->val[p] != 0.0) {
+            L.off.col[(size_t)k * ld + i] = A->col[p];
+            L.off.val[(size_t)k * ld + i] = A->val[p];
+            ++k;
+          }
+      // padding slots point at the row itself; rows [n, ld) at a valid row (n - 1)
+      for (; k < w; ++k) {
+        L.off.col[(size_t)k * ld + i] = i < n ? i : n - 1;
+        L.off.val[(size_t)k * ld + i] = 0.0;
       }
-    for (; k < w; ++k) L.off.col[(size_t)k * ld + i] = i;
-  }
+    }
+  });
   // graph
   std::vector<int> deg(n, 0);
   L.graph_is_A = (G == nullptr);
@@ -199,7 +251,7 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int ag
     L.graph.n = n;
     L.graph.w = wg;
     L.graph.ld = round_up(n, 4);
-    L.graph.col.assign((size_t)wg * L.graph.ld, n - 1);
+    L.graph.col.assign((size_t)wg * L.graph.ld, n - 1);   // rows [n, ld): a valid column
     for (int i = 0; i < n; ++i) {
       int k = 0;
       for (int p = G->rowptr[i]; p < G->rowptr[i + 1]; ++p)
@@ -240,17 +292,28 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int ag
     }
   }
   // symmetry of the graph and of A (needed by the reverse sweep)
-  L.sym_A = true;
-  for (int i = 0; i < n && L.sym_A; ++i)
-    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
-      double v = 0.0;
-      if (!has_entry(A, A->col[p], i, &v) || v != A->val[p]) {
-        // an explicit zero may lack its mirror
-        if (A->val[p] == 0.0 && !has_entry(A, A->col[p], i, nullptr)) continue;
-        L.sym_A = false;
-        break;
-      }
+  if (!check_sym) {
+    L.sym_A = L.sym_graph = false;
+    return MG_OK;
+  }
+  std::vector<char> asym((size_t)std::min(n, 64), 0);   // one flag per row range
+  const int nr = (int)asym.size();
+  par_rows(nr, [&](int q0, int q1) {
+    for (int q = q0; q < q1; ++q) {
+      const int i0 = (int)((long long)n * q / nr), i1 = (int)((long long)n * (q + 1) / nr);
+      for (int i = i0; i < i1 && !asym[q]; ++i)
+        for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+          double v = 0.0;
+          if (!has_entry(A, A->col[p], i, &v) || v != A->val[p]) {
+            // an explicit zero may lack its mirror
+            if (A->val[p] == 0.0 && !has_entry(A, A->col[p], i, nullptr)) continue;
+            asym[q] = 1;
+            break;
+          }
+        }
     }
+  });
+  L.sym_A = std::find(asym.begin(), asym.end(), 1) == asym.end();
   if (!G) {
     L.sym_graph = L.sym_A;
   } else {
@@ -275,15 +338,21 @@ HEll ell_from_csr(const mg_csr* m, int mult) {
   for (int i = 0; i < m->nrows; ++i) w = std::max(w, m->rowptr[i + 1] - m->rowptr[i]);
   w = round_up(std::max(w, 1), mult);
   e.w = w;
-  e.col.assign((size_t)w * e.n, 0);
-  e.val.assign((size_t)w * e.n, 0.0);
-  for (int i = 0; i < e.n; ++i) {
-    int k = 0;
-    for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p, ++k) {
-      e.col[(size_t)k * e.n + i] = m->col[p];
-      e.val[(size_t)k * e.n + i] = m->val ? m->val[p] : 0.0;
+  e.col.resize((size_t)w * e.n);
+  e.val.resize((size_t)w * e.n);
+  par_rows(e.n, [&](int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+      int k = 0;
+      for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p, ++k) {
+        e.col[(size_t)k * e.n + i] = m->col[p];
+        e.val[(size_t)k * e.n + i] = m->val ? m->val[p] : 0.0;
+      }
+      for (; k < w; ++k) {   // padding: column 0, weight 0
+        e.col[(size_t)k * e.n + i] = 0;
+        e.val[(size_t)k * e.n + i] = 0.0;
+      }
     }
-  }
+  });
   return e;
 }
 
@@ -296,8 +365,12 @@ HEll ell_transpose(const mg_csr* m, int mult) {
   for (int c : cnt) w = std::max(w, c);
   w = round_up(std::max(w, 1), mult);
   e.w = w;
-  e.col.assign((size_t)w * e.n, 0);
-  e.val.assign((size_t)w * e.n, 0.0);
+  e.col.resize((size_t)w * e.n);
+  e.val.resize((size_t)w * e.n);
+  par_rows(w, [&](int k0, int k1) {   // padding everywhere first: column 0, weight 0
+    std::fill(e.col.begin() + (size_t)k0 * e.n, e.col.begin() + (size_t)k1 * e.n, 0);
+    std::fill(e.val.begin() + (size_t)k0 * e.n, e.val.begin() + (size_t)k1 * e.n, 0.0);
+  });
   std::vector<int> fill(m->ncols, 0);
   for (int i = 0; i < m->nrows; ++i)
     for (int p = m->rowptr[i]; p < m->rowptr[i + 1]; ++p) {
@@ -403,7 +476,8 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
   pl.lv.resize(J);
   for (int l = 0; l < J; ++l) {
     if (full) {
-      MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l, p->aggregation));
+      MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l, p->aggregation,
+                         (o->flags & MG_FLAG_BACKWARD) != 0));
       pl.sym_all = pl.sym_all && pl.lv[l].sym_A && pl.lv[l].sym_graph;
     } else {
       // sizes only: widths from row counts
@@ -600,7 +674,7 @@ struct Engine final : EngineBase {
   bool owns_ws = false;
   int lbs = 0;
   // device-side host copies kept alive during setup
-  std::vector<std::vector<char>> staging;
+  std::vector<uvector<char>> staging;
 
   ~Engine() override {
     if (owns_ws && wsbase) (void)hipFree(wsbase);
@@ -755,17 +829,21 @@ struct Engine final : EngineBase {
     return c;
   }
 
-  template <class T>
-  mg_status up(T* dst, const std::vector<double>& src, hipStream_t st) {
+  template <class T, class V>
+  mg_status up(T* dst, const V& src, hipStream_t st) {
     if (src.empty()) return MG_OK;
-    std::vector<char> buf(src.size() * sizeof(T));
+    uvector<char> buf(src.size() * sizeof(T));
     T* t = reinterpret_cast<T*>(buf.data());
-    for (size_t i = 0; i < src.size(); ++i) t[i] = (T)src[i];
+    const long cnt = (long)src.size();
+    par_rows((int)((cnt + 1023) / 1024), [&](int b0, int b1) {
+      for (long i = (long)b0 * 1024; i < std::min(cnt, (long)b1 * 1024); ++i) t[i] = (T)src[i];
+    });
     HIP_TRY(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
     staging.push_back(std::move(buf));
     return MG_OK;
   }
-  mg_status upi(const int* dst, const std::vector<int>& src, hipStream_t st) {
+  template <class V>
+  mg_status upi(const int* dst, const V& src, hipStream_t st) {
     if (src.empty()) return MG_OK;
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(dst), src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, st));
     return MG_OK;
@@ -1633,6 +1711,7 @@ mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* 
   g_err.clear();
   if (!out) return fail(MG_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
+  const ActiveCall guard;
   std::unique_ptr<EngineBase> e(make_engine(o ? o->precision : 0));
   MG_TRY(build_plan(h, p, o, e->pl, true));
   const size_t need = e->ws_bytes();
