@@ -118,7 +118,8 @@ typedef struct {
 
 enum {
     MG_FLAG_BACKWARD = 1,   /* reserve buffers for mg_*_backward */
-    MG_FLAG_NO_TAIL = 2     /* never run the coarse levels as one LDS-resident kernel */
+    MG_FLAG_NO_TAIL = 2,    /* never run the coarse levels as one LDS-resident kernel */
+    MG_FLAG_NO_TILES = 4    /* never run a K-hop convolution as one fused LDS-tile kernel */
 };
 
 typedef struct {
@@ -265,7 +266,8 @@ enum {
     MG_KF_RESTRICT = 3,  /* restriction (with fused residual or last hop) */
     MG_KF_PROLONG = 4,   /* prolongation (with fused correction) */
     MG_KF_OUTER = 5,     /* FP64 outer residual with column norms */
-    MG_KF_KRYLOV = 6     /* FGMRES Gram-Schmidt sweeps (dot products, basis updates) */
+    MG_KF_KRYLOV = 6,    /* FGMRES Gram-Schmidt sweeps (dot products, basis updates) */
+    MG_KF_CONV = 7       /* fused K-hop graph convolutions over LDS tiles */
 };
 
 /* Start timing every launch of one kernel family on one level (level -1:

@@ -23,13 +23,14 @@ BASES = {"monomial": 0, "chebyshev": 1}
 AGGREGATIONS = {"mean": 0, "weighted": 1, "sym": 2}
 FLAG_BACKWARD = 1
 FLAG_NO_TAIL = 2
+FLAG_NO_TILES = 4
 
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
             "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
             "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
             "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error",
             "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres"]
-KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6}
+KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6, "conv": 7}
 PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
 # default threshold of the second Gram-Schmidt pass: run it for a vector when
 # the first pass left less than a tenth of its norm (orthogonality to about
@@ -224,12 +225,14 @@ class Context:
     basis: "monomial" or "chebyshev" (meaning of the convolution coefficients);
     aggregation: "mean", "weighted" (|a_ij| edge weights) or "sym" (symmetric
     normalisation), the graph operator of the convolutions.
+    tail / tiles: allow the LDS-resident coarse tail / the fused K-hop
+    convolution over LDS tiles (FP32/BF16 cycles with nrhs a multiple of 16).
     """
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
                  backward=False, device=None, stream=None, workspace=True, tail=True, native=None,
-                 basis="monomial", aggregation="mean"):
+                 basis="monomial", aggregation="mean", tiles=True):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -258,7 +261,8 @@ class Context:
         self._p = _Params(KB, KR, KP, nu_pre, nu_post, self._params.ctypes.data_as(C.POINTER(C.c_double)),
                           BASES[basis], AGGREGATIONS[aggregation])
         self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
-                           (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL))
+                           (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL) |
+                           (0 if tiles else FLAG_NO_TILES))
         ws, ck = C.c_size_t(), C.c_size_t()
         _check(self.lib.mg_workspace_bytes(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
                                            C.byref(ws), C.byref(ck)), "mg_workspace_bytes")

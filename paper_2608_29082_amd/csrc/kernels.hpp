@@ -325,6 +325,268 @@ __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY*
   }
 }
 
+// ---------------------------------------------------------------- fused K-hop convolution over tiles
+// One workgroup computes all K Horner hops of Phi(x) = sum_k c_k M^k x for
+// the own nodes of a tile and kTileCols of the B columns, with the input on
+// the tile's K-hop neighbourhood and the intermediate hops in LDS (node
+// lists and local graph columns are built on the host).  Per launch the
+// input is read once (halo rows mostly from the L2) and the output written
+// once; a chain of K separate hops moves about 3K vectors.
+//
+// The kernel is persistent: each XCD takes a contiguous range of the
+// (tile, column group) items and its workgroups walk that range with a
+// stride, so neighbouring tiles (whose halos overlap) are processed close in
+// time on one L2.  Loads are software-pipelined in registers: while the
+// hops of one item run out of LDS, the input rows, outputs, local columns
+// and row scales of the next item and the node ids of the one after are in
+// flight.
+#ifndef MGL_TILE_THREADS
+#define MGL_TILE_THREADS 1024
+#endif
+#ifndef MGL_TILE_ROWS
+#define MGL_TILE_ROWS 2
+#endif
+#ifndef MGL_TILE_OWN_PER_THREAD
+#define MGL_TILE_OWN_PER_THREAD 1
+#endif
+#ifndef MGL_TILE_COLS
+#define MGL_TILE_COLS 16
+#endif
+constexpr int kTileMaxK = 8;
+constexpr int kTileCols = MGL_TILE_COLS;  // columns per item (4 per work-item)
+constexpr int kTileQ = kTileCols / 4;     // work-items (float4 slots) per node
+constexpr int kTileThreads = MGL_TILE_THREADS;
+constexpr int kTileNp = kTileThreads / kTileQ;             // nodes per pass
+constexpr int kTileRows = MGL_TILE_ROWS;                   // input rows per item <= kTileRows * kTileNp
+constexpr int kTileOwnPerThread = MGL_TILE_OWN_PER_THREAD; // own rows per item <= this * kTileNp
+constexpr int kTileMeta = 2;   // column chunks (4 slots) and row scales per item <= kTileMeta * kTileThreads
+
+struct TileDev {
+  int ntiles;
+  int KM;                   // halo depth of the node lists
+  int wg;                   // graph ELL width (multiple of 4)
+  int ngroups;              // B / kTileCols
+  const int* toff;          // ntiles + 1
+  const int* node;          // per tile: own nodes, then by distance
+  const int* cnt;           // ntiles x (KM + 1): nodes at distance <= d
+  const int* goff;          // ntiles + 1; goff / wg indexes the per-row arrays below
+  const uint16_t* lcol;     // local graph columns of the rows at distance <= KM - 1 (padding: own index)
+  const float* lidg;        // row scale of the aggregation (invdeg) of those rows
+  const float* lgw;         // edge weights in their slots (weighted / symmetric aggregation), or null
+};
+struct TileCoef {
+  float c[kTileMaxK + 1];
+};
+// LDS layout of one workgroup, in float4 units
+struct TileLds {
+  int y0, y1;               // hop buffers (x occupies [0, y0))
+  int col;                  // local columns (uint16) of the rows at distance <= K - 1
+  int idg;                  // their row scales (float)
+};
+
+__device__ __forceinline__ void ld4v(const float* p, float (&v)[4]) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld4v(const bf16_t* p, float (&v)[4]) {
+  const uint2 t = *reinterpret_cast<const uint2*>(p);
+  v[0] = __uint_as_float(t.x << 16); v[1] = __uint_as_float(t.x & 0xffff0000u);
+  v[2] = __uint_as_float(t.y << 16); v[3] = __uint_as_float(t.y & 0xffff0000u);
+}
+__device__ __forceinline__ void st4v(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4v(bf16_t* p, const float (&v)[4]) {
+  uint2 t;
+  t.x = (uint32_t)f2bf(v[0]).bits | ((uint32_t)f2bf(v[1]).bits << 16);
+  t.y = (uint32_t)f2bf(v[2]).bits | ((uint32_t)f2bf(v[3]).bits << 16);
+  *reinterpret_cast<uint2*>(p) = t;
+}
+
+// s += sum over the graph slots of local row r of [w] y_j; columns from LDS,
+// y in LDS, weights (WG) from the tile's slot array in global memory
+template <bool WG>
+__device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const float* __restrict__ gw, int r,
+                                            const float4* y, int q, float (&s)[4]) {
+  for (int k = 0; k < wg; k += 4) {
+    const ushort4 jj = *reinterpret_cast<const ushort4*>(lc + k);
+    const int j[4] = {jj.x, jj.y, jj.z, jj.w};
+    float ew[4];
+    if constexpr (WG) {
+      const float4 w4 = *reinterpret_cast<const float4*>(gw + k);
+      ew[0] = w4.x; ew[1] = w4.y; ew[2] = w4.z; ew[3] = w4.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float4 t = y[j[e] * kTileQ + q];
+      float v[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (WG) v[c] *= ew[e];
+        s[c] += (j[e] != r) ? v[c] : 0.f;
+      }
+    }
+  }
+}
+
+// Item scalars and node ids (fetched two items ahead)
+struct TileHead {
+  int t, g, cK, rows1, own, base, m0;
+  int nd[kTileRows];
+};
+// Item data in registers (fetched one item ahead)
+struct TileBody {
+  float xv[kTileRows][4];
+  float ov[kTileOwnPerThread][4];
+  uint2 lc[kTileMeta];
+  float li[kTileMeta];
+};
+
+//   mode 0: out = Phi(x)      mode 1: out = (oz ? 0 : out) + scale * Phi(x)
+// Arithmetic per node and column as in k_hop (same order of the sums).
+// Grid: a multiple of 8 blocks of kTileThreads; out must not alias x.
+template <bool WG, class TX, class TO>
+__global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, int K, TileCoef cf,
+                                                           const TX* __restrict__ x, TO* __restrict__ out, int mode,
+                                                           float scale, int oz, TileLds lo) {
+  extern __shared__ __align__(16) float4 conv_smem[];
+  const int per = gridDim.x >> 3;             // workgroups per XCD
+  const int xc = blockIdx.x & 7;              // blocks are dispatched round-robin over the XCDs
+  const int W = T.ntiles * T.ngroups;
+  const int i1 = (int)((long long)W * (xc + 1) / 8);
+  int it = (int)((long long)W * xc / 8) + (blockIdx.x >> 3);
+  if (it >= i1) return;
+  const int q = threadIdx.x % kTileQ;
+  const int p0 = threadIdx.x / kTileQ;
+  const int KM = T.KM, wg = T.wg;
+  float4* S = conv_smem;
+  uint2* LC2 = reinterpret_cast<uint2*>(conv_smem + lo.col);
+  const uint16_t* LC = reinterpret_cast<const uint16_t*>(conv_smem + lo.col);
+  float* LI = reinterpret_cast<float*>(conv_smem + lo.idg);
+  const bool rd_out = mode == 1 && !oz;
+
+  auto head = [&](int i, TileHead& h) {
+    h.t = i / T.ngroups;
+    h.g = i - h.t * T.ngroups;
+    const int* cn = T.cnt + (size_t)h.t * (KM + 1);
+    h.cK = cn[K];
+    h.rows1 = cn[K - 1];
+    h.own = cn[0];
+    h.base = T.toff[h.t];
+    h.m0 = T.goff[h.t];
+#pragma unroll
+    for (int e = 0; e < kTileRows; ++e) h.nd[e] = T.node[h.base + min(p0 + e * kTileNp, h.cK - 1)];
+  };
+  auto body = [&](const TileHead& h, TileBody& b) {
+    const int col = h.g * kTileCols + q * 4;
+#pragma unroll
+    for (int e = 0; e < kTileRows; ++e) ld4v(x + (size_t)h.nd[e] * B + col, b.xv[e]);
+#pragma unroll
+    for (int e = 0; e < kTileOwnPerThread; ++e) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b.ov[e][c] = 0.f;
+      if (rd_out && p0 + e * kTileNp < h.own) ld4v(out + (size_t)h.nd[e] * B + col, b.ov[e]);
+    }
+    const uint2* src = reinterpret_cast<const uint2*>(T.lcol + h.m0);
+    const float* ls = T.lidg + h.m0 / wg;
+    const int nch = h.rows1 * wg / 4;
+#pragma unroll
+    for (int e = 0; e < kTileMeta; ++e) {
+      const int c = threadIdx.x + e * kTileThreads;
+      if (c < nch) b.lc[e] = src[c];
+      if (c < h.rows1) b.li[e] = ls[c];
+    }
+  };
+
+  TileHead hc, hn;
+  TileBody bc;
+  head(it, hc);
+  body(hc, bc);
+  int itn = it + per;
+  if (itn < i1) head(itn, hn);
+  while (true) {
+    // item `it` into LDS
+#pragma unroll
+    for (int e = 0; e < kTileRows; ++e) {
+      const int r = p0 + e * kTileNp;
+      if (r < hc.cK) S[r * kTileQ + q] = make_float4(bc.xv[e][0], bc.xv[e][1], bc.xv[e][2], bc.xv[e][3]);
+    }
+    {
+      const int nch = hc.rows1 * wg / 4;
+#pragma unroll
+      for (int e = 0; e < kTileMeta; ++e) {
+        const int c = threadIdx.x + e * kTileThreads;
+        if (c < nch) LC2[c] = bc.lc[e];
+        if (c < hc.rows1) LI[c] = bc.li[e];
+      }
+    }
+    const TileHead h = hc;
+    float ov[kTileOwnPerThread][4];
+#pragma unroll
+    for (int e = 0; e < kTileOwnPerThread; ++e)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ov[e][c] = bc.ov[e][c];
+    __syncthreads();
+    // next item's data and the one after's node ids, in flight during the hops
+    const bool more = itn < i1;
+    if (more) {
+      body(hn, bc);
+      hc = hn;
+    }
+    const int itnn = itn + per;
+    if (itnn < i1) head(itnn, hn);
+    const int* cn = T.cnt + (size_t)h.t * (KM + 1);
+    const float* gw = WG ? T.lgw + h.m0 : nullptr;
+    // hops 1 .. K-1 on the nodes at distance <= K - hop
+    const float4* yin = S;
+    for (int hp = 1; hp < K; ++hp) {
+      const int rows = cn[K - hp];
+      const float a = hp == 1 ? cf.c[K] : 1.f;
+      const float cc = cf.c[K - hp];
+      float4* yo = conv_smem + ((hp & 1) ? lo.y0 : lo.y1);
+      for (int r = p0; r < rows; r += kTileNp) {
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, r, yin, q, s);
+        const float idg = LI[r];
+        const float4 xv = S[r * kTileQ + q];
+        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+        float o[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] = a * (idg * s[c]) + cc * xs[c];
+        yo[r * kTileQ + q] = make_float4(o[0], o[1], o[2], o[3]);
+      }
+      __syncthreads();
+      yin = yo;
+    }
+    // last hop on the own nodes, fused with the output update
+    const float a = K == 1 ? cf.c[1] : 1.f;
+    const float c0 = cf.c[0];
+    const int col = h.g * kTileCols + q * 4;
+#pragma unroll
+    for (int e = 0; e < kTileOwnPerThread; ++e) {
+      const int r = p0 + e * kTileNp;
+      if (r < h.own) {
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, r, yin, q, s);
+        const float idg = LI[r];
+        const float4 xv = S[r * kTileQ + q];
+        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+        float v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float w = a * (idg * s[c]) + c0 * xs[c];
+          v[c] = mode == 0 ? w : ov[e][c] + scale * w;
+        }
+        st4v(out + (size_t)h.nd[e] * B + col, v);
+      }
+    }
+    __syncthreads();
+    if (!more) break;
+    it = itn;
+    itn = itnn;
+  }
+}
+
 // out = (oz ? 0 : out) + alpha * x
 template <class C, class TX, class TO>
 __global__ __launch_bounds__(256) void k_axpy(int n, int B, int lbs, const TX* __restrict__ x, C alpha,

@@ -23,6 +23,7 @@
 #include "kernels.hpp"
 #include "krylov.hpp"
 #include "mgl.h"
+#include "tiles.hpp"
 
 using namespace mgl;
 
@@ -647,6 +648,10 @@ struct Engine final : EngineBase {
     unsigned blocks = 0;            // one work-item per (row, lane): n * LB / 256
     int rows4 = 0;                  // row-tile sweeps use 4 rows per work-item
     unsigned rblocks = 0;           // blocks of the row-tile sweeps
+    TileDev td{};                   // fused convolution tiles (td.ntiles == 0: none)
+    TileLds tlo[kTileMaxK + 1] = {};  // LDS layout of a fused convolution of order K
+    size_t tlds[kTileMaxK + 1] = {};  // and its size in bytes
+    unsigned tgrid[kTileMaxK + 1] = {};  // persistent grid (a multiple of 8 blocks)
   };
   std::vector<DL> d;
   Lvl<double> L64{};                // level-0 operator in FP64 (outer residual)
@@ -666,6 +671,8 @@ struct Engine final : EngineBase {
   int* hcount = nullptr;            // pinned host
   char* kr_own = nullptr;           // Krylov workspace allocated by the library
   size_t kr_own_bytes = 0;
+  char* tile_mem = nullptr;         // tile lists of the fused convolution, allocated by the library
+  size_t tile_mem_bytes = 0;
   // coarse tail (levels tail_lt .. J-1 in LDS, one workgroup per column)
   int tail_lt = -1;                 // shallowest level whose tail fits in LDS
   std::vector<TailArgs<C>> tails;   // launch arguments for start levels tail_lt .. J-2
@@ -679,6 +686,7 @@ struct Engine final : EngineBase {
   ~Engine() override {
     if (owns_ws && wsbase) (void)hipFree(wsbase);
     if (kr_own) (void)hipFree(kr_own);
+    if (tile_mem) (void)hipFree(tile_mem);
     if (hcount) (void)hipHostFree(hcount);
   }
 
@@ -922,6 +930,7 @@ struct Engine final : EngineBase {
     staging.shrink_to_fit();
     if (info != 0) return fail(MG_ERR_SHAPE, "coarsest matrix is singular (zero pivot in column " + std::to_string(info - 1) + ")");
     MG_TRY(setup_tail());
+    MG_TRY(setup_tiles(st));
     sizes.resize(J);
     widths.resize(J);
     for (int l = 0; l < J; ++l) { sizes[l] = pl.lv[l].n; widths[l] = pl.lv[l].off.w; }
@@ -985,6 +994,155 @@ struct Engine final : EngineBase {
     return MG_OK;
   }
 
+  // Tiles of the fused K-hop convolution (FP32/BF16 cycles, B a multiple of
+  // kTileCols): levels with at least kTileMinRows rows, halo depth the largest
+  // convolution order >= 2; tile shape shrunk until one workgroup's LDS fits
+  // kTileLds.  The lists live in library-owned device memory.
+#ifndef MGL_TILE_LDS_KB
+#define MGL_TILE_LDS_KB 160
+#endif
+#ifndef MGL_TILE_GROUP
+#define MGL_TILE_GROUP 4
+#endif
+  static constexpr int kTileMinRows = 4096;
+  static constexpr size_t kTileLds = MGL_TILE_LDS_KB * 1024;
+  mg_status setup_tiles(hipStream_t st) {
+    if constexpr (std::is_same<C, float>::value) return setup_tiles_f(st);
+    else return MG_OK;
+  }
+  mg_status setup_tiles_f(hipStream_t st) {
+    if ((pl.flags & MG_FLAG_NO_TILES) || B() % kTileCols != 0) return MG_OK;
+    int KM = 0;
+    for (int K : {pl.KB, pl.KR, pl.KP})
+      if (K >= 2) KM = std::max(KM, K);
+    if (KM < 2) return MG_OK;
+    // per-item limits of the kernel's register pipeline
+    auto fits = [&](const TilePlan& t) {
+      const int m = t.maxcnt[KM - 1];
+      return t.maxcnt[KM] <= kTileRows * kTileNp && t.maxcnt[0] <= kTileOwnPerThread * kTileNp &&
+             m * t.wg / 4 <= kTileMeta * kTileThreads && m <= kTileMeta * kTileThreads &&
+             tile_lds_bytes(t, KM, kTileCols) <= kTileLds;
+    };
+    std::vector<TilePlan> tp(pl.J);
+    std::vector<std::vector<float>> lidg(pl.J), lgw(pl.J);
+    size_t bytes = 0;
+    auto a256 = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
+    for (int l = 0; l < pl.J; ++l) {
+      const HLevel& H = pl.lv[l];
+      if (H.n < kTileMinRows) continue;
+      const HEll& g = H.graph_is_A ? H.off : H.graph;
+      for (int side : {16, 15, 14, 12, 10, 8}) {
+        if (build_tiles(H.n, g.ld, g.w, g.col.data(), KM, side, side, tp[l], MGL_TILE_GROUP) && fits(tp[l])) break;
+        tp[l] = TilePlan{};
+      }
+      const TilePlan& t = tp[l];
+      if (!t.ntiles) continue;
+      if (!check_tiles(H.n, g.ld, g.col.data(), t))
+        return fail(MG_ERR_STATE, "tile lists of level " + std::to_string(l) + " are inconsistent");
+      // row scales and edge weights of the listed rows, in the device's precision
+      lidg[l].resize(t.lcol.size() / t.wg);
+      if (wgt()) lgw[l].resize(t.lcol.size());
+      for (int k = 0; k < t.ntiles; ++k) {
+        const int* L = &t.node[t.toff[k]];
+        const int m0 = t.goff[k], rows = (t.goff[k + 1] - m0) / t.wg;
+        for (int r = 0; r < rows; ++r) {
+          lidg[l][m0 / t.wg + r] = (float)H.invdeg[L[r]];
+          if (wgt())
+            for (int s = 0; s < t.wg; ++s) lgw[l][m0 + (size_t)r * t.wg + s] = (float)H.gval[(size_t)s * g.ld + L[r]];
+        }
+      }
+      bytes += a256((t.ntiles + 1) * sizeof(int)) * 2 + a256(t.node.size() * sizeof(int)) +
+               a256(t.cnt.size() * sizeof(int)) + a256(t.lcol.size() * sizeof(uint16_t)) +
+               a256(lidg[l].size() * sizeof(float)) + a256(lgw[l].size() * sizeof(float));
+    }
+    if (!bytes) return MG_OK;
+    HIP_TRY(hipMalloc(&tile_mem, bytes));
+    tile_mem_bytes = bytes;
+    char* p = tile_mem;
+    bool ok = true;
+    auto put = [&](const void* src, size_t b) -> void* {
+      void* dst = p;
+      p += a256(b);
+      if (b && hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st) != hipSuccess) ok = false;
+      return dst;
+    };
+    size_t maxlds = 0;
+    for (int l = 0; l < pl.J; ++l) {
+      const TilePlan& t = tp[l];
+      if (!t.ntiles) continue;
+      TileDev& td = d[l].td;
+      td.ntiles = t.ntiles; td.KM = t.KM; td.wg = t.wg; td.ngroups = B() / kTileCols;
+      td.toff = static_cast<const int*>(put(t.toff.data(), t.toff.size() * sizeof(int)));
+      td.goff = static_cast<const int*>(put(t.goff.data(), t.goff.size() * sizeof(int)));
+      td.node = static_cast<const int*>(put(t.node.data(), t.node.size() * sizeof(int)));
+      td.cnt = static_cast<const int*>(put(t.cnt.data(), t.cnt.size() * sizeof(int)));
+      td.lcol = static_cast<const uint16_t*>(put(t.lcol.data(), t.lcol.size() * sizeof(uint16_t)));
+      td.lidg = static_cast<const float*>(put(lidg[l].data(), lidg[l].size() * sizeof(float)));
+      td.lgw = wgt() ? static_cast<const float*>(put(lgw[l].data(), lgw[l].size() * sizeof(float))) : nullptr;
+      for (int K = 2; K <= t.KM; ++K) {
+        const TileLayout y = tile_layout(t, K, kTileCols);
+        d[l].tlo[K] = TileLds{y.y0, y.y1, y.col, y.idg};
+        d[l].tlds[K] = tile_lds_bytes(t, K, kTileCols);
+        maxlds = std::max(maxlds, d[l].tlds[K]);
+      }
+    }
+    if (!ok) return fail(MG_ERR_HIP, "tile list upload failed");
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_conv_tile<false, TH, TU>), reinterpret_cast<const void*>(&k_conv_tile<true, TH, TU>),
+        reinterpret_cast<const void*>(&k_conv_tile<false, TU, TH>), reinterpret_cast<const void*>(&k_conv_tile<true, TU, TH>)};
+    if (maxlds > 65536)
+      for (const void* fn : fns)
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)maxlds));
+    // persistent grid: resident workgroups per XCD (the instances share one
+    // register and LDS footprint up to the weights; take the smallest)
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int l = 0; l < pl.J; ++l) {
+      if (!d[l].td.ntiles) continue;
+      const long W = (long)d[l].td.ntiles * d[l].td.ngroups;
+      for (int K = 2; K <= d[l].td.KM; ++K) {
+        int occ = 1 << 30;
+        for (const void* fn : fns) {
+          int nb = 0;
+          HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kTileThreads, d[l].tlds[K]));
+          occ = std::min(occ, nb);
+        }
+        if (occ < 1) return fail(MG_ERR_STATE, "fused convolution does not fit one compute unit");
+        const long per = std::min<long>((W + 7) / 8, (long)std::max(1, ncu / 8) * occ);
+        d[l].tgrid[K] = (unsigned)(8 * per);
+      }
+    }
+    HIP_TRY(hipStreamSynchronize(st));   // the host lists are freed on return
+    return MG_OK;
+  }
+
+  bool tiled(int l, int K, const void* x, const void* out) const {
+    const TileDev& td = d[l].td;
+    return td.ntiles > 0 && K >= 2 && K <= td.KM && x != out && ((uintptr_t)x % 16) == 0 &&
+           ((uintptr_t)out % 16) == 0;
+  }
+
+  // fused convolution: mode 0 out = Phi(x), mode 1 out = (oz ? 0 : out) + scale Phi(x)
+  template <class TX, class TO>
+  mg_status conv_tile(int l, const double* c, int K, const TX* x, TO* out, int mode, double scale, int oz,
+                      hipStream_t st) {
+    if constexpr (std::is_same<C, float>::value) {
+      const DL& D = d[l];
+      TileCoef cf{};
+      for (int k = 0; k <= K; ++k) cf.c[k] = (float)c[k];
+      const double bytes = nB(l) * (sizeof(TX) + sizeof(TO) * ((mode && !oz) ? 2 : 1)) +
+                           (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C);
+      TIMED(MG_KF_CONV, bytes,
+            WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
+                                        D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
+                                        D.tlo[K])));
+      return MG_OK;
+    } else {
+      return fail(MG_ERR_STATE, "fused convolution needs FP32 cycles");
+    }
+  }
+
   // e = LMG(A_l, f, 0) (fmg: e = FMG(f)) for levels l .. J-1 in one launch (l >= tail_lt)
   mg_status run_tail(int l, const TU* f, TU* e, hipStream_t st, int fmg = 0) {
     const int q = l - tail_lt;
@@ -1034,6 +1192,7 @@ struct Engine final : EngineBase {
       LAUNCH_OK();
       return MG_OK;
     }
+    if (tiled(l, K, x, u)) return conv_tile<TH, TU>(l, c, K, x, u, 1, scale, oz, st);
     const TH* yin = x;
     double a = c[K];
     TH* buf[2] = {D.ya, D.yb};
@@ -1812,7 +1971,7 @@ mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
 
 mg_status mg_timing_start(mg_ctx* c, int32_t fam, int32_t level) {
   g_err.clear();
-  if (!c || fam < MG_KF_NONE || fam > MG_KF_KRYLOV) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
+  if (!c || fam < MG_KF_NONE || fam > MG_KF_CONV) return fail(MG_ERR_INVALID_ARG, "bad context or kernel family");
   return c->e->timing_start(fam, level);
 }
 

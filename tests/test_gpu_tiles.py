@@ -1,0 +1,148 @@
+"""GPU parity of the fused K-hop convolution over LDS tiles.
+
+The fused kernel computes the same Horner hops as the chain of per-hop
+sweeps, in the same order of operations per node and column, so with FP32
+cycles its results are compared with the chain's bit for bit (contexts set
+up with and without tiles, same inputs); with BF16 intermediates the fused
+kernel keeps the hops in FP32 and is compared with the oracle.  Cases span
+up to a thousand tiles, ragged column groups (B = 16, 48, 64), the three
+aggregations in both bases, K from 2 to 4 and an unstructured mesh."""
+import numpy as np
+import pytest
+
+from mginputs import configs as C, hierarchy as H
+from oracle import lmg as O
+from tests.gpu_util import ctx_for, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 2e-5, "bf16": 3e-2}
+
+
+def _cases():
+    return [("blocks129", H.square_hierarchy(129, H.block_field(C.rng(7, 1, 1), 16, -3, 3))),
+            ("blocks257", H.square_hierarchy(257, H.block_field(C.rng(7, 1, 0), 16, -2, 2))),
+            ("lshape", H.lshape_hierarchy(C.rng(7, 4, 0), target_nodes=120, refinements=4))]
+
+
+CASES = _cases()
+IDS = [c[0] for c in CASES]
+
+
+def _pair(hier, flat, K, B, prec, **kw):
+    on = ctx_for(hier, flat, K, B, prec, **kw)
+    off = ctx_for(hier, flat, K, B, prec, tiles=False, **kw)
+    return on, off
+
+
+def _conv_launches(ctx, f, u):
+    import torch
+    ctx.timing_start("conv", -1)
+    ctx.vcycle(f, u)
+    torch.cuda.synchronize()
+    n, ms, by = ctx.timing_read()
+    ctx.timing_start(None)
+    return n
+
+
+@pytest.mark.parametrize("agg,basis", [("mean", "monomial"), ("mean", "chebyshev"), ("weighted", "monomial"),
+                                       ("sym", "chebyshev")])
+@pytest.mark.parametrize("K", [(3, 3, 3), (2, 2, 2), (4, 2, 3)])
+@pytest.mark.parametrize("name,hier", CASES, ids=IDS)
+def test_fused_conv_equals_hop_chain_fp32(agg, basis, K, name, hier):
+    import torch
+    J = hier.nlevels
+    B = 16
+    flat = C.random_params(J, *K, seed=101, spread=0.2)
+    g = C.rng(6, 21, 0)
+    f = g.standard_normal((hier.sizes[0], B))
+    u = g.standard_normal((hier.sizes[0], B))
+    on, off = _pair(hier, flat, K, B, "fp32", basis=basis, aggregation=agg)
+    outs = []
+    for ctx in (on, off):
+        ud = to_dev(u, torch.float32)
+        ctx.vcycle(to_dev(f, torch.float32), ud)
+        e = ctx.refine_step(to_dev(f, torch.float64), torch.zeros((hier.sizes[0], B), dtype=torch.float64,
+                                                                   device="cuda"))
+        outs.append((to_np(ud), to_np(e)))
+    n_on = _conv_launches(on, to_dev(f, torch.float32), to_dev(u, torch.float32))
+    n_off = _conv_launches(off, to_dev(f, torch.float32), to_dev(u, torch.float32))
+    d1 = float(np.abs(outs[0][0] - outs[1][0]).max())
+    d2 = float(np.abs(outs[0][1] - outs[1][1]).max())
+    print(f"{name} {agg}/{basis} K={K}: fused launches {n_on} (untiled {n_off}), max diff {d1:.1e} {d2:.1e}",
+          flush=True)
+    assert n_on > 0 and n_off == 0
+    assert d1 == 0.0 and d2 == 0.0
+    on.close(); off.close()
+
+
+@pytest.mark.parametrize("B", [16, 48, 64])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fused_conv_cycle_matches_oracle(prec, B):
+    import torch
+    name, hier = CASES[0]
+    J = hier.nlevels
+    flat = C.random_params(J, 3, 3, 3, seed=102, spread=0.2)
+    g = C.rng(6, 22, B)
+    f = g.standard_normal((hier.sizes[0], B))
+    u = g.standard_normal((hier.sizes[0], B))
+    want = O.lmg(O.make_levels(hier.A, hier.P, hier.R), O.unpack(flat, J, 3, 3, 3), 0, f, u)
+    ctx = ctx_for(hier, flat, 3, B, prec)
+    ud = to_dev(u, torch.float32)
+    ctx.vcycle(to_dev(f, torch.float32), ud)
+    err = rel(to_np(ud), want)
+    assert _conv_launches(ctx, to_dev(f, torch.float32), to_dev(u, torch.float32)) > 0
+    print(f"{name} {prec} B={B}: rel {err:.2e}", flush=True)
+    assert err <= TOL[prec]
+    ctx.close()
+
+
+def test_fused_conv_solve_and_gradient_equal_hop_chain():
+    """Stationary solve to 1e-8 (same cycle counts and iterates) and the
+    reverse sweep (its forward recomputation uses the fused kernel)."""
+    import torch
+    from paper_2608_29082_amd import autograd as AG
+    name, hier = CASES[0]
+    J = hier.nlevels
+    B = 16
+    flat = C.random_params(J, 3, 3, 3, seed=103, spread=0.1)
+    f = C.rng(6, 23, 0).standard_normal((hier.sizes[0], B))
+    res = []
+    for tiles in (True, False):
+        ctx = ctx_for(hier, C.identity_params(J, 3, 3, 3), 3, B, "fp32", tiles=tiles, max_outer=400)
+        u = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
+        info = ctx.solve(to_dev(f, torch.float64), u)
+        ctx.close()
+        ctxb = ctx_for(hier, flat, 3, B, "fp32", tiles=tiles, backward=True)
+        th = torch.tensor(flat, dtype=torch.float64, requires_grad=True)
+        L = AG.unrolled_loss(ctxb, th, to_dev(f, torch.float64), cycles=2)
+        L.backward()
+        ctxb.close()
+        res.append((info.iters.copy(), to_np(u), L.item(), th.grad.numpy().copy()))
+    print(f"iters {res[0][0].max()} / {res[1][0].max()}, loss {res[0][2]:.6e} / {res[1][2]:.6e}", flush=True)
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+    assert np.array_equal(res[0][3], res[1][3])
+
+
+def test_fused_conv_unaligned_vectors_use_hop_chain():
+    """Vectors that are not 16-byte aligned take the per-hop sweeps (same result)."""
+    import torch
+    name, hier = CASES[0]
+    J = hier.nlevels
+    B = 16
+    flat = C.random_params(J, 3, 3, 3, seed=104, spread=0.2)
+    g = C.rng(6, 24, 0)
+    n = hier.sizes[0]
+    f = g.standard_normal((n, B))
+    u = g.standard_normal((n, B))
+    ctx = ctx_for(hier, flat, 3, B, "fp32")
+    ref = to_dev(u, torch.float32)
+    ctx.vcycle(to_dev(f, torch.float32), ref)
+    buf = torch.zeros(n * B + 1, dtype=torch.float32, device="cuda")
+    ud = buf[1:].view(n, B)
+    ud.copy_(to_dev(u, torch.float32))
+    ctx.vcycle(to_dev(f, torch.float32), ud)
+    assert float((ud - ref).abs().max()) == 0.0
+    ctx.close()
