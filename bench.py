@@ -9,7 +9,10 @@ relative residual of 1e-8 per column.  One step = one batched solve of the
 
 Also reported: the plain FP64 GPU V-cycle (classical components, K = 0) on the
 same hierarchy and right-hand sides, the roofline of the dominant kernel
-family (HIP events around each of its launches in the timed region), flexible
+family (HIP events around each of its launches in the timed region), the
+per-family time of the finest level's kernels, the same solve with the
+graph convolutions as chains of per-hop sweeps instead of the fused LDS-tile
+kernel, flexible
 GMRES with the learned and the classical cycle (or FMG) as preconditioner on
 the same inputs, the request loop, and the CPU FP64 oracle timed on a bounded
 sample.
@@ -41,13 +44,16 @@ def parse():
     ap.add_argument("--params", default="default",
                     help="'default' (parameters trained on this workload's operator, shipped with the package), "
                          "'identity', or a .npy parameter file")
-    ap.add_argument("--roofline-family", default="hop")
+    ap.add_argument("--roofline-family", default="conv",
+                    help="kernel family of the roofline entry (conv: the fused LDS-tile convolution)")
     ap.add_argument("--roofline-level", type=int, default=0)
     ap.add_argument("--max-outer", type=int, default=20000)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the convolution-variant and Darcy sections")
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="run the convolutions as chains of per-hop sweeps (no fused LDS-tile kernel)")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length of the Krylov comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=60,
@@ -95,7 +101,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=B,
-                     max_outer=args.max_outer, check_every=25, stream=stream)
+                     max_outer=args.max_outer, check_every=25, stream=stream, tiles=not args.no_tiles)
     f = torch.tensor(w.f, dtype=torch.float64, device=dev)
     u = torch.zeros_like(f)
 
@@ -162,6 +168,25 @@ def main():
             "alg_bytes_per_launch": kbytes / max(launches, 1),
         },
     }
+
+    out["level0_kernels"] = level0_kernels(ctx, f)
+    if not args.no_tiles and args.precision != "fp64":
+        # the same solve with every convolution as a chain of per-hop sweeps
+        hctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=B,
+                          max_outer=args.max_outer, check_every=25, stream=stream, tiles=False)
+        uh = torch.zeros_like(f)
+        hctx.solve(f, uh)
+        uh.zero_()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        hinfo = hctx.solve(f, uh)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        out["per_hop_sweeps"] = {"value": B / (tb - ta), "unit": "solves/s", "iters_max": int(hinfo.iters.max()),
+                                 "converged": bool(hinfo.code == 0),
+                                 "level0_kernels": level0_kernels(hctx, f)}
+        hctx.close()
+        print(f"# per-hop sweeps: {out['per_hop_sweeps']['value']:.1f} solves/s", file=sys.stderr, flush=True)
 
     if not args.no_plain:
         # plain FP64 GPU V-cycle: classical components (K = 0, identity), same inputs
@@ -233,8 +258,9 @@ def krylov(args, ctxs, f, w, h, B):
 def conv_variants(args, h, f, B, stream):
     """Per-cycle cost of the convolution variants on the same hierarchy and
     right-hand sides (identity parameters, so every variant runs the same
-    number of hops): ms per refinement step and the finest-level hop's
-    achieved bandwidth (algorithmic bytes over HIP-event time)."""
+    number of hops): ms per refinement step and the finest-level fused
+    convolution's time and achieved bandwidth (algorithmic bytes over
+    HIP-event time)."""
     import torch
     from paper_2608_29082_amd import binding as Bd
     from paper_2608_29082_amd import params as PR
@@ -245,7 +271,7 @@ def conv_variants(args, h, f, B, stream):
                          precision=args.precision, nrhs=B, stream=stream, basis=basis, aggregation=agg)
         u = torch.zeros_like(f)
         ctx.refine_step(f, u, u)
-        ctx.timing_start("hop", 0)
+        ctx.timing_start("conv", 0)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for _ in range(10):
@@ -253,9 +279,11 @@ def conv_variants(args, h, f, B, stream):
         torch.cuda.synchronize()
         tb = time.perf_counter()
         n, ms, by = ctx.timing_read()
+        ctx.timing_start(None)
         ctx.close()
-        out[f"{agg}_{basis}"] = {"ms_per_cycle": 1e2 * (tb - ta), "hop_level0_GBps": by / (ms * 1e-3) / 1e9,
-                                 "hop_level0_us": 1e3 * ms / max(n, 1)}
+        out[f"{agg}_{basis}"] = {"ms_per_cycle": 1e2 * (tb - ta),
+                                 "conv_level0_GBps": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                                 "conv_level0_us": 1e3 * ms / n if n else None}
         print(f"# variant {agg}/{basis}: {out[f'{agg}_{basis}']}", file=sys.stderr, flush=True)
     return out
 
@@ -298,19 +326,49 @@ def darcy(args):
     return out
 
 
+TRAFFIC_FILES = {("conv", 0): "k_conv_tile_level0_diffusion513_traffic.json",
+                 ("hop", 0): "k_hop_level0_diffusion513_traffic.json"}
+
+
+def kernel_sources_sha256():
+    """SHA-256 over the kernel and tiling sources (kernels.hpp, tiles.hpp)."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for name in ("kernels.hpp", "tiles.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_29082_amd", "csrc", name), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
 def counter_traffic(kernel_family, level):
     """Calibrated HBM bytes per dispatch of the timed kernel from the committed
-    PMC measurement, or None if the kernel source changed since it was taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_hop_level0_diffusion513_traffic.json")
-    if kernel_family != "hop" or level != 0 or not os.path.exists(path):
+    PMC measurement, or None if the kernel sources changed since it was taken."""
+    name = TRAFFIC_FILES.get((kernel_family, level))
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = os.path.join(ROOT, "paper_2608_29082_amd", "csrc", "kernels.hpp")
-    with open(src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    return rec["bytes_per_dispatch"] if rec.get("kernels_hpp_sha256") == digest else None
+    return rec["bytes_per_dispatch"] if rec.get("kernel_sources_sha256") == kernel_sources_sha256() else None
+
+
+def level0_kernels(ctx, f, steps=3):
+    """Per kernel family on the finest level: launches per refinement step,
+    microseconds per launch and achieved algorithmic GB/s (HIP events), over
+    `steps` refinement steps from zero."""
+    import torch
+    out = {}
+    u = torch.zeros_like(f)
+    for fam in ("conv", "hop", "resid", "restrict", "prolong", "outer"):
+        ctx.timing_start(fam, 0)
+        u.zero_()
+        for _ in range(steps):
+            ctx.refine_step(f, u, u)
+        n, ms, by = ctx.timing_read()
+        if n:
+            out[fam] = {"launches_per_step": n // steps, "us": 1e3 * ms / n, "GBps": by / (ms * 1e-3) / 1e9}
+    ctx.timing_start(None)
+    return out
 
 
 def serving(args):

@@ -341,13 +341,13 @@ __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY*
 // and row scales of the next item and the node ids of the one after are in
 // flight.
 #ifndef MGL_TILE_THREADS
-#define MGL_TILE_THREADS 1024
+#define MGL_TILE_THREADS 512
 #endif
 #ifndef MGL_TILE_ROWS
-#define MGL_TILE_ROWS 2
+#define MGL_TILE_ROWS 4
 #endif
 #ifndef MGL_TILE_OWN_PER_THREAD
-#define MGL_TILE_OWN_PER_THREAD 1
+#define MGL_TILE_OWN_PER_THREAD 2
 #endif
 #ifndef MGL_TILE_COLS
 #define MGL_TILE_COLS 16

@@ -999,7 +999,7 @@ struct Engine final : EngineBase {
   // convolution order >= 2; tile shape shrunk until one workgroup's LDS fits
   // kTileLds.  The lists live in library-owned device memory.
 #ifndef MGL_TILE_LDS_KB
-#define MGL_TILE_LDS_KB 160
+#define MGL_TILE_LDS_KB 80
 #endif
 #ifndef MGL_TILE_GROUP
 #define MGL_TILE_GROUP 4
@@ -1238,6 +1238,14 @@ struct Engine final : EngineBase {
             WG_SPLIT(RESTRICT_LAUNCH(cb, (WGv, C, TU, TU, TU), D.R, D.L, B(), lbs, 1,
                                (const TU*)D.r, (C)c[1], (const TU*)D.r, (C)c[0], (const TU*)nullptr,
                                (const TU*)nullptr, 0, (C)1, rc)));
+      return MG_OK;
+    }
+    if (tiled(l, K, D.r, D.ya)) {
+      // y = Phi_R(r) in one fused launch, then the plain restriction of y
+      MG_TRY(conv_tile<TU, TH>(l, c, K, D.r, D.ya, 0, 1.0, 0, st));
+      TIMED(MG_KF_RESTRICT, nB(l) * sizeof(TH) + bytes_X(D.R) + nB(l + 1) * sizeof(TU),
+            RESTRICT_LAUNCH(cb, (false, C, TU, TH, TU), D.R, D.L, B(), lbs, 0, (const TH*)D.ya, (C)0,
+                            (const TU*)nullptr, (C)0, (const TU*)nullptr, (const TU*)nullptr, 0, (C)1, rc));
       return MG_OK;
     }
     MG_TRY(hop<TU, TU, TH>(l, D.r, c[K], D.r, c[K - 1], D.ya, 0, 0.0, 0, st));
