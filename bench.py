@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="skip the convolution-variant and Darcy sections")
     ap.add_argument("--no-tiles", action="store_true",
                     help="run the convolutions as chains of per-hop sweeps (no fused LDS-tile kernel)")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the per-family finest-level timing and the per-hop-sweep comparison")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length of the Krylov comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=60,
@@ -169,8 +171,9 @@ def main():
         },
     }
 
-    out["level0_kernels"] = level0_kernels(ctx, f)
-    if not args.no_tiles and args.precision != "fp64":
+    if not args.no_ablation:
+        out["level0_kernels"] = level0_kernels(ctx, f)
+    if not args.no_ablation and not args.no_tiles and args.precision != "fp64":
         # the same solve with every convolution as a chain of per-hop sweeps
         hctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=B,
                           max_outer=args.max_outer, check_every=25, stream=stream, tiles=False)

@@ -444,8 +444,9 @@ struct TileBody {
 
 //   mode 0: out = Phi(x)      mode 1: out = (oz ? 0 : out) + scale * Phi(x)
 // Arithmetic per node and column as in k_hop (same order of the sums).
-// Grid: a multiple of 8 blocks of kTileThreads; out must not alias x.
-template <bool WG, class TX, class TO>
+// Grid: a multiple of 8 blocks of kTileThreads; out must not alias x.  FINE
+// only tags finest-level launches with their own symbol (same code).
+template <bool FINE, bool WG, class TX, class TO>
 __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, int K, TileCoef cf,
                                                            const TX* __restrict__ x, TO* __restrict__ out, int mode,
                                                            float scale, int oz, TileLds lo) {

@@ -1088,8 +1088,14 @@ struct Engine final : EngineBase {
     }
     if (!ok) return fail(MG_ERR_HIP, "tile list upload failed");
     const void* fns[] = {
-        reinterpret_cast<const void*>(&k_conv_tile<false, TH, TU>), reinterpret_cast<const void*>(&k_conv_tile<true, TH, TU>),
-        reinterpret_cast<const void*>(&k_conv_tile<false, TU, TH>), reinterpret_cast<const void*>(&k_conv_tile<true, TU, TH>)};
+        reinterpret_cast<const void*>(&k_conv_tile<false, false, TH, TU>),
+        reinterpret_cast<const void*>(&k_conv_tile<false, true, TH, TU>),
+        reinterpret_cast<const void*>(&k_conv_tile<false, false, TU, TH>),
+        reinterpret_cast<const void*>(&k_conv_tile<false, true, TU, TH>),
+        reinterpret_cast<const void*>(&k_conv_tile<true, false, TH, TU>),
+        reinterpret_cast<const void*>(&k_conv_tile<true, true, TH, TU>),
+        reinterpret_cast<const void*>(&k_conv_tile<true, false, TU, TH>),
+        reinterpret_cast<const void*>(&k_conv_tile<true, true, TU, TH>)};
     if (maxlds > 65536)
       for (const void* fn : fns)
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)maxlds));
@@ -1133,10 +1139,16 @@ struct Engine final : EngineBase {
       for (int k = 0; k <= K; ++k) cf.c[k] = (float)c[k];
       const double bytes = nB(l) * (sizeof(TX) + sizeof(TO) * ((mode && !oz) ? 2 : 1)) +
                            (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C);
-      TIMED(MG_KF_CONV, bytes,
-            WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
-                                        D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
-                                        D.tlo[K])));
+      if (l == 0)
+        TIMED(MG_KF_CONV, bytes,
+              WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<true, WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
+                                          D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
+                                          D.tlo[K])));
+      else
+        TIMED(MG_KF_CONV, bytes,
+              WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<false, WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
+                                          D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
+                                          D.tlo[K])));
       return MG_OK;
     } else {
       return fail(MG_ERR_STATE, "fused convolution needs FP32 cycles");
