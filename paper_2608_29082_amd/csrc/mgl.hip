@@ -929,16 +929,17 @@ struct Engine final : EngineBase {
     staging.clear();
     staging.shrink_to_fit();
     if (info != 0) return fail(MG_ERR_SHAPE, "coarsest matrix is singular (zero pivot in column " + std::to_string(info - 1) + ")");
-    MG_TRY(setup_tail());
     MG_TRY(setup_tiles(st));
+    MG_TRY(setup_tail());
     sizes.resize(J);
     widths.resize(J);
     for (int l = 0; l < J; ++l) { sizes[l] = pl.lv[l].n; widths[l] = pl.lv[l].off.w; }
     return MG_OK;
   }
 
-  // Choose the shallowest start level whose coarse tail fits the workgroup's
-  // LDS, and prepare the launch arguments for every start level below it.
+  // Choose the shallowest start level without fused-convolution tiles whose
+  // coarse tail fits the workgroup's LDS, and prepare the launch arguments
+  // for every start level below it.
   mg_status setup_tail() {
     tail_lt = -1;
     tails.clear();
@@ -954,8 +955,12 @@ struct Engine final : EngineBase {
       for (int l = lt; l < J; ++l) elems += 2 * r4(pl.lv[l].n);
       return (size_t)elems * sizeof(C);
     };
+    // levels with fused-convolution tiles keep their per-level launches
     for (int lt = 0; lt <= J - 2; ++lt)
-      if (J - lt <= kTailMaxLevels && bytes_from(lt) <= (size_t)maxlds) { tail_lt = lt; break; }
+      if (J - lt <= kTailMaxLevels && bytes_from(lt) <= (size_t)maxlds && d[lt].td.ntiles == 0) {
+        tail_lt = lt;
+        break;
+      }
     if (tail_lt < 0) return MG_OK;
     const void* tail_fn = wgt() ? reinterpret_cast<const void*>(&k_tail<1, true, C, TU>)
                                 : reinterpret_cast<const void*>(&k_tail<1, false, C, TU>);
@@ -995,7 +1000,8 @@ struct Engine final : EngineBase {
   }
 
   // Tiles of the fused K-hop convolution (FP32/BF16 cycles, B a multiple of
-  // kTileCols): levels with at least kTileMinRows rows, halo depth the largest
+  // kTileCols): levels with at least kTileMinRows rows (the coarse tail then
+  // starts below them), halo depth the largest
   // convolution order >= 2; tile shape shrunk until one workgroup's LDS fits
   // kTileLds.  The lists live in library-owned device memory.
 #ifndef MGL_TILE_LDS_KB
@@ -1004,7 +1010,10 @@ struct Engine final : EngineBase {
 #ifndef MGL_TILE_GROUP
 #define MGL_TILE_GROUP 4
 #endif
-  static constexpr int kTileMinRows = 4096;
+#ifndef MGL_TILE_MIN_ROWS
+#define MGL_TILE_MIN_ROWS 2048
+#endif
+  static constexpr int kTileMinRows = MGL_TILE_MIN_ROWS;
   static constexpr size_t kTileLds = MGL_TILE_LDS_KB * 1024;
   mg_status setup_tiles(hipStream_t st) {
     if constexpr (std::is_same<C, float>::value) return setup_tiles_f(st);

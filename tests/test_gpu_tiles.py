@@ -3,8 +3,10 @@
 The fused kernel computes the same Horner hops as the chain of per-hop
 sweeps, in the same order of operations per node and column, so with FP32
 cycles its results are compared with the chain's bit for bit (contexts set
-up with and without tiles, same inputs); with BF16 intermediates the fused
-kernel keeps the hops in FP32 and is compared with the oracle.  Cases span
+up with and without tiles, same inputs, per-level sweeps on every level);
+the default configuration (coarse LDS tail below the tiled levels) and the
+BF16 cycles, whose fused kernel keeps the hops in FP32, are compared with the
+oracle.  Cases span
 up to a thousand tiles, ragged column groups (B = 16, 48, 64), the three
 aggregations in both bases, K from 2 to 4 and an unstructured mesh."""
 import numpy as np
@@ -30,8 +32,10 @@ IDS = [c[0] for c in CASES]
 
 
 def _pair(hier, flat, K, B, prec, **kw):
-    on = ctx_for(hier, flat, K, B, prec, **kw)
-    off = ctx_for(hier, flat, K, B, prec, tiles=False, **kw)
+    # the coarse LDS tail starts below the tiled levels, so it would start at
+    # different levels in the two contexts; compare with per-level sweeps only
+    on = ctx_for(hier, flat, K, B, prec, tail=False, **kw)
+    off = ctx_for(hier, flat, K, B, prec, tiles=False, tail=False, **kw)
     return on, off
 
 
@@ -91,9 +95,13 @@ def test_fused_conv_cycle_matches_oracle(prec, B):
     ud = to_dev(u, torch.float32)
     ctx.vcycle(to_dev(f, torch.float32), ud)
     err = rel(to_np(ud), want)
+    # a refinement step from zero: the cycle from a zero iterate, with the coarse tail
+    e = ctx.refine_step(to_dev(f, torch.float64), torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda"))
+    err2 = rel(to_np(e), O.lmg(O.make_levels(hier.A, hier.P, hier.R), O.unpack(flat, J, 3, 3, 3), 0, f,
+                               np.zeros_like(f)))
     assert _conv_launches(ctx, to_dev(f, torch.float32), to_dev(u, torch.float32)) > 0
-    print(f"{name} {prec} B={B}: rel {err:.2e}", flush=True)
-    assert err <= TOL[prec]
+    print(f"{name} {prec} B={B}: cycle rel {err:.2e}, refinement step rel {err2:.2e}", flush=True)
+    assert err <= TOL[prec] and err2 <= TOL[prec]
     ctx.close()
 
 
@@ -109,11 +117,11 @@ def test_fused_conv_solve_and_gradient_equal_hop_chain():
     f = C.rng(6, 23, 0).standard_normal((hier.sizes[0], B))
     res = []
     for tiles in (True, False):
-        ctx = ctx_for(hier, C.identity_params(J, 3, 3, 3), 3, B, "fp32", tiles=tiles, max_outer=400)
+        ctx = ctx_for(hier, C.identity_params(J, 3, 3, 3), 3, B, "fp32", tiles=tiles, tail=False, max_outer=400)
         u = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
         info = ctx.solve(to_dev(f, torch.float64), u)
         ctx.close()
-        ctxb = ctx_for(hier, flat, 3, B, "fp32", tiles=tiles, backward=True)
+        ctxb = ctx_for(hier, flat, 3, B, "fp32", tiles=tiles, tail=False, backward=True)
         th = torch.tensor(flat, dtype=torch.float64, requires_grad=True)
         L = AG.unrolled_loss(ctxb, th, to_dev(f, torch.float64), cycles=2)
         L.backward()
