@@ -187,48 +187,6 @@ __device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ c
   }
 }
 
-// ell_dot over the values w = x + 1.0 * e (formed in C before the product,
-// as an in-place update x += 1.0 * e would store them)
-template <bool WIDE, bool CONSEC, int NR, class C, class TX, class TE>
-__device__ __forceinline__ void ell_dot_sum(int W, int ld, const int* __restrict__ col, const C* __restrict__ val,
-                                            const int (&row)[NR], int row0, const TX* __restrict__ x,
-                                            const TE* __restrict__ e, int B, int b, C (&s)[NR]) {
-  for (int k = 0; k < W; k += 4) {
-    int j[NR][4];
-    C v[NR][4];
-    if constexpr (CONSEC && NR == 4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const V4<int> jj = ld4(col + (size_t)(k + q) * ld + row0);
-        const V4<C> vv = ld4(val + (size_t)(k + q) * ld + row0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          j[r][q] = uni<WIDE>(jj.v[r]);
-          v[r][q] = uni<WIDE>(vv.v[r]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const size_t o = (size_t)(k + q) * ld + row[r];
-          j[r][q] = uni<WIDE>(col[o]);
-          v[r][q] = uni<WIDE>(val[o]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const size_t o = (size_t)j[r][q] * B + b;
-        C w = ldc<C>(x + o);
-        w += C(1) * ldc<C>(e + o);
-        s[r] += v[r][q] * w;
-      }
-  }
-}
-
 // Neighbour sums over the graph (W multiple of 4, padding col == row):
 //   TRANS = false: s[r] += sum_{j in N(row)} [w_{row,j}] y_j         ((G y) = r_row * s)
 //   TRANS = true:  s[r] += sum_{j in N(row)} [w_{row,j}] r_j y_j     ((G^T y) = s, symmetric
@@ -815,18 +773,11 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* W, int* in
 // Block b (XCD-remapped) owns the contiguous rows [b*chunk, (b+1)*chunk) and
 // walks them four rows per work-item at a time, so neighbour rows are reused
 // from L2; the summation order is fixed (deterministic).  B <= 256.
-//
-// With UPD the iterate is first advanced by the cycle's correction e in the
-// columns still active (act[b] != 0): w = u + e, written to uo (not u: other
-// blocks read u's rows), and r = f - A w with every w formed as k_update
-// forms it (one FP64 rounding), so the result equals k_update followed by
-// this kernel bit for bit.
-template <bool WIDE, bool UPD, class TR, class TE>
+template <bool WIDE, class TR>
 __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, int chunk,
                                                      const double* __restrict__ f, const double* __restrict__ u,
                                                      double* __restrict__ r64, TR* __restrict__ rc,
-                                                     double* __restrict__ part, const TE* __restrict__ e,
-                                                     const int* __restrict__ act, double* __restrict__ uo) {
+                                                     double* __restrict__ part) {
   __shared__ double red[256 * 4];
   const int LB = 1 << lbs, rpb = 256 >> lbs;
   const int lane = threadIdx.x & (LB - 1), rg = uni<WIDE>((int)(threadIdx.x >> lbs));
@@ -850,25 +801,19 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
     row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
-      const bool up = UPD && act[b] != 0;
       // own f and u loaded first, consumed after the off-diagonal gathers
       double fv[4], uv[4], s[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         fv[r] = f[(size_t)row[r] * B + b];
         uv[r] = u[(size_t)row[r] * B + b];
-        if (up) uv[r] += 1.0 * (double)e[(size_t)row[r] * B + b];
         s[r] = 0.0;
       }
-      if (up)
-        ell_dot_sum<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, e, B, b, s);
-      else
-        ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
+      ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (!ok[r]) continue;
         const size_t o = (size_t)row[r] * B + b;
-        if (UPD) uo[o] = uv[r];
         const double v = fv[r] - (s[r] + dg[r] * uv[r]);
         if (r64) r64[o] = v;
         if (rc) put(rc + o, v);

@@ -1358,31 +1358,18 @@ struct Engine final : EngineBase {
     return (unsigned)((pl.lv[0].n + c - 1) / c);
   }
 
-  // r = f - A u (FP64); with e: first w = u + e in the active columns
-  // (written to uo), then r = f - A w
   template <class TR>
-  mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st,
-                        const TU* e = nullptr, double* uo = nullptr) {
+  mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st) {
     const int l = 0;   // timing level of the finest-level outer residual
     const unsigned g = outer_blocks();
     const double nb0 = (double)L64.n * B();
     const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
-                      (rc ? nb0 * sizeof(TR) : 0.0) + (e ? nb0 * (sizeof(TU) + 8) : 0.0);
-    const int* act = st_ptr();
-    if (e)
-      TIMED(MG_KF_OUTER, ob,
-            if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, true, TR, TU>), dim3(g), dim3(256), 0, st, L64, B(),
-                                             lbs, outer_chunk(), f, u, r64, rc, part, e, act, uo);
-            else hipLaunchKernelGGL((k_outer_resid<false, true, TR, TU>), dim3(g), dim3(256), 0, st, L64, B(), lbs,
-                                    outer_chunk(), f, u, r64, rc, part, e, act, uo));
-    else
-      TIMED(MG_KF_OUTER, ob,
-            if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, false, TR, TU>), dim3(g), dim3(256), 0, st, L64,
-                                             B(), lbs, outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr,
-                                             (const int*)nullptr, (double*)nullptr);
-            else hipLaunchKernelGGL((k_outer_resid<false, false, TR, TU>), dim3(g), dim3(256), 0, st, L64, B(), lbs,
-                                    outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr, (const int*)nullptr,
-                                    (double*)nullptr));
+                      (rc ? nb0 * sizeof(TR) : 0.0);
+    TIMED(MG_KF_OUTER, ob,
+          if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs,
+                                           outer_chunk(), f, u, r64, rc, part);
+          else hipLaunchKernelGGL((k_outer_resid<false, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, outer_chunk(),
+                                  f, u, r64, rc, part));
     if (nrm) {
       hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), nrm);
       LAUNCH_OK();
@@ -1414,19 +1401,9 @@ struct Engine final : EngineBase {
     hipLaunchKernelGGL((k_fill0<double>), dim3(nblocks((long)n0 * B())), dim3(256), 0, st, (long)n0 * B(), dbuf);
     LAUNCH_OK();
     MG_TRY(outer_resid<TU>(f, dbuf, nullptr, (TU*)nullptr, fnorm, st));
-    // The update u += e of cycle m runs inside the residual of step m + 1
-    // (same values as k_update followed by the residual); the iterate moves
-    // between u and dbuf and ends in u.
     int m = 0;
-    double* cur = u;
-    double* alt = dbuf;
     for (; m < pl.max_outer; ++m) {
-      if (m == 0) {
-        MG_TRY(outer_resid<TU>(f, cur, nullptr, r0, norms, st));
-      } else {
-        MG_TRY(outer_resid<TU>(f, cur, nullptr, r0, norms, st, e0, alt));
-        std::swap(cur, alt);
-      }
+      MG_TRY(outer_resid<TU>(f, u, nullptr, r0, norms, st));
       hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf,
                          m == 0 ? 1 : 0);
       LAUNCH_OK();
@@ -1436,15 +1413,16 @@ struct Engine final : EngineBase {
         if (hcount[0] == 0) break;
       }
       MG_TRY(fwd(0, r0, e0, 1, nullptr, st));
+      hipLaunchKernelGGL((k_update<TU>), dim3(d[0].blocks), dim3(256), 0, st, n0, B(), lbs, (const TU*)e0, u,
+                         (const int*)st_ptr(), 1.0);
+      LAUNCH_OK();
     }
     if (m == pl.max_outer) {
-      // the last cycle's update, and its residual
-      MG_TRY(outer_resid<TU>(f, cur, nullptr, (TU*)nullptr, norms, st, e0, alt));
-      std::swap(cur, alt);
+      // account for the last iterate
+      MG_TRY(outer_resid<TU>(f, u, nullptr, (TU*)nullptr, norms, st));
       hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf, 0);
       LAUNCH_OK();
     }
-    if (cur != u) MG_TRY(copy((const double*)cur, u, (long)n0 * B(), st));
     std::vector<int> hst(3 * B() + 1);
     std::vector<double> hn(B()), hf(B());
     HIP_TRY(hipMemcpyAsync(hst.data(), st_ptr(), hst.size() * sizeof(int), hipMemcpyDeviceToHost, st));
