@@ -139,6 +139,7 @@ def main():
     value = solves / elapsed if converged_all else 0.0
     avg_ms = kms / max(launches, 1)
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    copy_gbps = device_copy_gbps()
 
     out = {
         "metric": "solves/sec at 1e-8 rel. residual vs plain GMG; HBM GB/s; p50/p99 solve latency",
@@ -165,6 +166,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel_family": args.roofline_family, "level": args.roofline_level,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps if copy_gbps else None,
             "traffic": counter_traffic(args.roofline_family, args.roofline_level),
             "launches": launches, "avg_launch_us": 1e3 * avg_ms,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
@@ -204,6 +206,8 @@ def main():
         out["plain_fp64_gmg"] = {"value": B / (tb - ta), "unit": "solves/s", "ms_per_solve_batch": 1e3 * (tb - ta),
                                  "iters_max": int(pinfo.iters.max()), "converged": bool(pinfo.code == 0)}
         out["speedup_vs_plain_fp64_gmg"] = value / out["plain_fp64_gmg"]["value"]
+        out["learned_fp64"] = learned_fp64(args, h, params, f, B, stream)
+        out["learned_unbatched"] = unbatched(args, h, params, f, stream)
         if not args.no_krylov:
             out["krylov"] = krylov(args, {"learned_" + args.precision: ctx, "classical_fp64": pctx}, f, w, h, B)
         pctx.close()
@@ -410,6 +414,67 @@ def serving(args):
         r.pop("by_side", None)
     print(f"# serving: {json.dumps(runs)}", file=sys.stderr, flush=True)
     return {"requests_per_run": args.serving_requests, "sides": [65, 129, 257, 513, 1025], **runs}
+
+
+def device_copy_gbps(mib=256, reps=5):
+    """Read + write bandwidth of a plain device-to-device copy of `mib` MiB
+    (torch's copy kernel, HIP events), the practical streaming ceiling."""
+    import torch
+    a = torch.empty(mib * 2**20 // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def learned_fp64(args, h, params, f, B, stream):
+    """The same learned parameters with FP64 cycles (no mixed precision), same
+    right-hand sides: the mixed form's gain at equal parameters."""
+    import torch
+    from paper_2608_29082_amd import binding as Bd
+    ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision="fp64", nrhs=B,
+                     max_outer=args.max_outer, check_every=25, stream=stream)
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    info = ctx.solve(f, u)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ctx.close()
+    out = {"value": B / (tb - ta), "unit": "solves/s", "iters_max": int(info.iters.max()),
+           "converged": bool(info.code == 0)}
+    print(f"# learned fp64: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def unbatched(args, h, params, f, stream, cols=4):
+    """The learned mixed form solving one right-hand side at a time (B = 1
+    contexts; no tiles, the whole coarse part in the LDS tail) on the first
+    `cols` columns: solves/s = cols / total time."""
+    import torch
+    from paper_2608_29082_amd import binding as Bd
+    ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=1,
+                     max_outer=args.max_outer, check_every=25, stream=stream)
+    iters = []
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for c in range(cols):
+        fc = f[:, c:c + 1].contiguous()
+        u = torch.zeros_like(fc)
+        info = ctx.solve(fc, u)
+        iters.append(int(info.iters.max()))
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ctx.close()
+    out = {"value": cols / (tb - ta), "unit": "solves/s", "columns": cols, "iters": iters}
+    print(f"# learned {args.precision} unbatched: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(w, params, args, cycles_per_solve):
