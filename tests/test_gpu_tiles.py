@@ -154,3 +154,47 @@ def test_fused_conv_unaligned_vectors_use_hop_chain():
     ctx.vcycle(to_dev(f, torch.float32), ud)
     assert float((ud - ref).abs().max()) == 0.0
     ctx.close()
+
+
+def _mesh_graph(A):
+    """A's pattern plus the other diagonal of every grid cell (a graph that is
+    not A's pattern, with more neighbours than A has)."""
+    import scipy.sparse as sp
+    n = A.shape[0]
+    m = int(round(np.sqrt(n)))
+    pat = (A != 0).astype(float).tolil()
+    for i in range(n):
+        x, y = i % m, i // m
+        if x + 1 < m and y + 1 < m:
+            pat[i, i + m + 1] = 1.0
+            pat[i + m + 1, i] = 1.0
+    return sp.csr_matrix(pat)
+
+
+@pytest.mark.parametrize("K,graph", [((6, 2, 5), False), ((3, 3, 3), True)], ids=["K652", "mesh-graph"])
+def test_fused_conv_high_order_and_given_graph(K, graph):
+    """High convolution orders (deeper halos, smaller tiles) and a separately
+    given graph: bit for bit the per-hop sweeps, and the oracle's cycle."""
+    import torch
+    name, hier = CASES[0]
+    J = hier.nlevels
+    B = 32
+    flat = C.random_params(J, *K, seed=105, spread=0.1)
+    G = [_mesh_graph(a) for a in hier.A] if graph else None
+    g = C.rng(6, 25, 0)
+    f = g.standard_normal((hier.sizes[0], B))
+    u = g.standard_normal((hier.sizes[0], B))
+    on, off = _pair(hier, flat, K, B, "fp32", G=G)
+    outs = []
+    for ctx in (on, off):
+        ud = to_dev(u, torch.float32)
+        ctx.vcycle(to_dev(f, torch.float32), ud)
+        outs.append(to_np(ud))
+    assert _conv_launches(on, to_dev(f, torch.float32), to_dev(u, torch.float32)) > 0
+    want = O.lmg(O.make_levels(hier.A, hier.P, hier.R, G), O.unpack(flat, J, *K), 0, f, u)
+    d = float(np.abs(outs[0] - outs[1]).max())
+    err = rel(outs[0], want)
+    print(f"{name} K={K} graph={graph}: max diff {d:.1e}, rel to oracle {err:.2e}", flush=True)
+    assert d == 0.0
+    assert err <= TOL["fp32"]
+    on.close(); off.close()
