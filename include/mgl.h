@@ -152,7 +152,12 @@ mg_status mg_workspace_bytes(const mg_hierarchy* h, const mg_params* p, const mg
  * Gauss-Jordan elimination with partial pivoting in FP64) and return a
  * context.  workspace: caller-owned device memory of at least the size
  * reported by mg_workspace_bytes (kept for the context's lifetime), or NULL
- * to let the library allocate it.  Synchronises `stream` before returning. */
+ * to let the library allocate it.  FP32/BF16 contexts with nrhs a multiple
+ * of 16 also tile the levels of >= 2048 rows for the fused K-hop
+ * convolution (unless MG_FLAG_NO_TILES); the tile lists (about 50 bytes per
+ * unknown of those levels at K = 3) are allocated by the library outside
+ * the workspace and freed by mg_destroy.  Synchronises `stream` before
+ * returning. */
 mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* o,
                    void* workspace, size_t workspace_bytes, void* stream, mg_ctx** out);
 
