@@ -12,7 +12,7 @@ after 10 unrolled refinement steps (cycle precision as chosen, FP64 iterate
 and residual), minimised with Rprop from the identity initialisation
 (Sec. 3.1; Sec. 3.4; learning rate 0.01, at most 100 epochs, Sec. 4).
 --fields N trains on N coefficient fields at once (the right-hand sides are
-split between them).  Held-out right-hand sides, on the training fields and
+split between them).  --init starts Rprop from a saved parameter file.  Held-out right-hand sides, on the training fields and
 on held-out fields, are then solved to 1e-8 with the trained and with the
 identity parameters, and the cycle counts are reported.
 
@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -78,6 +79,7 @@ def main(argv=None):
     ap.add_argument("--fields", type=int, default=1)
     ap.add_argument("--field-seed", type=int, default=0, help="seed of the first training field")
     ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--init", default=None, help="start from this parameter file (.npy) instead of the identity")
     ap.add_argument("--out", default=None)
     ap.add_argument("--eval-B", type=int, default=8)
     ap.add_argument("--eval-fields", type=int, default=2)
@@ -121,7 +123,12 @@ def main(argv=None):
     fs = [dev(a) for a in fs_np]
     u0s = [dev(a) for a in u0s_np]
 
-    phi = torch.tensor(var.initial(), dtype=torch.float64, requires_grad=True)
+    start = None
+    if args.init:
+        start, _ = PR.load(args.init)
+        if start.size != theta0.size:
+            raise SystemExit(f"{args.init}: {start.size} parameters, expected {theta0.size}")
+    phi = torch.tensor(var.initial(start), dtype=torch.float64, requires_grad=True)
     opt = torch.optim.Rprop([phi], lr=args.lr, etas=(0.5, 1.2), step_sizes=(1e-6, 50.0))
     losses = []
     t0 = time.time()
@@ -179,6 +186,7 @@ def main(argv=None):
         PR.save(args.out, theta_np, {
             "trained_on": desc, "J": J, "KB": K, "KR": K, "KP": K, "nu": [nu, nu], "precision": args.precision,
             "variant": args.variant, "optimizer": f"Rprop lr={args.lr}", "steps": len(losses),
+            "init": os.path.basename(args.init) if args.init else "identity",
             "loss0": losses[0], "loss_final": losses[-1], "eval": evals})
     print(json.dumps(out), flush=True)
 
