@@ -48,6 +48,9 @@ def parse():
                     help="kernel family of the roofline entry (conv: the fused LDS-tile convolution)")
     ap.add_argument("--roofline-level", type=int, default=0)
     ap.add_argument("--max-outer", type=int, default=20000)
+    ap.add_argument("--check-every", type=int, default=5,
+                    help="mg_solve reads the active-column count on the host every this many cycles (every solve "
+                         "in the run; a solve ends at the first check after its last column converged)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
@@ -103,7 +106,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=B,
-                     max_outer=args.max_outer, check_every=25, stream=stream, tiles=not args.no_tiles)
+                     max_outer=args.max_outer, check_every=args.check_every, stream=stream, tiles=not args.no_tiles)
     f = torch.tensor(w.f, dtype=torch.float64, device=dev)
     u = torch.zeros_like(f)
 
@@ -178,7 +181,7 @@ def main():
     if not args.no_ablation and not args.no_tiles and args.precision != "fp64":
         # the same solve with every convolution as a chain of per-hop sweeps
         hctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=B,
-                          max_outer=args.max_outer, check_every=25, stream=stream, tiles=False)
+                          max_outer=args.max_outer, check_every=args.check_every, stream=stream, tiles=False)
         uh = torch.zeros_like(f)
         hctx.solve(f, uh)
         uh.zero_()
@@ -196,7 +199,7 @@ def main():
     if not args.no_plain:
         # plain FP64 GPU V-cycle: classical components (K = 0, identity), same inputs
         pctx = Bd.Context(h.A, h.P, C.identity_params(J, 0, 0, 0), 0, 0, 0, precision="fp64", nrhs=B,
-                          max_outer=args.max_outer, check_every=25, stream=stream)
+                          max_outer=args.max_outer, check_every=args.check_every, stream=stream)
         up = torch.zeros_like(f)
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -439,7 +442,7 @@ def learned_fp64(args, h, params, f, B, stream):
     import torch
     from paper_2608_29082_amd import binding as Bd
     ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision="fp64", nrhs=B,
-                     max_outer=args.max_outer, check_every=25, stream=stream)
+                     max_outer=args.max_outer, check_every=args.check_every, stream=stream)
     u = torch.zeros_like(f)
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -460,7 +463,7 @@ def unbatched(args, h, params, f, stream, cols=4):
     import torch
     from paper_2608_29082_amd import binding as Bd
     ctx = Bd.Context(h.A, h.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=1,
-                     max_outer=args.max_outer, check_every=25, stream=stream)
+                     max_outer=args.max_outer, check_every=args.check_every, stream=stream)
     iters = []
     torch.cuda.synchronize()
     ta = time.perf_counter()
