@@ -157,3 +157,78 @@ def serving_arrivals(count: int, qps: float, stream_seed: int = 0) -> np.ndarray
     """Poisson arrivals: cumulative sums of exponential gaps with mean 1/qps."""
     gaps = rng(5, _ARRIVAL, stream_seed).exponential(1.0 / qps, size=count)
     return np.cumsum(gaps)
+
+
+# ----------------------------------------------------------------------------- Helmholtz (two features)
+@dataclass
+class HelmholtzWorkload:
+    name: str
+    hier: object             # helmholtz.HelmholtzHierarchy
+    f: np.ndarray            # (n0, B) complex128
+    params: np.ndarray       # flat float64, layout of hz_n_params
+    KB: int
+    KR: int
+    KP: int
+    plan: list               # [J-1] (kind, nu_pre, nu_post)
+    v: int = 4               # GMRES steps of a GMRES smoothing step
+    rtol: float = 1e-8
+
+    @property
+    def B(self) -> int:
+        return self.f.shape[1]
+
+
+def hz_n_params(J: int, KB: int, KR: int, KP: int) -> int:
+    """Per level l < J-1: [theta_l, eta_l, W_B,l[0..KB] (2 x 2 row-major)];
+    then the shared W_R[0..KR] and W_P[0..KP]."""
+    return (J - 1) * (2 + 4 * (KB + 1)) + 4 * (KR + 1) + 4 * (KP + 1)
+
+
+def hz_identity_params(J: int, KB: int, KR: int, KP: int, plan, omega: float = 2.0 / 3.0) -> np.ndarray:
+    """Identity initialisation with two features: W_0 = I, W_k = 0 (k > 0),
+    eta = 1; theta = omega on Jacobi levels and 0 on GMRES levels (a GMRES
+    smoothing step then starts from zero: the classical GMRES smoother)."""
+    per = 2 + 4 * (KB + 1)
+    lv = np.zeros((J - 1, per))
+    for l in range(J - 1):
+        lv[l, 0] = omega if plan[l][0] == "jacobi" else 0.0
+        lv[l, 1] = 1.0
+        lv[l, 2:6] = (1.0, 0.0, 0.0, 1.0)
+    sh = np.zeros(4 * (KR + 1) + 4 * (KP + 1))
+    sh[0:4] = (1.0, 0.0, 0.0, 1.0)
+    sh[4 * (KR + 1):4 * (KR + 1) + 4] = (1.0, 0.0, 0.0, 1.0)
+    return np.concatenate([lv.ravel(), sh])
+
+
+def hz_random_params(J: int, KB: int, KR: int, KP: int, plan, seed: int = 0, spread: float = 0.2) -> np.ndarray:
+    """Random parameters near the identity initialisation, with off-diagonal
+    (real/imaginary mixing) entries in every weight matrix."""
+    g = rng(10, _PARAMS, seed)
+    per = 2 + 4 * (KB + 1)
+    lv = np.zeros((J - 1, per))
+    for l in range(J - 1):
+        lv[l, 0] = g.uniform(0.5, 0.8) if plan[l][0] == "jacobi" else g.uniform(0.1, 0.6)
+        lv[l, 1] = g.uniform(0.8, 1.2)
+        W = g.uniform(-spread, spread, (KB + 1, 2, 2))
+        W[0] += np.eye(2)
+        lv[l, 2:] = W.ravel()
+    WR = g.uniform(-spread, spread, (KR + 1, 2, 2))
+    WR[0] += np.eye(2)
+    WP = g.uniform(-spread, spread, (KP + 1, 2, 2))
+    WP[0] += np.eye(2)
+    return np.concatenate([lv.ravel(), WR.ravel(), WP.ravel()])
+
+
+def helmholtz(side: int = 257, k: float = 16.0 * np.pi, J: int = 5, B: int = 16, K: int = 1, seed: int = 0,
+              v: int = 4) -> HelmholtzWorkload:
+    """Impedance Helmholtz on [-1/2, 1/2]^2 (the "/" P1 mesh with `side`
+    points per direction, every vertex an unknown), J levels, smoothed-disk
+    sources (column 0 the training source, column 1 the test source, the rest
+    at seeded random centres), Jacobi V(1,1) where k h_l <= 0.5 and GMRES(v)
+    V(1,2) elsewhere, convolutions of order K at identity initialisation.
+    Default: k = 16 pi, h = 1/256 (66 049 unknowns, k h = 0.196), 5 levels."""
+    from . import helmholtz as HZ
+    h = HZ.hierarchy(side, k, J)
+    plan = HZ.smoother_plan(h)
+    f = HZ.load_vectors(side, HZ.source_centres(B, rng(10, _RHS, seed)))
+    return HelmholtzWorkload(f"helmholtz-{side}", h, f, hz_identity_params(J, K, K, K, plan), K, K, K, plan, v)
