@@ -34,8 +34,8 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = True) -> str:
-    """Compile csrc/mgl.hip and csrc/hierarchy.cpp into libmgl.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, "mgl.hip"), os.path.join(CSRC, "hierarchy.cpp")]
+    """Compile csrc/mgl.hip, csrc/helm.hip and csrc/hierarchy.cpp into libmgl.so (always recompiles)."""
+    srcs = [os.path.join(CSRC, "mgl.hip"), os.path.join(CSRC, "helm.hip"), os.path.join(CSRC, "hierarchy.cpp")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp]
     if verbose:

@@ -82,3 +82,48 @@ def test_malformed_inputs_rejected_on_host():
     assert st == 1
     st, _, _ = _sizes(Bd, lib, hier, B=257)
     assert st == 1
+
+
+def test_helmholtz_header_symbols_exported():
+    """Every entry point of include/mgh.h is exported and bound."""
+    Bd, lib = _lib()
+    from paper_2608_29082_amd import helmholtz as HB
+    hdr = open(os.path.join(ROOT, "include", "mgh.h")).read()
+    declared = set(re.findall(r"\b(mgh_[a-z_]+)\s*\(", hdr))
+    out = subprocess.run(["nm", "-D", "--defined-only", Bd.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (mgh_[a-z_]+)", out))
+    assert declared and declared <= exported, declared - exported
+    assert declared == set(HB.EXPORTED)
+    HB.load_library()
+    assert lib.mgh_num_params(5, 1, 1, 1) == Cf.hz_n_params(5, 1, 1, 1) == 4 * 10 + 8 + 8
+    assert lib.mgh_num_params(1, 1, 1, 1) == -1
+
+
+def test_helmholtz_setup_rejects_bad_input_before_any_device_work():
+    """mgh_setup validates its arguments on the host (no GPU needed for the
+    rejected cases)."""
+    Bd, lib = _lib()
+    from paper_2608_29082_amd import helmholtz as HB
+    from mginputs import helmholtz as HZ
+    HB.load_library()
+    h = HZ.hierarchy(9, 3.0, 2)
+    host = HB._Host(h.A, h.P)
+    vals = np.ascontiguousarray(Cf.hz_identity_params(2, 1, 1, 1, [("jacobi", 1, 1)]))
+    ip = C.POINTER(C.c_int32)
+    sm, pre, post = (np.array([0], dtype=np.int32), np.array([1], dtype=np.int32), np.array([1], dtype=np.int32))
+
+    def call(KB=1, v=4, prec=0, B=1, smk=0, hier=None):
+        sm[0] = smk
+        p = HB._HParams(KB, 1, 1, sm.ctypes.data_as(ip), pre.ctypes.data_as(ip), post.ctypes.data_as(ip), v,
+                        vals.ctypes.data_as(C.POINTER(C.c_double)))
+        o = HB._HOptions(prec, B)
+        out = C.c_void_p()
+        return lib.mgh_setup(C.byref(hier or host.h), C.byref(p), C.byref(o), None, C.byref(out))
+    assert call(KB=9) == 1
+    assert call(v=0) == 1 and call(v=9) == 1
+    assert call(prec=2) == 1
+    assert call(B=0) == 1 and call(B=257) == 1
+    assert call(smk=2) == 1
+    bad = HB._Host([h.A[0], h.A[0]], h.P)           # P has the wrong column count
+    assert call(hier=bad.h) == 2
+    assert b"P_0" in lib.mgh_last_error()
