@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-family finest-level timing and the per-hop-sweep comparison")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length of the Krylov comparison")
+    ap.add_argument("--no-helmholtz", action="store_true", help="skip the complex Helmholtz section")
+    ap.add_argument("--helmholtz-only", action="store_true",
+                    help="run only the complex Helmholtz section (no CPU leg) and print its JSON")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="requests per serving run (closed loop, then open loop at 0.5x and 0.8x its rate); 0 skips")
@@ -85,6 +88,9 @@ def main():
     from mginputs import configs as C
     from paper_2608_29082_amd import binding as Bd
 
+    if args.helmholtz_only:
+        print(json.dumps({"helmholtz": helmholtz(args, cpu=False)}), flush=True)
+        return
     t0 = time.time()
     w, coef = workload(args.workload, args.K)
     h = w.hier
@@ -223,6 +229,9 @@ def main():
 
     if args.serving_requests > 0:
         out["serving"] = serving(args)
+
+    if not args.no_helmholtz:
+        out["helmholtz"] = helmholtz(args, cpu=not args.no_cpu)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, params, args, float(info.iters.mean()))
@@ -417,6 +426,83 @@ def serving(args):
         r.pop("by_side", None)
     print(f"# serving: {json.dumps(runs)}", file=sys.stderr, flush=True)
     return {"requests_per_run": args.serving_requests, "sides": [65, 129, 257, 513, 1025], **runs}
+
+
+def helmholtz(args, cpu=True):
+    """Complex Helmholtz with an impedance boundary (Sec. 4.2): k = 16 pi on
+    the 257 x 257 P1 mesh of the centred unit square (66 049 unknowns, k h =
+    0.196), 5 levels, Jacobi V(1,1) where k h <= 1/2 and GMRES(4) V(1,2)
+    elsewhere, two-feature K = 1 convolutions at identity initialisation,
+    16 smoothed-disk sources.  FGMRES(40) to 1e-8 with the cycle or FMG as
+    preconditioner, FP32 and FP64 cycles (one warm-up solve, one timed);
+    the time of one cycle of the K = 1 form and of the form without
+    convolution hops (K = 0); the oracle's FGMRES-FMG solve of one column."""
+    import torch
+    from mginputs import configs as C
+    from paper_2608_29082_amd import helmholtz as HB
+    w = C.helmholtz(B=16)
+    h = w.hier
+    J, B = h.nlevels, w.B
+    dev = torch.device("cuda:0")
+    f = torch.tensor(w.f, dtype=torch.complex128, device=dev)
+    fn = np.linalg.norm(w.f, axis=0)
+    out = {"workload": f"helmholtz-257: k = 16 pi, {h.sizes[0]} unknowns, {J} levels, impedance boundary, "
+                       f"{B} smoothed-disk sources",
+           "smoothers": [f"{p[0]} V({p[1]},{p[2]})" for p in w.plan], "kh": [round(h.kh(l), 3) for l in range(J)],
+           "gmres_steps": w.v, "K": 1, "params": "identity initialisation (classical smoothers, two-feature form)",
+           "restart": 40, "rtol": 1e-8}
+
+    def cycle_ms(ctx, reps=20):
+        fc = f.to(ctx.cycle_dtype)
+        u = torch.zeros_like(fc)
+        ctx.vcycle(fc, u)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            ctx.vcycle(fc, u)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - ta) / reps
+
+    for prec in ("fp32", "fp64"):
+        ctx = HB.from_workload(w, precision=prec)
+        for pc in ("vcycle", "fmg"):
+            x = torch.zeros_like(f)
+            ctx.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+            x.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            info = ctx.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / fn
+            ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+            out[f"fgmres_{pc}_{prec}"] = {"value": B / (tb - ta) if ok else 0.0, "unit": "solves/s",
+                                          "iters_max": int(info.iters.max()), "iters_mean": float(info.iters.mean()),
+                                          "relres_max_fp64_host": float(rr.max()), "converged": bool(ok)}
+            print(f"# helmholtz fgmres {pc} {prec}: {out[f'fgmres_{pc}_{prec}']}", file=sys.stderr, flush=True)
+        out[f"cycle_ms_{prec}"] = cycle_ms(ctx)
+        ctx.close()
+    ctx0 = HB.HelmholtzContext(h.A, h.P, C.hz_identity_params(J, 0, 0, 0, w.plan), 0, 0, 0, w.plan, v=w.v,
+                               precision="fp32", nrhs=B)
+    out["cycle_ms_fp32_no_hops"] = cycle_ms(ctx0)
+    ctx0.close()
+    out["cycle_cost_K1_over_no_hops"] = out["cycle_ms_fp32"] / out["cycle_ms_fp32_no_hops"]
+    if cpu:
+        import resource
+        from oracle import helmholtz as OH
+        lev = OH.make_levels(h.A, h.P, h.R)
+        prm = OH.unpack(w.params, J, 1, 1, 1, w.plan, w.v)
+        ru0 = resource.getrusage(resource.RUSAGE_SELF)
+        ta = time.perf_counter()
+        _, it, rr, _ = OH.fgmres(lev, prm, w.f[:, :1], restart=40, rtol=1e-8, max_iter=200, precond="fmg")
+        wall = time.perf_counter() - ta
+        ru1 = resource.getrusage(resource.RUSAGE_SELF)
+        cpu_s = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+        out["cpu_oracle_fgmres_fmg"] = {"value": 1.0 / wall, "unit": "solves/s", "iters": int(it[0]),
+                                        "cores": max(1, int(round(cpu_s / wall))), "kind": "oracle",
+                                        "sample": f"one column (the training source), {wall:.1f}s wall"}
+    print(f"# helmholtz: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 def device_copy_gbps(mib=256, reps=5):

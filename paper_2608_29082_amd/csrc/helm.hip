@@ -52,7 +52,7 @@ mg_status hfail(mg_status s, const std::string& m) {
                                    hipGetErrorString(e_));                                       \
   } while (0)
 
-constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 512, kKrBlocks = 2048, kNG = 8;
+constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 512, kKrBlocks = 1024, kNG = 8;
 
 template <class T> struct C2;
 template <> struct C2<float> { using t = float2; };
@@ -181,22 +181,6 @@ __global__ __launch_bounds__(256) void k_hz_xfer(REll<T> X, int B, int lb, const
   }
 }
 
-// coarsest level: u = A^{-1} f with the FP64 inverse
-template <class T>
-__global__ __launch_bounds__(256) void k_hz_dense(int n, int B, int lb, const double2* __restrict__ Ainv,
-                                                  const cx<T>* __restrict__ f, cx<T>* __restrict__ u) {
-  HZ_ROW(n)
-  double ar = 0.0, ai = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double2 a = Ainv[(size_t)i * n + j];
-    const cx<T> t = f[(size_t)j * B + b];
-    const double tr = (double)t.x, ti = (double)t.y;
-    ar += a.x * tr - a.y * ti;
-    ai += a.x * ti + a.y * tr;
-  }
-  u[o] = mkc<T>((T)ar, (T)ai);
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void k_hz_zero(size_t cnt, cx<T>* __restrict__ p) {
   const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -295,9 +279,12 @@ __device__ void hz_givens_lsq(double2* H, int ldh, int m, double beta, double2* 
 
 // One GMRES smoothing step on column blockIdx.x of level (A, G):
 //   r = f - A u;  d0 = theta Phi_B(r);  u += eta GMRES(A, r, d0, v)
-// scr holds v + 5 vectors [n][B]: r, two Horner buffers, d0, V_0 .. V_v.
-// Orthogonalisation: classical Gram-Schmidt applied twice per Arnoldi step;
-// dot products and norms are accumulated in FP64.
+// scr holds v + 5 vectors of n x B values: r, two Horner buffers, d0,
+// V_0 .. V_v, each stored column by column (column b of slot t at
+// scr + t n B + b n), so the work-group's sweeps over its column are
+// coalesced; f and u keep the [n][B] layout.  Orthogonalisation: classical
+// Gram-Schmidt applied twice per Arnoldi step; dot products and norms are
+// accumulated in FP64.
 template <class T>
 __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
                                                   const cx<T>* __restrict__ f, cx<T>* __restrict__ u, T theta,
@@ -308,46 +295,47 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
   __shared__ double csw[kMaxV];
   const int b = blockIdx.x, n = A.n, nt = blockDim.x, t0 = threadIdx.x;
   const size_t NB = (size_t)n * B;
-  cx<T>* R = scr;
-  cx<T>* D0 = scr + 3 * NB;
-  cx<T>* V = scr + 4 * NB;
+  cx<T>* base = scr + (size_t)b * n;           // slot t of this column: base + t NB
+  cx<T>* R = base;
+  cx<T>* D0 = base + 3 * NB;
+  cx<T>* V = base + 4 * NB;
   // 1. residual
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
     ell_cmul<T, T, T>(A, u, i, B, b, ar, ai);
     const cx<T> fi = f[(size_t)i * B + b];
-    R[(size_t)i * B + b] = mkc<T>(fi.x - ar, fi.y - ai);
+    R[i] = mkc<T>(fi.x - ar, fi.y - ai);
   }
   __syncthreads();
   // 2. initial guess d0 = theta Phi_B(r) (Horner over the neighbour mean)
   if (K == 0) {
     for (int i = t0; i < n; i += nt) {
-      const cx<T> t = mixw(W.w[0], R[(size_t)i * B + b]);
-      D0[(size_t)i * B + b] = mkc<T>(theta * t.x, theta * t.y);
+      const cx<T> t = mixw(W.w[0], R[i]);
+      D0[i] = mkc<T>(theta * t.x, theta * t.y);
     }
   } else {
-    for (int i = t0; i < n; i += nt) scr[NB + (size_t)i * B + b] = mixw(W.w[K], R[(size_t)i * B + b]);
+    for (int i = t0; i < n; i += nt) base[NB + i] = mixw(W.w[K], R[i]);
     __syncthreads();
     int cur = 0;
     for (int k = K - 1; k >= 0; --k) {
-      cx<T>* dst = k == 0 ? D0 : scr + (size_t)(2 - cur) * NB;      // the other Horner buffer
+      cx<T>* dst = k == 0 ? D0 : base + (size_t)(2 - cur) * NB;     // the other Horner buffer
       const T s = k == 0 ? theta : (T)1;
-      const cx<T>* yc = scr + (size_t)(1 + cur) * NB;
+      const cx<T>* yc = base + (size_t)(1 + cur) * NB;
       for (int i = t0; i < n; i += nt) {
         T mr = 0, mi = 0;
         for (int q = 0; q < G.w; ++q) {
           const int j = G.col[(size_t)q * n + i];
           if (j != i) {
-            const cx<T> t = yc[(size_t)j * B + b];
+            const cx<T> t = yc[j];
             mr += t.x;
             mi += t.y;
           }
         }
-        cx<T> t = mixw(W.w[k], R[(size_t)i * B + b]);
+        cx<T> t = mixw(W.w[k], R[i]);
         const T r = invdeg[i];
         t.x += r * mr;
         t.y += r * mi;
-        dst[(size_t)i * B + b] = mkc<T>(s * t.x, s * t.y);
+        dst[i] = mkc<T>(s * t.x, s * t.y);
       }
       __syncthreads();
       cur ^= 1;
@@ -359,10 +347,10 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
   acc[0] = 0.0;
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
-    ell_cmul<T, T, T>(A, D0, i, B, b, ar, ai);
-    const cx<T> ri = R[(size_t)i * B + b];
+    ell_cmul<T, T, T>(A, D0, i, 1, 0, ar, ai);
+    const cx<T> ri = R[i];
     const cx<T> t = mkc<T>(ri.x - ar, ri.y - ai);
-    V[(size_t)i * B + b] = t;
+    V[i] = t;
     acc[0] += (double)t.x * t.x + (double)t.y * t.y;
   }
   hz_block_sum(acc, 1, red);
@@ -371,8 +359,8 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
   if (beta > 0.0) {
     const T ib = (T)(1.0 / beta);
     for (int i = t0; i < n; i += nt) {
-      cx<T> t = V[(size_t)i * B + b];
-      V[(size_t)i * B + b] = mkc<T>(t.x * ib, t.y * ib);
+      const cx<T> t = V[i];
+      V[i] = mkc<T>(t.x * ib, t.y * ib);
     }
     if (t0 == 0)
       for (int k = 0; k < (kMaxV + 1) * kMaxV; ++k) H[k] = zc(0.0, 0.0);
@@ -383,19 +371,19 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
       cx<T>* Wn = V + (size_t)(j + 1) * NB;
       for (int i = t0; i < n; i += nt) {
         T ar = 0, ai = 0;
-        ell_cmul<T, T, T>(A, Vj, i, B, b, ar, ai);
-        Wn[(size_t)i * B + b] = mkc<T>(ar, ai);
+        ell_cmul<T, T, T>(A, Vj, i, 1, 0, ar, ai);
+        Wn[i] = mkc<T>(ar, ai);
       }
       for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
         for (int t = 0; t <= kMaxV; ++t)
           if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
         for (int i = t0; i < n; i += nt) {
-          const cx<T> w = Wn[(size_t)i * B + b];
+          const cx<T> w = Wn[i];
 #pragma unroll
           for (int t = 0; t <= kMaxV; ++t) {
             if (t <= j) {
-              const cx<T> q = V[(size_t)t * NB + (size_t)i * B + b];     // conj(q) w
+              const cx<T> q = V[(size_t)t * NB + i];     // conj(q) w
               acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
               acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
             }
@@ -403,17 +391,17 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
         }
         hz_block_sum(acc, 2 * (j + 1), red);
         for (int i = t0; i < n; i += nt) {
-          cx<T> w = Wn[(size_t)i * B + b];
+          cx<T> w = Wn[i];
 #pragma unroll
           for (int t = 0; t <= kMaxV; ++t) {
             if (t <= j) {
-              const cx<T> q = V[(size_t)t * NB + (size_t)i * B + b];
+              const cx<T> q = V[(size_t)t * NB + i];
               const T hr = (T)acc[2 * t], hi = (T)acc[2 * t + 1];
               w.x -= hr * q.x - hi * q.y;
               w.y -= hr * q.y + hi * q.x;
             }
           }
-          Wn[(size_t)i * B + b] = w;
+          Wn[i] = w;
         }
         if (t0 == 0)
           for (int t = 0; t <= j; ++t) {
@@ -423,7 +411,7 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
       }
       acc[0] = 0.0;
       for (int i = t0; i < n; i += nt) {
-        const cx<T> w = Wn[(size_t)i * B + b];
+        const cx<T> w = Wn[i];
         acc[0] += (double)w.x * w.x + (double)w.y * w.y;
       }
       hz_block_sum(acc, 1, red);
@@ -435,8 +423,8 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
       }
       const T ih = (T)(1.0 / hn);
       for (int i = t0; i < n; i += nt) {
-        const cx<T> w = Wn[(size_t)i * B + b];
-        Wn[(size_t)i * B + b] = mkc<T>(w.x * ih, w.y * ih);
+        const cx<T> w = Wn[i];
+        Wn[i] = mkc<T>(w.x * ih, w.y * ih);
       }
       __syncthreads();
     }
@@ -446,11 +434,11 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
   }
   // 4. u += eta (d0 + V y)
   for (int i = t0; i < n; i += nt) {
-    const cx<T> d = D0[(size_t)i * B + b];
+    const cx<T> d = D0[i];
     double dr = d.x, di = d.y;
     for (int t = 0; t < m; ++t) {
       const double2 y = yls[t];
-      const cx<T> q = V[(size_t)t * NB + (size_t)i * B + b];
+      const cx<T> q = V[(size_t)t * NB + i];
       dr += y.x * q.x - y.y * q.y;
       di += y.x * q.y + y.y * q.x;
     }
@@ -485,6 +473,29 @@ __device__ __forceinline__ double kr_rowsum(double v, int lb, double* red) {
   const double r = red[threadIdx.x & (LB - 1)];
   __syncthreads();
   return r;
+}
+
+// coarsest level: u = A^{-1} f with the FP64 inverse; one work-group per row
+// i, the 256 >> lb lane groups splitting the sum over j (fixed tree)
+template <class T>
+__global__ __launch_bounds__(256) void k_hz_dense(int n, int B, int lb, const double2* __restrict__ Ainv,
+                                                  const cx<T>* __restrict__ f, cx<T>* __restrict__ u) {
+  __shared__ double red[256];
+  const int i = blockIdx.x, ng = 256 >> lb;
+  const int b = threadIdx.x & ((1 << lb) - 1), jg = (int)(threadIdx.x >> lb);
+  double ar = 0.0, ai = 0.0;
+  if (b < B) {
+    for (int j = jg; j < n; j += ng) {
+      const double2 a = Ainv[(size_t)i * n + j];
+      const cx<T> t = f[(size_t)j * B + b];
+      const double tr = (double)t.x, ti = (double)t.y;
+      ar += a.x * tr - a.y * ti;
+      ai += a.x * ti + a.y * tr;
+    }
+  }
+  ar = kr_rowsum(ar, lb, red);
+  ai = kr_rowsum(ai, lb, red);
+  if (jg == 0 && b < B) u[(size_t)i * B + b] = mkc<T>((T)ar, (T)ai);
 }
 
 // w = f - A x (x null: w = f), FP64
@@ -549,19 +560,25 @@ __global__ __launch_bounds__(256) void k_fx_dot(int n, int B, int lb, int chunk,
   }
 }
 
-// out[t * B + b] = sum over blocks (in order) of part[(blk * rows + t) * B + b]
+// out[t * B + b] = sum over blocks of part[(blk * rows + t) * B + b]: one
+// wavefront per output, lane q summing blocks q, q + 64, ... in order, then a
+// butterfly over the lanes (a fixed order: deterministic)
 __global__ __launch_bounds__(256) void k_fx_reduce(int nblk, int rows, int B, const double2* __restrict__ part,
                                                    double2* __restrict__ out, const int* __restrict__ skip) {
   if (skip && *skip == 0) return;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= rows * B) return;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
+  if (t >= rows * B) return;                   // uniform over the wavefront
   double sr = 0.0, si = 0.0;
-  for (int k = 0; k < nblk; ++k) {
+  for (int k = ln; k < nblk; k += 64) {
     const double2 p = part[(size_t)k * rows * B + t];
     sr += p.x;
     si += p.y;
   }
-  out[t] = zc(sr, si);
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    si += __shfl_xor(si, off);
+  }
+  if (ln == 0) out[t] = zc(sr, si);
 }
 
 // wo = wi - sum_{t < nv} h_t v_t and part[blk * B + b].x = sum |wo|^2 (wi may equal wo)
@@ -995,8 +1012,7 @@ struct HzEngine final : mgh_ctx {
   }
 
   mg_status coarse(const cx<T>* f, cx<T>* u, hipStream_t st) {
-    hipLaunchKernelGGL((k_hz_dense<T>), dim3(rows_grid(nc)), dim3(256), 0, st, nc, Bn, lb, (const double2*)Ainv, f,
-                       u);
+    hipLaunchKernelGGL((k_hz_dense<T>), dim3(nc), dim3(256), 0, st, nc, Bn, lb, (const double2*)Ainv, f, u);
     H_LAUNCH();
     return MG_OK;
   }
@@ -1086,7 +1102,7 @@ struct HzEngine final : mgh_ctx {
                        Kpart, skip);
     H_LAUNCH();
     const int rows = nv + 1;
-    hipLaunchKernelGGL(k_fx_reduce, dim3(lin_grid((size_t)rows * Bn)), dim3(256), 0, st, kblk, rows, Bn,
+    hipLaunchKernelGGL(k_fx_reduce, dim3(((size_t)rows * Bn + 3) / 4), dim3(256), 0, st, kblk, rows, Bn,
                        (const double2*)Kpart, out, skip);
     H_LAUNCH();
     return MG_OK;
@@ -1097,7 +1113,7 @@ struct HzEngine final : mgh_ctx {
     hipLaunchKernelGGL(k_fx_upd, dim3(kblk), dim3(256), 0, st, n, Bn, lb, kchunk, (const double2*)KV, mp1, nv, h,
                        wi, wis, wo, wos, Kpart, skip);
     H_LAUNCH();
-    hipLaunchKernelGGL(k_fx_reduce, dim3(lin_grid((size_t)Bn)), dim3(256), 0, st, kblk, 1, Bn,
+    hipLaunchKernelGGL(k_fx_reduce, dim3(((size_t)Bn + 3) / 4), dim3(256), 0, st, kblk, 1, Bn,
                        (const double2*)Kpart, n2, skip);
     H_LAUNCH();
     return MG_OK;
