@@ -52,7 +52,7 @@ mg_status hfail(mg_status s, const std::string& m) {
                                    hipGetErrorString(e_));                                       \
   } while (0)
 
-constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 512, kKrBlocks = 1024, kNG = 8;
+constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 1024, kKrBlocks = 1024, kNG = 8;
 
 template <class T> struct C2;
 template <> struct C2<float> { using t = float2; };
@@ -194,10 +194,11 @@ __global__ __launch_bounds__(256) void k_hz_copy(size_t cnt, const cx<T>* __rest
 }
 
 // ------------------------------------------------------------------ GMRES smoothing step
-// Block-wide sums of the first cnt of N doubles, broadcast to every work-item
-// (wavefront butterflies, then the waves' totals in wave order).
+// Block-wide sums of the first cnt of N doubles, broadcast to every work-item:
+// wavefront butterflies, then work-item k adds the waves' totals of value k in
+// wave order (a fixed order: deterministic).  lds: N x 16 doubles, tot: N.
 template <int N>
-__device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* lds) {
+__device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* lds, double* tot) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -208,15 +209,15 @@ __device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* ld
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    if (k < cnt) {
-      double s = 0.0;
-      for (int q = 0; q < nw; ++q) s += lds[k * 16 + q];
-      a[k] = s;
-    }
+  if ((int)threadIdx.x < cnt) {
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += lds[threadIdx.x * 16 + q];
+    tot[threadIdx.x] = s;
   }
   __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (k < cnt) a[k] = tot[k];
 }
 
 __device__ __forceinline__ double2 zc(double r, double i) { return make_double2(r, i); }
@@ -289,7 +290,7 @@ template <class T>
 __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
                                                   const cx<T>* __restrict__ f, cx<T>* __restrict__ u, T theta,
                                                   T eta, WK<T> W, int K, int v, cx<T>* __restrict__ scr) {
-  __shared__ double red[2 * (kMaxV + 1) * 16];
+  __shared__ double red[2 * (kMaxV + 1) * 16], tot[2 * (kMaxV + 1)];
   __shared__ double2 H[(kMaxV + 1) * kMaxV];
   __shared__ double2 yls[kMaxV], gw[kMaxV + 1], snw[kMaxV];
   __shared__ double csw[kMaxV];
@@ -353,83 +354,113 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
     V[i] = t;
     acc[0] += (double)t.x * t.x + (double)t.y * t.y;
   }
-  hz_block_sum(acc, 1, red);
+  hz_block_sum(acc, 1, red, tot);
   const double beta = sqrt(acc[0]);
+  // Arnoldi with a lazily normalised basis: slot t holds Vt_t and the actual
+  // basis vector is v_t = sc[t] Vt_t.  Each step is three sweeps, each ending
+  // in one block reduction: w = A v_j with the first-pass dots, the first
+  // update with the second-pass dots, the second update with the norm.
+  double sc[kMaxV + 1], cf[2 * (kMaxV + 1)];
+#pragma unroll
+  for (int t = 0; t <= kMaxV; ++t) sc[t] = 0.0;
   int m = 0;
   if (beta > 0.0) {
-    const T ib = (T)(1.0 / beta);
-    for (int i = t0; i < n; i += nt) {
-      const cx<T> t = V[i];
-      V[i] = mkc<T>(t.x * ib, t.y * ib);
-    }
+    sc[0] = 1.0 / beta;
     if (t0 == 0)
       for (int k = 0; k < (kMaxV + 1) * kMaxV; ++k) H[k] = zc(0.0, 0.0);
-    __syncthreads();
     m = v;
     for (int j = 0; j < v; ++j) {
+      double sj = 0.0;
+#pragma unroll
+      for (int t = 0; t <= kMaxV; ++t)
+        if (t == j) sj = sc[t];
+      const T sjt = (T)sj;
       const cx<T>* Vj = V + (size_t)j * NB;
       cx<T>* Wn = V + (size_t)(j + 1) * NB;
+      // sweep 1: w = A v_j and <Vt_t, w>
+#pragma unroll
+      for (int t = 0; t <= kMaxV; ++t)
+        if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
       for (int i = t0; i < n; i += nt) {
         T ar = 0, ai = 0;
         ell_cmul<T, T, T>(A, Vj, i, 1, 0, ar, ai);
-        Wn[i] = mkc<T>(ar, ai);
+        const cx<T> w = mkc<T>(ar * sjt, ai * sjt);
+        Wn[i] = w;
+#pragma unroll
+        for (int t = 0; t <= kMaxV; ++t) {
+          if (t <= j) {
+            const cx<T> q = V[(size_t)t * NB + i];     // conj(q) w
+            acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
+            acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
+          }
+        }
       }
+      hz_block_sum(acc, 2 * (j + 1), red, tot);
+      // h_t = sc[t] acc_t; the update subtracts h_t v_t = (h_t sc[t]) Vt_t
       for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-        for (int t = 0; t <= kMaxV; ++t)
-          if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
-        for (int i = t0; i < n; i += nt) {
-          const cx<T> w = Wn[i];
+        for (int t = 0; t <= kMaxV; ++t) {
+          if (t <= j) {
+            cf[2 * t] = acc[2 * t] * sc[t] * sc[t];
+            cf[2 * t + 1] = acc[2 * t + 1] * sc[t] * sc[t];
+          }
+        }
+        if (t0 == 0)
 #pragma unroll
           for (int t = 0; t <= kMaxV; ++t) {
             if (t <= j) {
-              const cx<T> q = V[(size_t)t * NB + i];     // conj(q) w
-              acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
-              acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
+              const double2 h = H[t * kMaxV + j];
+              H[t * kMaxV + j] = zc(h.x + acc[2 * t] * sc[t], h.y + acc[2 * t + 1] * sc[t]);
             }
           }
-        }
-        hz_block_sum(acc, 2 * (j + 1), red);
+#pragma unroll
+        for (int t = 0; t <= kMaxV; ++t)
+          if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
         for (int i = t0; i < n; i += nt) {
           cx<T> w = Wn[i];
 #pragma unroll
           for (int t = 0; t <= kMaxV; ++t) {
             if (t <= j) {
               const cx<T> q = V[(size_t)t * NB + i];
-              const T hr = (T)acc[2 * t], hi = (T)acc[2 * t + 1];
+              const T hr = (T)cf[2 * t], hi = (T)cf[2 * t + 1];
               w.x -= hr * q.x - hi * q.y;
               w.y -= hr * q.y + hi * q.x;
             }
           }
           Wn[i] = w;
-        }
-        if (t0 == 0)
-          for (int t = 0; t <= j; ++t) {
-            const double2 h = H[t * kMaxV + j];
-            H[t * kMaxV + j] = zc(h.x + acc[2 * t], h.y + acc[2 * t + 1]);
+          if (pass == 0) {
+#pragma unroll
+            for (int t = 0; t <= kMaxV; ++t) {
+              if (t <= j) {
+                const cx<T> q = V[(size_t)t * NB + i];
+                acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
+                acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
+              }
+            }
+          } else {
+            acc[0] += (double)w.x * w.x + (double)w.y * w.y;
           }
+        }
+        hz_block_sum(acc, pass == 0 ? 2 * (j + 1) : 1, red, tot);
       }
-      acc[0] = 0.0;
-      for (int i = t0; i < n; i += nt) {
-        const cx<T> w = Wn[i];
-        acc[0] += (double)w.x * w.x + (double)w.y * w.y;
-      }
-      hz_block_sum(acc, 1, red);
       const double hn = sqrt(acc[0]);
       if (t0 == 0) H[(j + 1) * kMaxV + j] = zc(hn, 0.0);
       if (hn == 0.0) {
         m = j + 1;
         break;
       }
-      const T ih = (T)(1.0 / hn);
-      for (int i = t0; i < n; i += nt) {
-        const cx<T> w = Wn[i];
-        Wn[i] = mkc<T>(w.x * ih, w.y * ih);
-      }
-      __syncthreads();
+#pragma unroll
+      for (int t = 0; t <= kMaxV; ++t)
+        if (t == j + 1) sc[t] = 1.0 / hn;
     }
     __syncthreads();
     if (t0 == 0) hz_givens_lsq(H, kMaxV, m, beta, yls, gw, csw, snw);
+    __syncthreads();
+    // fold the lazy scales into the coefficients: v_t y_t = Vt_t (sc[t] y_t)
+    if (t0 == 0)
+#pragma unroll
+      for (int t = 0; t < kMaxV; ++t)
+        if (t < m) yls[t] = zc(yls[t].x * sc[t], yls[t].y * sc[t]);
     __syncthreads();
   }
   // 4. u += eta (d0 + V y)
