@@ -278,6 +278,72 @@ __device__ void hz_givens_lsq(double2* H, int ldh, int m, double beta, double2* 
   }
 }
 
+// Sweeps of an Arnoldi step over the rows of this work-item (rows threadIdx.x
+// + k blockDim.x of one column; the column's vectors are contiguous).  The
+// restrict-qualified parameters let the compiler issue the loads of the next
+// row before the store of the current one.
+// sweep 1: w = s (A x), stored to wn; acc_t += conj(V_t) w for t <= j
+template <class T>
+__device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__ col, const cx<T>* __restrict__ val,
+                                          const cx<T>* __restrict__ x, T s, const cx<T>* __restrict__ V, size_t NB,
+                                          int j, cx<T>* __restrict__ wn, double (&acc)[2 * (kMaxV + 1)]) {
+#pragma unroll 2
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T ar = 0, ai = 0;
+    for (int q = 0; q < w_; ++q) {
+      const int c = col[(size_t)q * n + i];
+      const cx<T> a = val[(size_t)q * n + i];
+      const cx<T> t = x[c];
+      ar += a.x * t.x - a.y * t.y;
+      ai += a.x * t.y + a.y * t.x;
+    }
+    const cx<T> w = mkc<T>(ar * s, ai * s);
+    wn[i] = w;
+#pragma unroll
+    for (int t = 0; t <= kMaxV; ++t) {
+      if (t <= j) {
+        const cx<T> q = V[(size_t)t * NB + i];     // conj(q) w
+        acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
+        acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
+      }
+    }
+  }
+}
+
+// update sweep: w -= sum_{t <= j} cf_t V_t in place; DOTS: acc_t += conj(V_t) w,
+// else acc_0 += |w|^2
+template <class T, bool DOTS>
+__device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V, size_t NB, int j,
+                                             const double (&cf)[2 * (kMaxV + 1)], cx<T>* __restrict__ wn,
+                                             double (&acc)[2 * (kMaxV + 1)]) {
+#pragma unroll 2
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    cx<T> w = wn[i];
+#pragma unroll
+    for (int t = 0; t <= kMaxV; ++t) {
+      if (t <= j) {
+        const cx<T> q = V[(size_t)t * NB + i];
+        const T hr = (T)cf[2 * t], hi = (T)cf[2 * t + 1];
+        w.x -= hr * q.x - hi * q.y;
+        w.y -= hr * q.y + hi * q.x;
+      }
+    }
+    wn[i] = w;
+    if (DOTS) {
+#pragma unroll
+      for (int t = 0; t <= kMaxV; ++t) {
+        if (t <= j) {
+          const cx<T> q = V[(size_t)t * NB + i];
+          acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
+          acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
+        }
+      }
+    } else {
+      acc[0] += (double)w.x * w.x + (double)w.y * w.y;
+    }
+  }
+}
+
 // One GMRES smoothing step on column blockIdx.x of level (A, G):
 //   r = f - A u;  d0 = theta Phi_B(r);  u += eta GMRES(A, r, d0, v)
 // scr holds v + 5 vectors of n x B values: r, two Horner buffers, d0,
@@ -381,20 +447,7 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
 #pragma unroll
       for (int t = 0; t <= kMaxV; ++t)
         if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
-      for (int i = t0; i < n; i += nt) {
-        T ar = 0, ai = 0;
-        ell_cmul<T, T, T>(A, Vj, i, 1, 0, ar, ai);
-        const cx<T> w = mkc<T>(ar * sjt, ai * sjt);
-        Wn[i] = w;
-#pragma unroll
-        for (int t = 0; t <= kMaxV; ++t) {
-          if (t <= j) {
-            const cx<T> q = V[(size_t)t * NB + i];     // conj(q) w
-            acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
-            acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
-          }
-        }
-      }
+      gm_sweep1<T>(n, A.w, A.col, A.val, Vj, sjt, V, NB, j, Wn, acc);
       hz_block_sum(acc, 2 * (j + 1), red, tot);
       // h_t = sc[t] acc_t; the update subtracts h_t v_t = (h_t sc[t]) Vt_t
       for (int pass = 0; pass < 2; ++pass) {
@@ -416,31 +469,8 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
 #pragma unroll
         for (int t = 0; t <= kMaxV; ++t)
           if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
-        for (int i = t0; i < n; i += nt) {
-          cx<T> w = Wn[i];
-#pragma unroll
-          for (int t = 0; t <= kMaxV; ++t) {
-            if (t <= j) {
-              const cx<T> q = V[(size_t)t * NB + i];
-              const T hr = (T)cf[2 * t], hi = (T)cf[2 * t + 1];
-              w.x -= hr * q.x - hi * q.y;
-              w.y -= hr * q.y + hi * q.x;
-            }
-          }
-          Wn[i] = w;
-          if (pass == 0) {
-#pragma unroll
-            for (int t = 0; t <= kMaxV; ++t) {
-              if (t <= j) {
-                const cx<T> q = V[(size_t)t * NB + i];
-                acc[2 * t] += (double)q.x * w.x + (double)q.y * w.y;
-                acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
-              }
-            }
-          } else {
-            acc[0] += (double)w.x * w.x + (double)w.y * w.y;
-          }
-        }
+        if (pass == 0) gm_sweep_upd<T, true>(n, V, NB, j, cf, Wn, acc);
+        else gm_sweep_upd<T, false>(n, V, NB, j, cf, Wn, acc);
         hz_block_sum(acc, pass == 0 ? 2 * (j + 1) : 1, red, tot);
       }
       const double hn = sqrt(acc[0]);
