@@ -175,3 +175,53 @@ def test_bench_configuration_cycle_and_fmg_solve():
     rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / np.linalg.norm(w.f, axis=0)
     print(f"bench-config fgmres-fmg iters {info.iters.min()}..{info.iters.max()} relres {rr.max():.2e}", flush=True)
     assert info.code == 0 and rr.max() <= 1.01e-8
+
+
+@pytest.mark.parametrize("B", [64, 256])
+def test_cycle_wide_batches(B):
+    """64 and the maximum 256 right-hand sides (lane groups of a whole
+    wavefront and of a whole work-group per row)."""
+    h, plan, f = case(17, 20.0, 3, B, seed=11)
+    K = (1, 1, 1)
+    flat = C.hz_random_params(3, *K, plan, seed=12)
+    want = OH.lmg(OH.make_levels(h.A, h.P, h.R), OH.unpack(flat, 3, *K, plan), 0, f, np.zeros_like(f))
+    c = ctx(h, plan, flat, K, B, "fp64")
+    u = c.empty()
+    u.zero_()
+    c.vcycle(dev(f, cdt("fp64")), u)
+    assert rel(u.cpu().numpy(), want) <= 1e-11
+
+
+def test_set_params_and_explicit_restriction():
+    """mgh_set_params replaces the weights (same plan); an explicit R = 0.5 P^T
+    is used as given."""
+    from paper_2608_29082_amd import helmholtz as HB
+    h, plan, f = case(33, 12.0, 4, 3, seed=13)
+    K = (2, 1, 1)
+    p1 = C.hz_random_params(4, *K, plan, seed=14)
+    p2 = C.hz_random_params(4, *K, plan, seed=15)
+    R = [0.5 * r for r in h.R]
+    c = HB.HelmholtzContext(h.A, h.P, p1, *K, plan, precision="fp64", nrhs=3, R=R)
+    lev = OH.make_levels(h.A, h.P, R)
+    for p in (p1, p2):
+        c.set_params(p)
+        u = c.empty()
+        u.zero_()
+        c.vcycle(dev(f, cdt("fp64")), u)
+        want = OH.lmg(lev, OH.unpack(p, 4, *K, plan), 0, f, np.zeros_like(f))
+        assert rel(u.cpu().numpy(), want) <= 1e-11
+
+
+def test_fgmres_is_deterministic():
+    """Block partial sums are reduced in a fixed order: two solves of the same
+    system give bitwise equal iterates and iteration counts."""
+    import torch
+    h, plan, f = case(65, 20.0, 5, 8, seed=16)
+    c = ctx(h, plan, C.hz_identity_params(5, 1, 1, 1, plan), (1, 1, 1), 8, "fp32")
+    xs, its = [], []
+    for _ in range(2):
+        x = torch.zeros(f.shape, dtype=torch.complex128, device="cuda")
+        info = c.fgmres(dev(f, torch.complex128), x, restart=20, max_iter=120, rtol=1e-8, precond="fmg")
+        xs.append(x.cpu().numpy())
+        its.append(info.iters.copy())
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(its[0], its[1])
