@@ -53,6 +53,17 @@ mg_status hfail(mg_status s, const std::string& m) {
   } while (0)
 
 constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 1024, kKrBlocks = 1024, kNG = 8;
+// per-work-item partial sums of a GMRES smoothing step: 2 (kMaxV + 1) dot
+// products (re, im) and one squared norm in the last slot
+constexpr int kAcc = 2 * (kMaxV + 1) + 1, kNorm = kAcc - 1;
+// vectors of a GMRES smoothing step: r, d0, V_0 .. V_v, and at least the two
+// Horner buffers in slots 3 and 4
+constexpr int hz_slots(int v) { return v + 3 > 5 ? v + 3 : 5; }
+// dynamic LDS of the LDS-resident GMRES smoothing step (static shared ~4 KB besides)
+constexpr int kGmresLds = 144 * 1024;
+// work-items of the LDS-resident step (its rows per work-item are cheap; the
+// larger register budget avoids spills)
+constexpr int kGTL = 512;
 
 template <class T> struct C2;
 template <> struct C2<float> { using t = float2; };
@@ -194,30 +205,32 @@ __global__ __launch_bounds__(256) void k_hz_copy(size_t cnt, const cx<T>* __rest
 }
 
 // ------------------------------------------------------------------ GMRES smoothing step
-// Block-wide sums of the first cnt of N doubles, broadcast to every work-item:
-// wavefront butterflies, then work-item k adds the waves' totals of value k in
-// wave order (a fixed order: deterministic).  lds: N x 16 doubles, tot: N.
+// Block-wide sums of the first cnt of N doubles (and of the last one when
+// last is set), broadcast to every work-item: wavefront butterflies, then
+// work-item k adds the waves' totals of value k in wave order (a fixed order:
+// deterministic).  lds: N x 16 doubles, tot: N.
 template <int N>
-__device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* lds, double* tot) {
+__device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* lds, double* tot, bool last = false) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    if (k < cnt) {
+    if (k < cnt || (last && k == N - 1)) {
       double x = a[k];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
       if (ln == 0) lds[k * 16 + wv] = x;
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < cnt) {
+  const int k0 = (int)threadIdx.x < cnt ? (int)threadIdx.x : (last && (int)threadIdx.x == cnt ? N - 1 : -1);
+  if (k0 >= 0) {
     double s = 0.0;
-    for (int q = 0; q < nw; ++q) s += lds[threadIdx.x * 16 + q];
-    tot[threadIdx.x] = s;
+    for (int q = 0; q < nw; ++q) s += lds[k0 * 16 + q];
+    tot[k0] = s;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < N; ++k)
-    if (k < cnt) a[k] = tot[k];
+    if (k < cnt || (last && k == N - 1)) a[k] = tot[k];
 }
 
 __device__ __forceinline__ double2 zc(double r, double i) { return make_double2(r, i); }
@@ -282,11 +295,12 @@ __device__ void hz_givens_lsq(double2* H, int ldh, int m, double beta, double2* 
 // + k blockDim.x of one column; the column's vectors are contiguous).  The
 // restrict-qualified parameters let the compiler issue the loads of the next
 // row before the store of the current one.
-// sweep 1: w = s (A x), stored to wn; acc_t += conj(V_t) w for t <= j
+// sweep 1: w = s (A x), stored to wn; acc_t += conj(V_t) w for t <= j and
+// acc[kNorm] += |w|^2
 template <class T>
 __device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__ col, const cx<T>* __restrict__ val,
                                           const cx<T>* __restrict__ x, T s, const cx<T>* __restrict__ V, size_t NB,
-                                          int j, cx<T>* __restrict__ wn, double (&acc)[2 * (kMaxV + 1)]) {
+                                          int j, cx<T>* __restrict__ wn, double (&acc)[kAcc]) {
 #pragma unroll 2
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     T ar = 0, ai = 0;
@@ -299,6 +313,7 @@ __device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__
     }
     const cx<T> w = mkc<T>(ar * s, ai * s);
     wn[i] = w;
+    acc[kNorm] += (double)w.x * w.x + (double)w.y * w.y;
 #pragma unroll
     for (int t = 0; t <= kMaxV; ++t) {
       if (t <= j) {
@@ -310,12 +325,12 @@ __device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__
   }
 }
 
-// update sweep: w -= sum_{t <= j} cf_t V_t in place; DOTS: acc_t += conj(V_t) w,
-// else acc_0 += |w|^2
+// update sweep: w -= sum_{t <= j} cf_t V_t in place; DOTS: acc_t += conj(V_t) w
+// and acc[kNorm] += |w|^2, else acc_0 += |w|^2
 template <class T, bool DOTS>
 __device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V, size_t NB, int j,
                                              const double (&cf)[2 * (kMaxV + 1)], cx<T>* __restrict__ wn,
-                                             double (&acc)[2 * (kMaxV + 1)]) {
+                                             double (&acc)[kAcc]) {
 #pragma unroll 2
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     cx<T> w = wn[i];
@@ -338,6 +353,7 @@ __device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V,
           acc[2 * t + 1] += (double)q.x * w.y - (double)q.y * w.x;
         }
       }
+      acc[kNorm] += (double)w.x * w.x + (double)w.y * w.y;
     } else {
       acc[0] += (double)w.x * w.x + (double)w.y * w.y;
     }
@@ -346,26 +362,31 @@ __device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V,
 
 // One GMRES smoothing step on column blockIdx.x of level (A, G):
 //   r = f - A u;  d0 = theta Phi_B(r);  u += eta GMRES(A, r, d0, v)
-// scr holds v + 5 vectors of n x B values: r, two Horner buffers, d0,
-// V_0 .. V_v, each stored column by column (column b of slot t at
-// scr + t n B + b n), so the work-group's sweeps over its column are
-// coalesced; f and u keep the [n][B] layout.  Orthogonalisation: classical
+// The step needs hz_slots(v) vectors of the column: r, d0, V_0 .. V_v (the
+// Horner buffers reuse V_1, V_2).  LDSV: they live in the work-group's LDS
+// (dynamic shared memory of hz_slots(v) n values); otherwise in scr, n x B
+// values per slot stored column by column (column b of slot t at
+// scr + t n B + b n) so the sweeps over a column are coalesced.  f and u keep
+// the [n][B] layout.  Orthogonalisation: classical
 // Gram-Schmidt applied twice per Arnoldi step; dot products and norms are
 // accumulated in FP64.
-template <class T>
-__global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
+template <class T, bool LDSV>
+__global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
                                                   const cx<T>* __restrict__ f, cx<T>* __restrict__ u, T theta,
                                                   T eta, WK<T> W, int K, int v, cx<T>* __restrict__ scr) {
-  __shared__ double red[2 * (kMaxV + 1) * 16], tot[2 * (kMaxV + 1)];
+  __shared__ double red[kAcc * 16], tot[kAcc];
   __shared__ double2 H[(kMaxV + 1) * kMaxV];
   __shared__ double2 yls[kMaxV], gw[kMaxV + 1], snw[kMaxV];
   __shared__ double csw[kMaxV];
+  extern __shared__ __align__(16) unsigned char hz_dyn[];
   const int b = blockIdx.x, n = A.n, nt = blockDim.x, t0 = threadIdx.x;
-  const size_t NB = (size_t)n * B;
-  cx<T>* base = scr + (size_t)b * n;           // slot t of this column: base + t NB
+  // LDSV: this column's vectors live in LDS (slot stride n); otherwise in the
+  // global scratch, column b of slot t at scr + t n B + b n
+  const size_t NB = LDSV ? (size_t)n : (size_t)n * B;
+  cx<T>* base = LDSV ? reinterpret_cast<cx<T>*>(hz_dyn) : scr + (size_t)b * n;
   cx<T>* R = base;
-  cx<T>* D0 = base + 3 * NB;
-  cx<T>* V = base + 4 * NB;
+  cx<T>* D0 = base + NB;
+  cx<T>* V = base + 2 * NB;                    // V_t in slot 2 + t; the Horner buffers are slots 3, 4
   // 1. residual
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
@@ -381,13 +402,14 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
       D0[i] = mkc<T>(theta * t.x, theta * t.y);
     }
   } else {
-    for (int i = t0; i < n; i += nt) base[NB + i] = mixw(W.w[K], R[i]);
+    // the Horner buffers take basis slots 1 and 2, unused until the Arnoldi steps
+    for (int i = t0; i < n; i += nt) base[3 * NB + i] = mixw(W.w[K], R[i]);
     __syncthreads();
     int cur = 0;
     for (int k = K - 1; k >= 0; --k) {
-      cx<T>* dst = k == 0 ? D0 : base + (size_t)(2 - cur) * NB;     // the other Horner buffer
+      cx<T>* dst = k == 0 ? D0 : base + (size_t)(4 - cur) * NB;     // the other Horner buffer
       const T s = k == 0 ? theta : (T)1;
-      const cx<T>* yc = base + (size_t)(1 + cur) * NB;
+      const cx<T>* yc = base + (size_t)(3 + cur) * NB;
       for (int i = t0; i < n; i += nt) {
         T mr = 0, mi = 0;
         for (int q = 0; q < G.w; ++q) {
@@ -410,7 +432,7 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
   }
   __syncthreads();
   // 3. r0 = r - A d0 and beta = ||r0||
-  double acc[2 * (kMaxV + 1)];
+  double acc[kAcc];
   acc[0] = 0.0;
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
@@ -443,13 +465,19 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
       const T sjt = (T)sj;
       const cx<T>* Vj = V + (size_t)j * NB;
       cx<T>* Wn = V + (size_t)(j + 1) * NB;
-      // sweep 1: w = A v_j and <Vt_t, w>
+      // sweep 1: w = A v_j, <Vt_t, w> and |w|^2
 #pragma unroll
       for (int t = 0; t <= kMaxV; ++t)
         if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
+      acc[kNorm] = 0.0;
       gm_sweep1<T>(n, A.w, A.col, A.val, Vj, sjt, V, NB, j, Wn, acc);
-      hz_block_sum(acc, 2 * (j + 1), red, tot);
-      // h_t = sc[t] acc_t; the update subtracts h_t v_t = (h_t sc[t]) Vt_t
+      hz_block_sum(acc, 2 * (j + 1), red, tot, true);
+      const double w2 = acc[kNorm];
+      // h_t = sc[t] acc_t; an update subtracts h_t v_t = (h_t sc[t]) Vt_t.  The
+      // first update also forms the second pass's dot products and the new
+      // norm; the second update runs only when the first cancelled more than
+      // 1 - 1/sqrt 2 of the norm (Kahan-Parlett), uniformly over the block.
+      double hn2 = 0.0;
       for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
         for (int t = 0; t <= kMaxV; ++t) {
@@ -469,11 +497,19 @@ __global__ __launch_bounds__(kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __
 #pragma unroll
         for (int t = 0; t <= kMaxV; ++t)
           if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
-        if (pass == 0) gm_sweep_upd<T, true>(n, V, NB, j, cf, Wn, acc);
-        else gm_sweep_upd<T, false>(n, V, NB, j, cf, Wn, acc);
-        hz_block_sum(acc, pass == 0 ? 2 * (j + 1) : 1, red, tot);
+        acc[kNorm] = 0.0;
+        if (pass == 0) {
+          gm_sweep_upd<T, true>(n, V, NB, j, cf, Wn, acc);
+          hz_block_sum(acc, 2 * (j + 1), red, tot, true);
+          hn2 = acc[kNorm];
+          if (!(hn2 < 0.5 * w2)) break;
+        } else {
+          gm_sweep_upd<T, false>(n, V, NB, j, cf, Wn, acc);
+          hz_block_sum(acc, 1, red, tot);
+          hn2 = acc[0];
+        }
       }
-      const double hn = sqrt(acc[0]);
+      const double hn = sqrt(hn2);
       if (t0 == 0) H[(j + 1) * kMaxV + j] = zc(hn, 0.0);
       if (hn == 0.0) {
         m = j + 1;
@@ -936,7 +972,8 @@ struct HzEngine final : mgh_ctx {
     const cx<T>* dinv = nullptr;
     REll<T> P{}, R{};            // P: n_l x n_{l+1}; R: n_{l+1} x n_l
     cx<T>*F = nullptr, *U = nullptr, *Rb = nullptr, *D = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Tb = nullptr;
-    cx<T>* scr = nullptr;        // GMRES scratch
+    cx<T>* scr = nullptr;        // GMRES scratch (global), or null when the step runs in LDS
+    size_t lds = 0;              // dynamic LDS bytes of the LDS-resident GMRES step
     int kind = MGH_JACOBI, pre = 0, post = 0;
   };
   int J = 0, Bn = 0, lb = 0, KB = 0, KR = 0, KP = 0, v = 4;
@@ -1036,8 +1073,12 @@ struct HzEngine final : mgh_ctx {
       H_LAUNCH();
       return conv(l, WB[l], KB, L.D, u, (T)eta[l], true, st);
     }
-    hipLaunchKernelGGL((k_hz_gmres<T>), dim3(Bn), dim3(kGT), 0, st, L.A, L.G, L.invdeg, Bn, f, u, (T)theta[l],
-                       (T)eta[l], WB[l], KB, v, L.scr);
+    if (L.lds)
+      hipLaunchKernelGGL((k_hz_gmres<T, true>), dim3(Bn), dim3(kGTL), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
+                         (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
+    else
+      hipLaunchKernelGGL((k_hz_gmres<T, false>), dim3(Bn), dim3(kGT), 0, st, L.A, L.G, L.invdeg, Bn, f, u,
+                         (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
     H_LAUNCH();
     return MG_OK;
   }
@@ -1396,7 +1437,13 @@ struct HzEngine final : mgh_ctx {
         H_TRY(mem.alloc(&L.Y0, nB));
         H_TRY(mem.alloc(&L.Y1, nB));
         H_TRY(mem.alloc(&L.Tb, nB));
-        if (L.kind == MGH_GMRES) H_TRY(mem.alloc(&L.scr, nB * (size_t)(v + 5)));
+        if (L.kind == MGH_GMRES) {
+          L.lds = (size_t)hz_slots(v) * n * sizeof(cx<T>);
+          if (L.lds > (size_t)kGmresLds) {
+            L.lds = 0;
+            H_TRY(mem.alloc(&L.scr, nB * (size_t)hz_slots(v)));
+          }
+        }
       }
     }
     // transfers
@@ -1468,6 +1515,8 @@ struct HzEngine final : mgh_ctx {
       for (size_t k = 0; k < inv.size(); ++k) inv[k] = make_double2(I[k].real(), I[k].imag());
       H_TRY(mem.upload(&Ainv, inv, st));
     }
+    H_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hz_gmres<T, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kGmresLds));
     H_HIP(hipHostMalloc((void**)&hcnt, sizeof(int)));
     H_HIP(hipStreamSynchronize(st));
     return MG_OK;

@@ -43,6 +43,7 @@ CYCLE_CASES = [
     (17, 40.0, 3, 2, (1, 1, 1), None, 4),                   # GMRES on the finest level
     (17, 5.0, 2, 1, (0, 0, 0), [("jacobi", 2, 1)], 4),      # two-grid, plain Jacobi, B = 1
     (33, 12.0, 3, 4, (3, 1, 1), [("gmres", 1, 0), ("jacobi", 0, 2)], 1),   # v = 1, nu = 0 sides
+    (65, 40.0, 4, 3, (1, 1, 1), None, 4),                   # GMRES on a 65 x 65 finest level: scratch in HBM
 ]
 
 
