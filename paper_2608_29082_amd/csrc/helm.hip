@@ -14,6 +14,7 @@
 // than the sweep.  The outer FGMRES runs in FP64 with multi-block reductions
 // in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
+#include <rocprim/warp/warp_reduce.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -206,7 +207,8 @@ __global__ __launch_bounds__(256) void k_hz_copy(size_t cnt, const cx<T>* __rest
 
 // ------------------------------------------------------------------ GMRES smoothing step
 // Block-wide sums of the first cnt of N doubles (and of the last one when
-// last is set), broadcast to every work-item: wavefront butterflies, then
+// last is set), broadcast to every work-item: wavefront reductions (rocPRIM's,
+// DPP lane moves on this target), then
 // work-item k adds the waves' totals of value k in wave order (a fixed order:
 // deterministic).  lds: N x 16 doubles, tot: N.
 template <int N>
@@ -215,8 +217,10 @@ __device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* ld
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (k < cnt || (last && k == N - 1)) {
-      double x = a[k];
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      using WR = rocprim::warp_reduce<double, 64>;
+      __shared__ typename WR::storage_type wst[16];
+      double x;
+      WR().reduce(a[k], x, wst[wv], rocprim::plus<double>());
       if (ln == 0) lds[k * 16 + wv] = x;
     }
   }
