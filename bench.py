@@ -438,8 +438,9 @@ def helmholtz(args):
     16 smoothed-disk sources.  FGMRES(40) to 1e-8 with the cycle or FMG as
     preconditioner, FP32 and FP64 cycles (one warm-up solve, one timed);
     the time of one cycle of the K = 1 form and of the form without
-    convolution hops (K = 0).  The oracle's FGMRES-FMG solve of one column is
-    the CPU-baseline leg's (cpu_baseline_helmholtz)."""
+    convolution hops (K = 0); FGMRES with FP32 cycles on 6, 7 and 8 levels of
+    the same problem.  The oracle's FGMRES-FMG solve of one column is the
+    CPU-baseline leg's (cpu_baseline_helmholtz)."""
     import torch
     from mginputs import configs as C
     from paper_2608_29082_amd import helmholtz as HB
@@ -485,6 +486,30 @@ def helmholtz(args):
             print(f"# helmholtz fgmres {pc} {prec}: {out[f'fgmres_{pc}_{prec}']}", file=sys.stderr, flush=True)
         out[f"cycle_ms_{prec}"] = cycle_ms(ctx)
         ctx.close()
+    # deeper hierarchies of the same problem (the paper's level sweep, J = 5..8), FP32 cycles
+    by_levels = {}
+    for Jx in (6, 7, 8):
+        wx = C.helmholtz(B=B, J=Jx)
+        cx_ = HB.from_workload(wx, precision="fp32")
+        row = {"smoothers": "".join("J" if p[0] == "jacobi" else "G" for p in wx.plan),
+               "coarsest_unknowns": wx.hier.sizes[-1]}
+        for pc in ("vcycle", "fmg"):
+            x = torch.zeros_like(f)
+            cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+            x.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            info = cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / fn
+            ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+            row[pc] = {"value": B / (tb - ta) if ok else 0.0, "iters_max": int(info.iters.max()),
+                       "iters_mean": float(info.iters.mean()), "converged": bool(ok)}
+        cx_.close()
+        by_levels[f"J{Jx}"] = row
+    out["fgmres_fp32_by_levels"] = by_levels
+    print(f"# helmholtz by levels: {json.dumps(by_levels)}", file=sys.stderr, flush=True)
     ctx0 = HB.HelmholtzContext(h.A, h.P, C.hz_identity_params(J, 0, 0, 0, w.plan), 0, 0, 0, w.plan, v=w.v,
                                precision="fp32", nrhs=B)
     out["cycle_ms_fp32_no_hops"] = cycle_ms(ctx0)
