@@ -53,7 +53,7 @@ mg_status hfail(mg_status s, const std::string& m) {
                                    hipGetErrorString(e_));                                       \
   } while (0)
 
-constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 1024, kKrBlocks = 1024, kNG = 8;
+constexpr int kMaxK = 8, kMaxV = 8, kMaxNu = 8, kMaxB = 256, kGT = 512, kKrBlocks = 1024, kNG = 8;
 // per-work-item partial sums of a GMRES smoothing step: 2 (kMaxV + 1) dot
 // products (re, im) and one squared norm in the last slot
 constexpr int kAcc = 2 * (kMaxV + 1) + 1, kNorm = kAcc - 1;
@@ -62,9 +62,8 @@ constexpr int kAcc = 2 * (kMaxV + 1) + 1, kNorm = kAcc - 1;
 constexpr int hz_slots(int v) { return v + 3 > 5 ? v + 3 : 5; }
 // dynamic LDS of the LDS-resident GMRES smoothing step (static shared ~4 KB besides)
 constexpr int kGmresLds = 144 * 1024;
-// work-items of the LDS-resident step (its rows per work-item are cheap; the
-// larger register budget avoids spills)
-constexpr int kGTL = 512;
+// work-items of the GMRES smoothing step with its vectors in HBM scratch
+constexpr int kGTH = 1024;
 
 template <class T> struct C2;
 template <> struct C2<float> { using t = float2; };
@@ -89,16 +88,31 @@ template <class T>
 __device__ __forceinline__ cx<T> mixw(const W2<T>& W, cx<T> x) {
   return mkc<T>(W.a * x.x + W.b * x.y, W.c * x.x + W.d * x.y);
 }
-// (A x)_i of a complex ELL matrix, accumulated in AT
-template <class AT, class T, class X>
+// (A x)_i of a complex ELL matrix, accumulated in AT.  Slots go in groups of
+// kSlots: all column indices and values of a group are loaded before the
+// gathers, so a row costs one dependent round trip per group.
+constexpr int kSlots = 8;
+template <class AT, class T, class X, int SG = kSlots>
 __device__ __forceinline__ void ell_cmul(const CEll<T>& A, const cx<X>* x, int i, int B, int b, AT& ar, AT& ai) {
-  for (int s = 0; s < A.w; ++s) {
-    const int j = A.col[(size_t)s * A.n + i];
-    const cx<T> a = A.val[(size_t)s * A.n + i];
-    const cx<X> t = x[(size_t)j * B + b];
-    const AT tr = (AT)t.x, ti = (AT)t.y;
-    ar += (AT)a.x * tr - (AT)a.y * ti;
-    ai += (AT)a.x * ti + (AT)a.y * tr;
+  for (int s0 = 0; s0 < A.w; s0 += SG) {
+    int c[SG];
+    cx<T> a[SG];
+#pragma unroll
+    for (int q = 0; q < SG; ++q) {
+      if (s0 + q < A.w) {
+        c[q] = A.col[(size_t)(s0 + q) * A.n + i];
+        a[q] = A.val[(size_t)(s0 + q) * A.n + i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SG; ++q) {
+      if (s0 + q < A.w) {
+        const cx<X> t = x[(size_t)c[q] * B + b];
+        const AT tr = (AT)t.x, ti = (AT)t.y;
+        ar += (AT)a[q].x * tr - (AT)a[q].y * ti;
+        ai += (AT)a[q].x * ti + (AT)a[q].y * tr;
+      }
+    }
   }
 }
 
@@ -300,20 +314,32 @@ __device__ void hz_givens_lsq(double2* H, int ldh, int m, double beta, double2* 
 // restrict-qualified parameters let the compiler issue the loads of the next
 // row before the store of the current one.
 // sweep 1: w = s (A x), stored to wn; acc_t += conj(V_t) w for t <= j and
-// acc[kNorm] += |w|^2
-template <class T>
+// acc[kNorm] += |w|^2 (slots loaded in groups of SG, as in ell_cmul)
+template <class T, int SG>
 __device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__ col, const cx<T>* __restrict__ val,
                                           const cx<T>* __restrict__ x, T s, const cx<T>* __restrict__ V, size_t NB,
                                           int j, cx<T>* __restrict__ wn, double (&acc)[kAcc]) {
 #pragma unroll 2
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     T ar = 0, ai = 0;
-    for (int q = 0; q < w_; ++q) {
-      const int c = col[(size_t)q * n + i];
-      const cx<T> a = val[(size_t)q * n + i];
-      const cx<T> t = x[c];
-      ar += a.x * t.x - a.y * t.y;
-      ai += a.x * t.y + a.y * t.x;
+    for (int s0 = 0; s0 < w_; s0 += SG) {
+      int c[SG];
+      cx<T> a[SG];
+#pragma unroll
+      for (int q = 0; q < SG; ++q) {
+        if (s0 + q < w_) {
+          c[q] = col[(size_t)(s0 + q) * n + i];
+          a[q] = val[(size_t)(s0 + q) * n + i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < SG; ++q) {
+        if (s0 + q < w_) {
+          const cx<T> t = x[c[q]];
+          ar += a[q].x * t.x - a[q].y * t.y;
+          ai += a[q].x * t.y + a[q].y * t.x;
+        }
+      }
     }
     const cx<T> w = mkc<T>(ar * s, ai * s);
     wn[i] = w;
@@ -367,15 +393,17 @@ __device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V,
 // One GMRES smoothing step on column blockIdx.x of level (A, G):
 //   r = f - A u;  d0 = theta Phi_B(r);  u += eta GMRES(A, r, d0, v)
 // The step needs hz_slots(v) vectors of the column: r, d0, V_0 .. V_v (the
-// Horner buffers reuse V_1, V_2).  LDSV: they live in the work-group's LDS
-// (dynamic shared memory of hz_slots(v) n values); otherwise in scr, n x B
-// values per slot stored column by column (column b of slot t at
+// Horner buffers reuse V_1, V_2).  MODE 1: all of them live in the
+// work-group's LDS (dynamic shared memory of hz_slots(v) n values); MODE 2:
+// the basis vectors V_0 .. V_{v-1}, which every sweep reads, live in LDS (v n
+// values, v >= 3) and r, d0 and V_v in scr; MODE 0: all in scr.  scr holds
+// n x B values per slot stored column by column (column b of slot t at
 // scr + t n B + b n) so the sweeps over a column are coalesced.  f and u keep
 // the [n][B] layout.  Orthogonalisation: classical
 // Gram-Schmidt applied twice per Arnoldi step; dot products and norms are
 // accumulated in FP64.
-template <class T, bool LDSV>
-__global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
+template <class T, int MODE>
+__global__ __launch_bounds__(MODE ? kGT : kGTH) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
                                                   const cx<T>* __restrict__ f, cx<T>* __restrict__ u, T theta,
                                                   T eta, WK<T> W, int K, int v, cx<T>* __restrict__ scr) {
   __shared__ double red[kAcc * 16], tot[kAcc];
@@ -384,17 +412,22 @@ __global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll 
   __shared__ double csw[kMaxV];
   extern __shared__ __align__(16) unsigned char hz_dyn[];
   const int b = blockIdx.x, n = A.n, nt = blockDim.x, t0 = threadIdx.x;
-  // LDSV: this column's vectors live in LDS (slot stride n); otherwise in the
-  // global scratch, column b of slot t at scr + t n B + b n
-  const size_t NB = LDSV ? (size_t)n : (size_t)n * B;
-  cx<T>* base = LDSV ? reinterpret_cast<cx<T>*>(hz_dyn) : scr + (size_t)b * n;
-  cx<T>* R = base;
-  cx<T>* D0 = base + NB;
-  cx<T>* V = base + 2 * NB;                    // V_t in slot 2 + t; the Horner buffers are slots 3, 4
+  // slot group of the SpMVs: the HBM-scratch form runs 1024 work-items with
+  // half the registers per work-item
+  constexpr int SG = MODE ? kSlots : kSlots / 2;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(hz_dyn);
+  cx<T>* gcol = scr + (size_t)b * n;           // this column's slot 0 in the global scratch
+  const size_t GS = (size_t)n * B;             // global slot stride
+  cx<T>* R = MODE == 1 ? lds : gcol;
+  cx<T>* D0 = MODE == 1 ? lds + n : gcol + GS;
+  // V_t = V + t NB for t < v; the Horner buffers are V_1 and V_2
+  const size_t NB = MODE == 0 ? GS : (size_t)n;
+  cx<T>* V = MODE == 0 ? gcol + 2 * GS : (MODE == 1 ? lds + 2 * (size_t)n : lds);
+  cx<T>* Vlast = MODE == 2 ? gcol + 2 * GS : V + (size_t)v * NB;     // V_v
   // 1. residual
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
-    ell_cmul<T, T, T>(A, u, i, B, b, ar, ai);
+    ell_cmul<T, T, T, SG>(A, u, i, B, b, ar, ai);
     const cx<T> fi = f[(size_t)i * B + b];
     R[i] = mkc<T>(fi.x - ar, fi.y - ai);
   }
@@ -407,13 +440,13 @@ __global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll 
     }
   } else {
     // the Horner buffers take basis slots 1 and 2, unused until the Arnoldi steps
-    for (int i = t0; i < n; i += nt) base[3 * NB + i] = mixw(W.w[K], R[i]);
+    for (int i = t0; i < n; i += nt) V[NB + i] = mixw(W.w[K], R[i]);
     __syncthreads();
     int cur = 0;
     for (int k = K - 1; k >= 0; --k) {
-      cx<T>* dst = k == 0 ? D0 : base + (size_t)(4 - cur) * NB;     // the other Horner buffer
+      cx<T>* dst = k == 0 ? D0 : V + (size_t)(2 - cur) * NB;     // the other Horner buffer
       const T s = k == 0 ? theta : (T)1;
-      const cx<T>* yc = base + (size_t)(3 + cur) * NB;
+      const cx<T>* yc = V + (size_t)(1 + cur) * NB;
       for (int i = t0; i < n; i += nt) {
         T mr = 0, mi = 0;
         for (int q = 0; q < G.w; ++q) {
@@ -440,7 +473,7 @@ __global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll 
   acc[0] = 0.0;
   for (int i = t0; i < n; i += nt) {
     T ar = 0, ai = 0;
-    ell_cmul<T, T, T>(A, D0, i, 1, 0, ar, ai);
+    ell_cmul<T, T, T, SG>(A, D0, i, 1, 0, ar, ai);
     const cx<T> ri = R[i];
     const cx<T> t = mkc<T>(ri.x - ar, ri.y - ai);
     V[i] = t;
@@ -468,13 +501,13 @@ __global__ __launch_bounds__(LDSV ? kGTL : kGT) void k_hz_gmres(CEll<T> A, GEll 
         if (t == j) sj = sc[t];
       const T sjt = (T)sj;
       const cx<T>* Vj = V + (size_t)j * NB;
-      cx<T>* Wn = V + (size_t)(j + 1) * NB;
+      cx<T>* Wn = j + 1 < v ? V + (size_t)(j + 1) * NB : Vlast;
       // sweep 1: w = A v_j, <Vt_t, w> and |w|^2
 #pragma unroll
       for (int t = 0; t <= kMaxV; ++t)
         if (t <= j) acc[2 * t] = acc[2 * t + 1] = 0.0;
       acc[kNorm] = 0.0;
-      gm_sweep1<T>(n, A.w, A.col, A.val, Vj, sjt, V, NB, j, Wn, acc);
+      gm_sweep1<T, SG>(n, A.w, A.col, A.val, Vj, sjt, V, NB, j, Wn, acc);
       hz_block_sum(acc, 2 * (j + 1), red, tot, true);
       const double w2 = acc[kNorm];
       // h_t = sc[t] acc_t; an update subtracts h_t v_t = (h_t sc[t]) Vt_t.  The
@@ -977,7 +1010,8 @@ struct HzEngine final : mgh_ctx {
     REll<T> P{}, R{};            // P: n_l x n_{l+1}; R: n_{l+1} x n_l
     cx<T>*F = nullptr, *U = nullptr, *Rb = nullptr, *D = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Tb = nullptr;
     cx<T>* scr = nullptr;        // GMRES scratch (global), or null when the step runs in LDS
-    size_t lds = 0;              // dynamic LDS bytes of the LDS-resident GMRES step
+    size_t lds = 0;              // dynamic LDS bytes of the GMRES step
+    int gmode = 0;               // placement of its vectors (k_hz_gmres MODE)
     int kind = MGH_JACOBI, pre = 0, post = 0;
   };
   int J = 0, Bn = 0, lb = 0, KB = 0, KR = 0, KP = 0, v = 4;
@@ -1077,11 +1111,14 @@ struct HzEngine final : mgh_ctx {
       H_LAUNCH();
       return conv(l, WB[l], KB, L.D, u, (T)eta[l], true, st);
     }
-    if (L.lds)
-      hipLaunchKernelGGL((k_hz_gmres<T, true>), dim3(Bn), dim3(kGTL), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
+    if (L.gmode == 1)
+      hipLaunchKernelGGL((k_hz_gmres<T, 1>), dim3(Bn), dim3(kGT), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
+                         (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
+    else if (L.gmode == 2)
+      hipLaunchKernelGGL((k_hz_gmres<T, 2>), dim3(Bn), dim3(kGT), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
                          (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
     else
-      hipLaunchKernelGGL((k_hz_gmres<T, false>), dim3(Bn), dim3(kGT), 0, st, L.A, L.G, L.invdeg, Bn, f, u,
+      hipLaunchKernelGGL((k_hz_gmres<T, 0>), dim3(Bn), dim3(kGTH), 0, st, L.A, L.G, L.invdeg, Bn, f, u,
                          (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
     H_LAUNCH();
     return MG_OK;
@@ -1442,8 +1479,16 @@ struct HzEngine final : mgh_ctx {
         H_TRY(mem.alloc(&L.Y1, nB));
         H_TRY(mem.alloc(&L.Tb, nB));
         if (L.kind == MGH_GMRES) {
-          L.lds = (size_t)hz_slots(v) * n * sizeof(cx<T>);
-          if (L.lds > (size_t)kGmresLds) {
+          const size_t all = (size_t)hz_slots(v) * n * sizeof(cx<T>), basis = (size_t)v * n * sizeof(cx<T>);
+          if (all <= (size_t)kGmresLds) {
+            L.gmode = 1;
+            L.lds = all;
+          } else if (v >= 3 && basis <= (size_t)kGmresLds) {
+            L.gmode = 2;
+            L.lds = basis;
+            H_TRY(mem.alloc(&L.scr, nB * 3));
+          } else {
+            L.gmode = 0;
             L.lds = 0;
             H_TRY(mem.alloc(&L.scr, nB * (size_t)hz_slots(v)));
           }
@@ -1519,7 +1564,9 @@ struct HzEngine final : mgh_ctx {
       for (size_t k = 0; k < inv.size(); ++k) inv[k] = make_double2(I[k].real(), I[k].imag());
       H_TRY(mem.upload(&Ainv, inv, st));
     }
-    H_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hz_gmres<T, true>),
+    H_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hz_gmres<T, 1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kGmresLds));
+    H_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hz_gmres<T, 2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kGmresLds));
     H_HIP(hipHostMalloc((void**)&hcnt, sizeof(int)));
     H_HIP(hipStreamSynchronize(st));
