@@ -9,10 +9,10 @@
 // transfers, the dense coarsest solve) are bandwidth bound and stream their
 // operands once.  A GMRES smoothing step (v Arnoldi steps with block-wide
 // reductions, the small least-squares problem and the update) runs as one
-// kernel with one work-group per column: the levels that use it are the
-// coarse ones (k h > 1/2), where a launch per Arnoldi sweep would cost more
-// than the sweep.  The outer FGMRES runs in FP64 with multi-block reductions
-// in a fixed order (deterministic).
+// kernel with one work-group per column, its vectors in LDS where they fit:
+// the levels that use it are the coarse ones (k h > 1/2), where a launch per
+// Arnoldi sweep would cost more than the sweep.  The outer FGMRES runs in
+// FP64 with multi-block reductions in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 #include <rocprim/warp/warp_reduce.hpp>
 
