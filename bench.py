@@ -486,6 +486,48 @@ def helmholtz(args):
             print(f"# helmholtz fgmres {pc} {prec}: {out[f'fgmres_{pc}_{prec}']}", file=sys.stderr, flush=True)
         out[f"cycle_ms_{prec}"] = cycle_ms(ctx)
         ctx.close()
+    # the shipped trained parameters (train_helmholtz.py: Rprop on the loss after 10 cycles, training
+    # sources disjoint from these), FP32 cycles, and the stationary iteration with FP64 cycles
+    theta = np.load(os.path.join(ROOT, "paper_2608_29082_amd", "theta", "hz_k1_helmholtz257.npy"))
+    ctx = HB.from_workload(w, precision="fp32", params=theta)
+    for pc in ("vcycle", "fmg"):
+        x = torch.zeros_like(f)
+        ctx.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+        x.zero_()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        info = ctx.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / fn
+        ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+        out[f"fgmres_{pc}_fp32_learned"] = {"value": B / (tb - ta) if ok else 0.0, "unit": "solves/s",
+                                            "iters_max": int(info.iters.max()),
+                                            "iters_mean": float(info.iters.mean()),
+                                            "relres_max_fp64_host": float(rr.max()), "converged": bool(ok)}
+        print(f"# helmholtz learned fgmres {pc}: {out[f'fgmres_{pc}_fp32_learned']}", file=sys.stderr, flush=True)
+    ctx.close()
+    ctx = HB.from_workload(w, precision="fp64", params=theta)
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    cycles, rel = 0, None
+    while cycles < 400:
+        ctx.vcycle(f, u)
+        cycles += 1
+        _, norms = ctx.residual(f, u, want_r=False)
+        rel = norms.cpu().numpy() / fn
+        if not np.all(np.isfinite(rel)) or rel.max() <= 1e-8:
+            break
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ok = bool(rel is not None and np.all(np.isfinite(rel)) and rel.max() <= 1e-8)
+    out["stationary_fp64_learned"] = {"value": B / (tb - ta) if ok else 0.0, "unit": "solves/s", "cycles": cycles,
+                                      "converged": ok,
+                                      "note": "u <- LMG(A, f, u) with the residual checked after every cycle"}
+    ctx.close()
+    out["params_learned"] = "hz_k1_helmholtz257 (trained on 8 random-disk sources, seeds disjoint from these)"
+
     # deeper hierarchies of the same problem (the paper's level sweep, J = 5..8), FP32 cycles
     by_levels = {}
     for Jx in (6, 7, 8):

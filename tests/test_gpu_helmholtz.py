@@ -226,3 +226,28 @@ def test_fgmres_is_deterministic():
         xs.append(x.cpu().numpy())
         its.append(info.iters.copy())
     assert np.array_equal(xs[0], xs[1]) and np.array_equal(its[0], its[1])
+
+
+def test_training_loss_matches_oracle_and_descends():
+    """The Helmholtz training loss evaluated through the library (m FP64
+    cycles from zero) equals the oracle's, and steps against the sign of its
+    central-difference gradient reduce it."""
+    from paper_2608_29082_amd import train_helmholtz as TH
+    w = C.helmholtz(33, 12.0, 4, B=2)
+    f = HZ.load_vectors(33, HZ.source_centres(5, C.rng(10, 2, 1))[2:])
+    loss = TH.Loss(w, f, 4)
+    p = C.hz_random_params(4, 1, 1, 1, w.plan, seed=20, spread=0.05)
+    L = loss(p)
+    lev = OH.make_levels(w.hier.A, w.hier.P, w.hier.R)
+    prm = OH.unpack(p, 4, 1, 1, 1, w.plan)
+    u = np.zeros_like(f)
+    for _ in range(4):
+        u = OH.lmg(lev, prm, 0, f, u)
+    Lo = float(np.mean(np.linalg.norm(f - w.hier.A[0] @ u, axis=0) ** 2 / np.linalg.norm(f, axis=0) ** 2))
+    print(f"training loss gpu {L:.6e} oracle {Lo:.6e}", flush=True)
+    assert abs(L - Lo) <= 1e-9 * Lo
+    q = p.copy()
+    for _ in range(3):
+        g = loss.grad(q, 1e-6)
+        q = q - 0.005 * np.sign(g)
+    assert loss(q) < L
