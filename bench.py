@@ -529,26 +529,29 @@ def helmholtz(args):
     out["params_learned"] = "hz_k1_helmholtz257 (trained on 8 random-disk sources, seeds disjoint from these)"
 
     # deeper hierarchies of the same problem (the paper's level sweep, J = 5..8), FP32 cycles
+    # (identity parameters, and the 5-level trained ones moved over by the partial transfer rule)
+    from paper_2608_29082_amd import train_helmholtz as TH
     by_levels = {}
     for Jx in (6, 7, 8):
         wx = C.helmholtz(B=B, J=Jx)
-        cx_ = HB.from_workload(wx, precision="fp32")
         row = {"smoothers": "".join("J" if p[0] == "jacobi" else "G" for p in wx.plan),
                "coarsest_unknowns": wx.hier.sizes[-1]}
-        for pc in ("vcycle", "fmg"):
-            x = torch.zeros_like(f)
-            cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
-            x.zero_()
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            info = cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
-            torch.cuda.synchronize()
-            tb = time.perf_counter()
-            rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / fn
-            ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
-            row[pc] = {"value": B / (tb - ta) if ok else 0.0, "iters_max": int(info.iters.max()),
-                       "iters_mean": float(info.iters.mean()), "converged": bool(ok)}
-        cx_.close()
+        for label, prm in (("", wx.params), ("_transferred", TH.transfer(theta, w.plan, wx.plan, 1))):
+            cx_ = HB.from_workload(wx, precision="fp32", params=prm)
+            for pc in ("vcycle", "fmg"):
+                x = torch.zeros_like(f)
+                cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+                x.zero_()
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                info = cx_.fgmres(f, x, restart=40, max_iter=200, rtol=1e-8, precond=pc)
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                rr = np.linalg.norm(w.f - h.A[0] @ x.cpu().numpy(), axis=0) / fn
+                ok = info.code == 0 and float(rr.max()) <= 1e-8 * (1 + 1e-3)
+                row[pc + label] = {"value": B / (tb - ta) if ok else 0.0, "iters_max": int(info.iters.max()),
+                                   "iters_mean": float(info.iters.mean()), "converged": bool(ok)}
+            cx_.close()
         by_levels[f"J{Jx}"] = row
     out["fgmres_fp32_by_levels"] = by_levels
     print(f"# helmholtz by levels: {json.dumps(by_levels)}", file=sys.stderr, flush=True)

@@ -45,6 +45,35 @@ def parse(argv=None):
     return ap.parse_args(argv)
 
 
+def transfer(theta, plan_src, plan_dst, K: int) -> np.ndarray:
+    """Partial weight transfer to another hierarchy (Sec. 4.2, the transfer
+    rule): a target level whose smoother kind matches the source level of the
+    same index takes its weights; a target level beyond the source's takes the
+    deepest source level of its kind; a level without a match keeps the
+    classical (identity) weights of its kind; the shared Phi_R and Phi_P are
+    always copied.  plan_*: per level (kind, nu_pre, nu_post)."""
+    from mginputs import configs as C
+    per = 2 + 4 * (K + 1)
+    Js, Jd = len(plan_src) + 1, len(plan_dst) + 1
+    src = np.asarray(theta, dtype=np.float64)
+    assert src.size == C.hz_n_params(Js, K, K, K)
+    out = C.hz_identity_params(Jd, K, K, K, plan_dst)
+    lv_s = src[:(Js - 1) * per].reshape(Js - 1, per)
+    lv_d = out[:(Jd - 1) * per].reshape(Jd - 1, per)
+    for l in range(Jd - 1):
+        kind = plan_dst[l][0]
+        if l < Js - 1:
+            if plan_src[l][0] == kind:
+                lv_d[l] = lv_s[l]
+        else:
+            for m in range(Js - 2, -1, -1):
+                if plan_src[m][0] == kind:
+                    lv_d[l] = lv_s[m]
+                    break
+    out[(Jd - 1) * per:] = src[(Js - 1) * per:]
+    return out
+
+
 class Loss:
     """L(theta) on the GPU: m FP64 cycles from zero on the training sources."""
 
