@@ -42,6 +42,12 @@ def parse(argv=None):
     ap.add_argument("--init", default=None, help="start from this parameter file (.npy)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--eval-B", type=int, default=16)
+    ap.add_argument("--eval-only", default=None,
+                    help="evaluate this parameter file (trained on any hierarchy of the same problem family, moved "
+                         "over by the partial transfer rule) on --side/--k/--levels and exit")
+    ap.add_argument("--src-side", type=int, default=None, help="--eval-only: side of the source hierarchy")
+    ap.add_argument("--src-k", type=float, default=None, help="--eval-only: wave number of the source problem")
+    ap.add_argument("--src-levels", type=int, default=None, help="--eval-only: levels of the source hierarchy")
     return ap.parse_args(argv)
 
 
@@ -161,6 +167,15 @@ def main(argv=None):
 
     w = C.helmholtz(args.side, args.k, args.levels, B=args.eval_B, K=args.K)
     J = w.hier.nlevels
+    if args.eval_only:
+        src_plan = HZ.smoother_plan(HZ.hierarchy(args.src_side or args.side, args.src_k or args.k,
+                                                 args.src_levels or args.levels))
+        theta = transfer(np.load(args.eval_only), src_plan, w.plan, args.K)
+        ev = {"identity": evaluate(w, C.hz_identity_params(J, args.K, args.K, args.K, w.plan), args.eval_B),
+              "transferred": evaluate(w, theta, args.eval_B)}
+        print(json.dumps({"params": os.path.basename(args.eval_only), "target": f"helmholtz-{args.side}",
+                          "k": args.k, "levels": J, "eval": ev}))
+        return
     # training sources: random disks only (columns 0 and 1 of every source set are the paper's two
     # fixed sources), seeds disjoint from the benchmark's
     cents = HZ.source_centres(args.B + 2, C.rng(10, 2, 1))[2:]
