@@ -108,12 +108,13 @@ mg_status mgh_set_params(mgh_ctx* ctx, const double* values, void* stream);
 
 /* One learnable V-cycle on the finest level, in place: u <- LMG(A_0, f, u)
  * (Alg. 2 with the per-level smoothers above).  f, u: cycle-type complex
- * vectors [n_0 x B]; f and u must not overlap. */
+ * vectors [n_0 x B]; f and u must not overlap (MG_ERR_INVALID_ARG). */
 mg_status mgh_vcycle(mgh_ctx* ctx, const void* f, void* u, void* stream);
 
 /* Full multigrid with one cycle per level (Sec. 4.2, FMG paragraph):
  * f_{l+1} = R_l Phi_R(f_l), exact coarsest solve, u_l = LMG(A_l, f_l,
- * Phi_P(P_l u_{l+1})).  f, u: cycle-type complex vectors; u is overwritten. */
+ * Phi_P(P_l u_{l+1})).  f, u: cycle-type complex vectors that must not
+ * overlap; u is overwritten. */
 mg_status mgh_fmg(mgh_ctx* ctx, const void* f, void* u, void* stream);
 
 /* FP64 residual r = f - A_0 u (r may be NULL) and its per-column 2-norms

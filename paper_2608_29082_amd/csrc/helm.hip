@@ -1175,8 +1175,18 @@ struct HzEngine final : mgh_ctx {
     return MG_OK;
   }
 
+  // the cycle reads f after it has started writing u
+  mg_status check_disjoint(const void* f, const void* u) const {
+    const size_t bytes = (size_t)lv[0].n * Bn * sizeof(cx<T>);
+    const char* a = static_cast<const char*>(f);
+    const char* b = static_cast<const char*>(u);
+    if (a < b + bytes && b < a + bytes) return hfail(MG_ERR_INVALID_ARG, "f and u overlap");
+    return MG_OK;
+  }
+
   mg_status vcycle(const void* f, void* u, hipStream_t st) override {
     if (!f || !u) return hfail(MG_ERR_INVALID_ARG, "null vector");
+    H_TRY(check_disjoint(f, u));
     return cycle(0, static_cast<const cx<T>*>(f), static_cast<cx<T>*>(u), st);
   }
 
@@ -1197,6 +1207,7 @@ struct HzEngine final : mgh_ctx {
   }
   mg_status fmg(const void* f, void* u, hipStream_t st) override {
     if (!f || !u) return hfail(MG_ERR_INVALID_ARG, "null vector");
+    H_TRY(check_disjoint(f, u));
     return fmg_(static_cast<const cx<T>*>(f), static_cast<cx<T>*>(u), st);
   }
 

@@ -251,3 +251,16 @@ def test_training_loss_matches_oracle_and_descends():
         g = loss.grad(q, 1e-6)
         q = q - 0.005 * np.sign(g)
     assert loss(q) < L
+
+
+def test_overlapping_f_and_u_are_rejected():
+    """mgh_vcycle and mgh_fmg reject f and u that share memory (the cycle
+    reads f after it started writing u) with MG_ERR_INVALID_ARG."""
+    from paper_2608_29082_amd import binding as Bd
+    h, plan, f = case(17, 5.0, 2, 2, seed=21, plan=[("jacobi", 1, 1)])
+    c = ctx(h, plan, C.hz_identity_params(2, 1, 1, 1, plan), (1, 1, 1), 2, "fp64")
+    x = dev(f, cdt("fp64"))
+    for call in (c.vcycle, c.fmg):
+        with pytest.raises(Bd.MGError) as e:
+            call(x, x)
+        assert e.value.status == 1
