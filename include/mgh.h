@@ -138,6 +138,20 @@ mg_status mgh_residual(mgh_ctx* ctx, const double* f, const double* u, double* r
 mg_status mgh_fgmres(mgh_ctx* ctx, const double* f, double* u, const mg_krylov_options* o,
                      mg_rhs_info* info, void* stream);
 
+/* Stationary iteration u <- LMG(A_0, f, u) per column from the given u
+ * (the paper's use of the cycle as an iterative solver, Sec. 4.2 tables):
+ * a column stops at the first iterate with ||f - A_0 u|| <= rtol ||f||
+ * (FP64 residual after every cycle, decided on the device) and then keeps
+ * that iterate, or when its residual is not finite; at most max_cycles
+ * cycles.  Needs an MG_FP64 context (MG_ERR_UNSUPPORTED otherwise: the cycle
+ * is not affine, so lower-precision cycles have no refinement form).  f, u:
+ * double complex [n_0 x B], not overlapping.  Blocks the calling thread (reads
+ * the active-column count every check_every cycles).  info: host [B] or NULL;
+ * info[b].iters counts the cycles applied to column b.  Returns MG_OK,
+ * MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED. */
+mg_status mgh_solve(mgh_ctx* ctx, const double* f, double* u, double rtol, int32_t max_cycles,
+                    int32_t check_every, mg_rhs_info* info, void* stream);
+
 /* Level sizes n_l (host int64 [J]). */
 mg_status mgh_level_info(const mgh_ctx* ctx, int64_t* n);
 

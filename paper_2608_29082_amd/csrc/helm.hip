@@ -22,6 +22,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mgh.h"
@@ -934,6 +935,44 @@ __global__ __launch_bounds__(256) void k_fx_sqrt(int B, const double2* __restric
   if (b < B) out[b] = sqrt(in[b].x);
 }
 
+// stationary solve: u[:, b] = w[:, b] for the columns still iterating
+__global__ __launch_bounds__(256) void k_hz_take(int n, int B, int lb, const int* __restrict__ act,
+                                                 const double2* __restrict__ w, double2* __restrict__ u) {
+  HZ_ROW(n)
+  if (act[b]) u[o] = w[o];
+}
+
+// stationary solve, after each cycle (first: the start): per column the
+// residual norm beta = sqrt(nrm2), a column stops at the first iterate with
+// beta <= rtol fnorm (MG_OK) or a non-finite beta (MG_ERR_DIVERGED); iters
+// counts the cycles applied to it; cnt = columns still iterating
+__global__ __launch_bounds__(256) void k_hz_solve_check(FxState S, int B, const double2* __restrict__ nrm2,
+                                                        double rtol, int first) {
+  const int b = threadIdx.x;
+  if (b < B) {
+    const double nr = sqrt(nrm2[b].x);
+    if (first) {
+      S.status[b] = -1;
+      S.iters[b] = 0;
+      S.act[b] = 1;
+    } else if (S.act[b]) {
+      S.iters[b] += 1;
+    }
+    if (S.act[b]) {
+      S.beta[b] = nr;
+      if (!isfinite(nr)) {
+        S.status[b] = MG_ERR_DIVERGED;
+        S.act[b] = 0;
+      } else if (nr <= rtol * S.fnorm[b]) {
+        S.status[b] = MG_OK;
+        S.act[b] = 0;
+      }
+    }
+  }
+  __syncthreads();
+  fx_count(S, B);
+}
+
 // ------------------------------------------------------------------ host side
 using zd = std::complex<double>;
 
@@ -994,6 +1033,8 @@ struct mgh_ctx {
   virtual mg_status residual(const double* f, const double* u, double* r, double* norms, hipStream_t st) = 0;
   virtual mg_status fgmres(const double* f, double* u, const mg_krylov_options* o, mg_rhs_info* info,
                            hipStream_t st) = 0;
+  virtual mg_status solve(const double* f, double* u, double rtol, int max_cycles, int check_every,
+                          mg_rhs_info* info, hipStream_t st) = 0;
   std::vector<int64_t> sizes;
 };
 
@@ -1293,6 +1334,78 @@ struct HzEngine final : mgh_ctx {
       H_LAUNCH();
     }
     return MG_OK;
+  }
+
+  // per-column results of a solve (status, iterations, final relative residual)
+  mg_status report(mg_rhs_info* info, hipStream_t st) {
+    std::vector<int> hs(Bn), hi(Bn);
+    std::vector<double> hb(Bn), hf(Bn);
+    H_HIP(hipMemcpyAsync(hs.data(), S.status, Bn * sizeof(int), hipMemcpyDeviceToHost, st));
+    H_HIP(hipMemcpyAsync(hi.data(), S.iters, Bn * sizeof(int), hipMemcpyDeviceToHost, st));
+    H_HIP(hipMemcpyAsync(hb.data(), S.beta, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    H_HIP(hipMemcpyAsync(hf.data(), S.fnorm, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    H_HIP(hipStreamSynchronize(st));
+    mg_status ret = MG_OK;
+    for (int b = 0; b < Bn; ++b) {
+      const int s = hs[b] == -1 ? MG_ERR_NOT_CONVERGED : hs[b];
+      if (info) {
+        info[b].iters = hi[b];
+        info[b].status = s;
+        info[b].relres = hf[b] > 0 ? hb[b] / hf[b] : hb[b];
+      }
+      if (s == MG_ERR_DIVERGED) ret = MG_ERR_DIVERGED;
+      else if (s != MG_OK && ret == MG_OK) ret = MG_ERR_NOT_CONVERGED;
+    }
+    if (ret != MG_OK) h_err = ret == MG_ERR_DIVERGED ? "a column's residual is not finite" : "a column did not converge";
+    return ret;
+  }
+
+  // Stationary iteration u <- LMG(A, f, u) (FP64 cycles): each cycle runs on a
+  // copy of u, which the columns still iterating take over; their FP64
+  // residuals are checked on the device after every cycle.
+  mg_status solve(const double* fd, double* ud, double rtol, int max_cycles, int check_every, mg_rhs_info* info,
+                  hipStream_t st) override {
+    if (!fd || !ud) return hfail(MG_ERR_INVALID_ARG, "null vector");
+    if (!std::is_same<T, double>::value)
+      return hfail(MG_ERR_UNSUPPORTED, "the stationary solve needs FP64 cycles (the cycle is not affine, so there is "
+                                       "no refinement form for lower-precision cycles)");
+    if (max_cycles < 1 || check_every < 1 || !(rtol >= 0.0)) return hfail(MG_ERR_INVALID_ARG, "bad solve options");
+    H_TRY(check_disjoint(fd, ud));
+    H_TRY(kr_alloc(std::max(km, 1), st));
+    const int n = lv[0].n;
+    const size_t nB = (size_t)n * Bn;
+    const double2* f = reinterpret_cast<const double2*>(fd);
+    double2* u = reinterpret_cast<double2*>(ud);
+    cx<T>* w = reinterpret_cast<cx<T>*>(Kin);           // the cycle's working copy (double2 here)
+    const dim3 rg(rows_grid(n));
+    hipLaunchKernelGGL(k_fx_resid, rg, dim3(256), 0, st, A64, Bn, lb, f, (const double2*)nullptr, KW);
+    H_LAUNCH();
+    H_TRY(kr_dot(0, KW, Bn, Kh1, nullptr, st));
+    hipLaunchKernelGGL(k_fx_start, dim3(1), dim3(256), 0, st, S, Bn, km, (const double2*)Kh1, rtol, max_cycles, 1);
+    H_LAUNCH();
+    hipLaunchKernelGGL(k_fx_resid, rg, dim3(256), 0, st, A64, Bn, lb, f, (const double2*)u, KW);
+    H_LAUNCH();
+    H_TRY(kr_dot(0, KW, Bn, Kh1, nullptr, st));
+    hipLaunchKernelGGL(k_hz_solve_check, dim3(1), dim3(256), 0, st, S, Bn, (const double2*)Kh1, rtol, 1);
+    H_LAUNCH();
+    int cnt = 0;
+    H_TRY(read_cnt(&cnt, st));
+    for (int c = 1; c <= max_cycles && cnt > 0; ++c) {
+      hipLaunchKernelGGL((k_hz_copy<T>), dim3(lin_grid(nB)), dim3(256), 0, st, nB,
+                         reinterpret_cast<const cx<T>*>(u), w);
+      H_LAUNCH();
+      H_TRY(cycle(0, reinterpret_cast<const cx<T>*>(f), w, st));
+      hipLaunchKernelGGL(k_hz_take, rg, dim3(256), 0, st, n, Bn, lb, (const int*)S.act,
+                         reinterpret_cast<const double2*>(w), u);
+      H_LAUNCH();
+      hipLaunchKernelGGL(k_fx_resid, rg, dim3(256), 0, st, A64, Bn, lb, f, (const double2*)u, KW);
+      H_LAUNCH();
+      H_TRY(kr_dot(0, KW, Bn, Kh1, nullptr, st));
+      hipLaunchKernelGGL(k_hz_solve_check, dim3(1), dim3(256), 0, st, S, Bn, (const double2*)Kh1, rtol, 0);
+      H_LAUNCH();
+      if (c % check_every == 0 || c == max_cycles) H_TRY(read_cnt(&cnt, st));
+    }
+    return report(info, st);
   }
 
   mg_status fgmres(const double* fd, double* xd, const mg_krylov_options* o, mg_rhs_info* info,
@@ -1678,6 +1791,12 @@ mg_status mgh_fgmres(mgh_ctx* c, const double* f, double* u, const mg_krylov_opt
                      void* stream) {
   if (!c) return hfail(MG_ERR_INVALID_ARG, "null context");
   return c->fgmres(f, u, o, info, static_cast<hipStream_t>(stream));
+}
+
+mg_status mgh_solve(mgh_ctx* c, const double* f, double* u, double rtol, int32_t max_cycles, int32_t check_every,
+                    mg_rhs_info* info, void* stream) {
+  if (!c) return hfail(MG_ERR_INVALID_ARG, "null context");
+  return c->solve(f, u, rtol, max_cycles, check_every, info, static_cast<hipStream_t>(stream));
 }
 
 mg_status mgh_level_info(const mgh_ctx* c, int64_t* n) {

@@ -17,7 +17,7 @@ from . import binding as Bd
 
 SMOOTHERS = {"jacobi": 0, "gmres": 1}
 EXPORTED = ["mgh_num_params", "mgh_setup", "mgh_set_params", "mgh_vcycle", "mgh_fmg", "mgh_residual",
-            "mgh_fgmres", "mgh_level_info", "mgh_destroy", "mgh_last_error"]
+            "mgh_fgmres", "mgh_solve", "mgh_level_info", "mgh_destroy", "mgh_last_error"]
 
 
 class _CCSR(C.Structure):
@@ -58,12 +58,13 @@ def load_library():
     lib.mgh_fmg.argtypes = [vp, vp, vp, vp]
     lib.mgh_residual.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mgh_fgmres.argtypes = [vp, vp, vp, C.POINTER(Bd._KrylovOptions), C.POINTER(Bd.RhsInfo), vp]
+    lib.mgh_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(Bd.RhsInfo), vp]
     lib.mgh_level_info.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.mgh_destroy.argtypes = [vp]
     lib.mgh_destroy.restype = None
     lib.mgh_last_error.restype = C.c_char_p
     for name in ("mgh_setup", "mgh_set_params", "mgh_vcycle", "mgh_fmg", "mgh_residual", "mgh_fgmres",
-                 "mgh_level_info"):
+                 "mgh_solve", "mgh_level_info"):
         getattr(lib, name).restype = C.c_int
     _ready = True
     return lib
@@ -211,6 +212,18 @@ class HelmholtzContext:
         st = self.lib.mgh_fgmres(self._h, f.data_ptr(), u.data_ptr(), C.byref(o), info, self._s())
         if st not in (0, 5, 6) or (raise_on_failure and st != 0):
             _check(self.lib, st, "mgh_fgmres")
+        return Bd.SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
+                            np.array([x.relres for x in info]), st)
+
+    def solve(self, f, u, rtol=1e-8, max_cycles=1000, check_every=5, raise_on_failure=False) -> Bd.SolveInfo:
+        """Stationary iteration u <- LMG(A, f, u) per column to rtol (FP64 contexts)."""
+        c128 = self.torch.complex128
+        self._vec(f, c128, "f")
+        self._vec(u, c128, "u")
+        info = (Bd.RhsInfo * self.B)()
+        st = self.lib.mgh_solve(self._h, f.data_ptr(), u.data_ptr(), rtol, max_cycles, check_every, info, self._s())
+        if st not in (0, 5, 6) or (raise_on_failure and st != 0):
+            _check(self.lib, st, "mgh_solve")
         return Bd.SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
                             np.array([x.relres for x in info]), st)
 

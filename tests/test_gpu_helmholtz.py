@@ -264,3 +264,52 @@ def test_overlapping_f_and_u_are_rejected():
         with pytest.raises(Bd.MGError) as e:
             call(x, x)
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("side,k,J", [(33, 12.0, 4), (65, 20.0, 5)])
+def test_stationary_solve_matches_oracle(side, k, J):
+    """mgh_solve: per column the oracle's cycle count to 1e-8 (+-1 at the
+    threshold) and the oracle's iterate at that count; a column keeps its
+    first converged iterate."""
+    import torch
+    h, plan, f = case(side, k, J, 3, seed=5)
+    flat = C.hz_random_params(J, 1, 1, 1, plan, seed=30, spread=0.03)
+    lev = OH.make_levels(h.A, h.P, h.R)
+    prm = OH.unpack(flat, J, 1, 1, 1, plan)
+    fn = np.linalg.norm(f, axis=0)
+    u = np.zeros_like(f)
+    its, iterates = [None] * 3, [None] * 3
+    for cyc in range(1, 300):
+        u = OH.lmg(lev, prm, 0, f, u)
+        rr = np.linalg.norm(f - h.A[0] @ u, axis=0) / fn
+        for b in range(3):
+            if its[b] is None and rr[b] <= 1e-8:
+                its[b], iterates[b] = cyc, u[:, b].copy()
+        if all(i is not None for i in its):
+            break
+    c = ctx(h, plan, flat, (1, 1, 1), 3, "fp64")
+    x = torch.zeros(f.shape, dtype=torch.complex128, device="cuda")
+    info = c.solve(dev(f, torch.complex128), x, rtol=1e-8, max_cycles=300, check_every=3)
+    print(f"stationary: gpu {info.iters} oracle {its}", flush=True)
+    assert info.code == 0 and (info.relres <= 1e-8).all()
+    assert (np.abs(info.iters - np.array(its)) <= 1).all()
+    xs = x.cpu().numpy()
+    for b in range(3):
+        if info.iters[b] == its[b]:
+            assert np.linalg.norm(xs[:, b] - iterates[b]) <= 1e-9 * np.linalg.norm(iterates[b])
+
+
+def test_stationary_solve_cap_and_precision():
+    """The cycle cap gives MG_ERR_NOT_CONVERGED with the cap as every column's
+    count; an FP32 context refuses the stationary solve (MG_ERR_UNSUPPORTED)."""
+    import torch
+    from paper_2608_29082_amd import binding as Bd
+    h, plan, f = case(33, 12.0, 4, 2, seed=6)
+    c = ctx(h, plan, C.hz_identity_params(4, 1, 1, 1, plan), (1, 1, 1), 2, "fp64")
+    x = torch.zeros(f.shape, dtype=torch.complex128, device="cuda")
+    info = c.solve(dev(f, torch.complex128), x, rtol=1e-8, max_cycles=4, check_every=2)
+    assert info.code == 5 and list(info.iters) == [4, 4] and list(info.status) == [5, 5]
+    c32 = ctx(h, plan, C.hz_identity_params(4, 1, 1, 1, plan), (1, 1, 1), 2, "fp32")
+    with pytest.raises(Bd.MGError) as e:
+        c32.solve(dev(f, torch.complex128), x)
+    assert e.value.status == 8
