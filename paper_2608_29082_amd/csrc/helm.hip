@@ -404,7 +404,7 @@ __device__ __forceinline__ void gm_sweep_upd(int n, const cx<T>* __restrict__ V,
 // Gram-Schmidt applied twice per Arnoldi step; dot products and norms are
 // accumulated in FP64.
 template <class T, int MODE>
-__global__ __launch_bounds__(MODE ? kGT : kGTH) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
+__global__ __launch_bounds__(MODE == 1 ? kGT : kGTH) void k_hz_gmres(CEll<T> A, GEll G, const T* __restrict__ invdeg, int B,
                                                   const cx<T>* __restrict__ f, cx<T>* __restrict__ u, T theta,
                                                   T eta, WK<T> W, int K, int v, cx<T>* __restrict__ scr) {
   __shared__ double red[kAcc * 16], tot[kAcc];
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(MODE ? kGT : kGTH) void k_hz_gmres(CEll<T> A, GEll 
   const int b = blockIdx.x, n = A.n, nt = blockDim.x, t0 = threadIdx.x;
   // slot group of the SpMVs: the HBM-scratch form runs 1024 work-items with
   // half the registers per work-item
-  constexpr int SG = MODE ? kSlots : kSlots / 2;
+  constexpr int SG = MODE == 1 ? kSlots : kSlots / 2;
   cx<T>* lds = reinterpret_cast<cx<T>*>(hz_dyn);
   cx<T>* gcol = scr + (size_t)b * n;           // this column's slot 0 in the global scratch
   const size_t GS = (size_t)n * B;             // global slot stride
@@ -1156,7 +1156,7 @@ struct HzEngine final : mgh_ctx {
       hipLaunchKernelGGL((k_hz_gmres<T, 1>), dim3(Bn), dim3(kGT), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
                          (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
     else if (L.gmode == 2)
-      hipLaunchKernelGGL((k_hz_gmres<T, 2>), dim3(Bn), dim3(kGT), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
+      hipLaunchKernelGGL((k_hz_gmres<T, 2>), dim3(Bn), dim3(kGTH), L.lds, st, L.A, L.G, L.invdeg, Bn, f, u,
                          (T)theta[l], (T)eta[l], WB[l], KB, v, L.scr);
     else
       hipLaunchKernelGGL((k_hz_gmres<T, 0>), dim3(Bn), dim3(kGTH), 0, st, L.A, L.G, L.invdeg, Bn, f, u,
