@@ -82,7 +82,7 @@ def workload(name, K):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
     import torch
     from mginputs import configs as C
