@@ -275,3 +275,31 @@ def _transfer_pin():
 def test_eta_and_transfer_pins():
     _eta_pin()
     _transfer_pin()
+
+
+def test_fmg_two_level_closed_form():
+    """Two-level FMG with no smoothing: u = Phi_P(P A_c^{-1} R Phi_R(f))
+    followed by one cycle whose coarse correction vanishes when the
+    interpolated start already satisfies R Phi_R(f - A u) = 0 exactly: here
+    checked against dense matrices, with the two-feature weights applied to
+    [Re, Im]."""
+    h = HZ.hierarchy(9, 3.0, 2)
+    plan = [("jacobi", 0, 0)]
+    lev = OH.make_levels(h.A, h.P, h.R)
+    WR = np.array([[[1.1, 0.2], [-0.3, 0.8]]])
+    WP = np.array([[[0.9, -0.1], [0.4, 1.2]]])
+    prm = OH.HParams(np.zeros(1), np.ones(1), [np.eye(2)[None]], WR, WP, plan, 4)
+    g = np.random.default_rng(11)
+    n = h.sizes[0]
+    f = g.standard_normal((n, 2)) + 1j * g.standard_normal((n, 2))
+
+    def lay(W, x):
+        X = np.stack([x.real, x.imag], -1) @ W.T
+        return X[..., 0] + 1j * X[..., 1]
+    A, P, R, Ac = h.A[0].toarray(), h.P[0].toarray(), h.R[0].toarray(), h.A[1].toarray()
+    u1 = np.linalg.solve(Ac, R @ lay(WR[0], f))
+    u0 = lay(WP[0], P @ u1)
+    # the cycle from u0 adds Phi_P(P A_c^{-1} R Phi_R(f - A u0))
+    want = u0 + lay(WP[0], P @ np.linalg.solve(Ac, R @ lay(WR[0], f - A @ u0)))
+    got = OH.fmg(lev, prm, f)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
