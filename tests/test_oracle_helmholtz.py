@@ -278,11 +278,10 @@ def test_eta_and_transfer_pins():
 
 
 def test_fmg_two_level_closed_form():
-    """Two-level FMG with no smoothing: u = Phi_P(P A_c^{-1} R Phi_R(f))
-    followed by one cycle whose coarse correction vanishes when the
-    interpolated start already satisfies R Phi_R(f - A u) = 0 exactly: here
-    checked against dense matrices, with the two-feature weights applied to
-    [Re, Im]."""
+    """Two-level FMG with no smoothing: the coarse solution
+    u_1 = A_c^{-1} R Phi_R(f) is interpolated to u_0 = Phi_P(P u_1), and one
+    cycle from u_0 adds Phi_P(P A_c^{-1} R Phi_R(f - A u_0)); dense matrices,
+    the two-feature weights applied to [Re, Im]."""
     h = HZ.hierarchy(9, 3.0, 2)
     plan = [("jacobi", 0, 0)]
     lev = OH.make_levels(h.A, h.P, h.R)
