@@ -152,12 +152,14 @@ __global__ __launch_bounds__(256) void k_hz_resid(CEll<T> A, int B, int lb, cons
   out[o] = mkc<T>(rr, ri);
 }
 
-// one Horner hop of a two-feature convolution: v = [M y] + W x;
-// ADD: out += s v, else out = s v
-template <class T, bool NB, bool ADD>
+// one Horner hop of a two-feature convolution: v = [M y] + W x, or with MIXN
+// v = Wn (M y) + W x (y = x: the first two Horner steps in one sweep, since
+// the feature mixing commutes with the neighbour mean); ADD: out += s v,
+// else out = s v
+template <class T, bool NB, bool ADD, bool MIXN = false>
 __global__ __launch_bounds__(256) void k_hz_hop(GEll G, const T* __restrict__ invdeg, int B, int lb,
                                                 const cx<T>* __restrict__ y, const cx<T>* __restrict__ x, W2<T> W,
-                                                T s, cx<T>* __restrict__ out) {
+                                                T s, cx<T>* __restrict__ out, W2<T> Wn = W2<T>{}) {
   HZ_ROW(G.n)
   cx<T> v = mixw(W, x[o]);
   if (NB) {
@@ -171,8 +173,10 @@ __global__ __launch_bounds__(256) void k_hz_hop(GEll G, const T* __restrict__ in
       }
     }
     const T r = invdeg[i];
-    v.x += r * mr;
-    v.y += r * mi;
+    cx<T> m = mkc<T>(r * mr, r * mi);
+    if (MIXN) m = mixw(Wn, m);
+    v.x += m.x;
+    v.y += m.y;
   }
   if (ADD) {
     cx<T> u = out[o];
@@ -440,14 +444,14 @@ __global__ __launch_bounds__(MODE == 1 ? kGT : kGTH) void k_hz_gmres(CEll<T> A, 
       D0[i] = mkc<T>(theta * t.x, theta * t.y);
     }
   } else {
-    // the Horner buffers take basis slots 1 and 2, unused until the Arnoldi steps
-    for (int i = t0; i < n; i += nt) V[NB + i] = mixw(W.w[K], R[i]);
-    __syncthreads();
+    // the Horner buffers take basis slots 1 and 2, unused until the Arnoldi
+    // steps; hop k forms M y + W_k r, and the first one W_{K-1} r + W_K (M r)
+    // (the feature mixing commutes with the neighbour mean)
     int cur = 0;
     for (int k = K - 1; k >= 0; --k) {
       cx<T>* dst = k == 0 ? D0 : V + (size_t)(2 - cur) * NB;     // the other Horner buffer
       const T s = k == 0 ? theta : (T)1;
-      const cx<T>* yc = V + (size_t)(1 + cur) * NB;
+      const cx<T>* yc = k == K - 1 ? R : V + (size_t)(1 + cur) * NB;
       for (int i = t0; i < n; i += nt) {
         T mr = 0, mi = 0;
         for (int q = 0; q < G.w; ++q) {
@@ -460,8 +464,10 @@ __global__ __launch_bounds__(MODE == 1 ? kGT : kGTH) void k_hz_gmres(CEll<T> A, 
         }
         cx<T> t = mixw(W.w[k], R[i]);
         const T r = invdeg[i];
-        t.x += r * mr;
-        t.y += r * mi;
+        cx<T> m = mkc<T>(r * mr, r * mi);
+        if (k == K - 1) m = mixw(W.w[K], m);
+        t.x += m.x;
+        t.y += m.y;
         dst[i] = mkc<T>(s * t.x, s * t.y);
       }
       __syncthreads();
@@ -1113,33 +1119,42 @@ struct HzEngine final : mgh_ctx {
     return MG_OK;
   }
 
-  // out (+)= s Phi(x) with weights W[0..K] on level l
+  // out (+)= s Phi(x) with weights W[0..K] on level l; the first sweep forms
+  // W_{K-1} x + W_K (M x), the two leading Horner steps at once
   mg_status conv(int l, const WK<T>& W, int K, const cx<T>* x, cx<T>* out, T s, bool add, hipStream_t st) {
     Lv& L = lv[l];
     const dim3 g(rows_grid(L.n));
     if (K == 0) {
       if (add) hipLaunchKernelGGL((k_hz_hop<T, false, true>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                                  (const cx<T>*)nullptr, x, W.w[0], s, out);
+                                  (const cx<T>*)nullptr, x, W.w[0], s, out, W2<T>{});
       else hipLaunchKernelGGL((k_hz_hop<T, false, false>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                              (const cx<T>*)nullptr, x, W.w[0], s, out);
+                              (const cx<T>*)nullptr, x, W.w[0], s, out, W2<T>{});
       H_LAUNCH();
       return MG_OK;
     }
-    hipLaunchKernelGGL((k_hz_hop<T, false, false>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                       (const cx<T>*)nullptr, x, W.w[K], (T)1, L.Y0);
+    if (K == 1) {
+      if (add) hipLaunchKernelGGL((k_hz_hop<T, true, true, true>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb, x,
+                                  x, W.w[0], s, out, W.w[1]);
+      else hipLaunchKernelGGL((k_hz_hop<T, true, false, true>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb, x, x,
+                              W.w[0], s, out, W.w[1]);
+      H_LAUNCH();
+      return MG_OK;
+    }
+    hipLaunchKernelGGL((k_hz_hop<T, true, false, true>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb, x, x,
+                       W.w[K - 1], (T)1, L.Y0, W.w[K]);
     H_LAUNCH();
     cx<T>* cur = L.Y0;
     cx<T>* nxt = L.Y1;
-    for (int k = K - 1; k >= 1; --k) {
+    for (int k = K - 2; k >= 1; --k) {
       hipLaunchKernelGGL((k_hz_hop<T, true, false>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                         (const cx<T>*)cur, x, W.w[k], (T)1, nxt);
+                         (const cx<T>*)cur, x, W.w[k], (T)1, nxt, W2<T>{});
       H_LAUNCH();
       std::swap(cur, nxt);
     }
     if (add) hipLaunchKernelGGL((k_hz_hop<T, true, true>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                                (const cx<T>*)cur, x, W.w[0], s, out);
+                                (const cx<T>*)cur, x, W.w[0], s, out, W2<T>{});
     else hipLaunchKernelGGL((k_hz_hop<T, true, false>), g, dim3(256), 0, st, L.G, L.invdeg, Bn, lb,
-                            (const cx<T>*)cur, x, W.w[0], s, out);
+                            (const cx<T>*)cur, x, W.w[0], s, out, W2<T>{});
     H_LAUNCH();
     return MG_OK;
   }
