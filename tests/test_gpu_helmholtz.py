@@ -315,18 +315,20 @@ def test_stationary_solve_cap_and_precision():
     assert e.value.status == 8
 
 
-def test_bench_configuration_trained_parameters_fp64_cycle():
-    """The shipped trained parameters on the benchmark hierarchy: one FP64
-    cycle from zero against the oracle (2 columns, whole vectors)."""
+@pytest.mark.parametrize("K", [1, 2])
+def test_bench_configuration_trained_parameters_fp64_cycle(K):
+    """The shipped trained parameters (K = 1 and K = 2) on the benchmark
+    hierarchy: one FP64 cycle from zero against the oracle (2 columns, whole
+    vectors)."""
     import torch
     import os
-    w = C.helmholtz(B=2)
+    w = C.helmholtz(B=2, K=K)
     h = w.hier
     theta = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                                 "paper_2608_29082_amd", "theta", "hz_k1_helmholtz257.npy"))
-    want = OH.lmg(OH.make_levels(h.A, h.P, h.R), OH.unpack(theta, 5, 1, 1, 1, w.plan), 0, w.f,
+                                 "paper_2608_29082_amd", "theta", f"hz_k{K}_helmholtz257.npy"))
+    want = OH.lmg(OH.make_levels(h.A, h.P, h.R), OH.unpack(theta, 5, K, K, K, w.plan), 0, w.f,
                   np.zeros_like(w.f))
-    c = ctx(h, w.plan, theta, (1, 1, 1), 2, "fp64")
+    c = ctx(h, w.plan, theta, (K, K, K), 2, "fp64")
     u = torch.zeros(w.f.shape, dtype=torch.complex128, device="cuda")
     c.vcycle(dev(w.f, torch.complex128), u)
     err = rel(u.cpu().numpy(), want)
