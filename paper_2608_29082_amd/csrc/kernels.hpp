@@ -437,19 +437,23 @@ struct TileHead {
 // Item data in registers (fetched one item ahead)
 struct TileBody {
   float xv[kTileRows][4];
+  float xs[kTileRows];      // row scales of the input (xsc)
   float ov[kTileOwnPerThread][4];
   uint2 lc[kTileMeta];
   float li[kTileMeta];
 };
 
 //   mode 0: out = Phi(x)      mode 1: out = (oz ? 0 : out) + scale * Phi(x)
+// With xsc the input is x_i xsc_i (the Jacobi-scaled residual of a zero iterate,
+// f_i / a_ii, formed as the rows enter LDS: one sweep less per cycle level).
 // Arithmetic per node and column as in k_hop (same order of the sums).
 // Grid: a multiple of 8 blocks of kTileThreads; out must not alias x.  FINE
 // only tags finest-level launches with their own symbol (same code).
 template <bool FINE, bool WG, class TX, class TO>
 __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, int K, TileCoef cf,
                                                            const TX* __restrict__ x, TO* __restrict__ out, int mode,
-                                                           float scale, int oz, TileLds lo) {
+                                                           float scale, int oz, TileLds lo,
+                                                           const float* __restrict__ xsc) {
   extern __shared__ __align__(16) float4 conv_smem[];
   const int per = gridDim.x >> 3;             // workgroups per XCD
   const int xc = blockIdx.x & 7;              // blocks are dispatched round-robin over the XCDs
@@ -481,7 +485,10 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
   auto body = [&](const TileHead& h, TileBody& b) {
     const int col = h.g * kTileCols + q * 4;
 #pragma unroll
-    for (int e = 0; e < kTileRows; ++e) ld4v(x + (size_t)h.nd[e] * B + col, b.xv[e]);
+    for (int e = 0; e < kTileRows; ++e) {
+      ld4v(x + (size_t)h.nd[e] * B + col, b.xv[e]);
+      if (xsc) b.xs[e] = xsc[h.nd[e]];
+    }
 #pragma unroll
     for (int e = 0; e < kTileOwnPerThread; ++e) {
 #pragma unroll
@@ -510,6 +517,10 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
 #pragma unroll
     for (int e = 0; e < kTileRows; ++e) {
       const int r = p0 + e * kTileNp;
+      if (xsc) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bc.xv[e][c] *= bc.xs[e];
+      }
       if (r < hc.cK) S[r * kTileQ + q] = make_float4(bc.xv[e][0], bc.xv[e][1], bc.xv[e][2], bc.xv[e][3]);
     }
     {

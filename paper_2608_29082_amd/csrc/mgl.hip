@@ -1138,26 +1138,28 @@ struct Engine final : EngineBase {
            ((uintptr_t)out % 16) == 0;
   }
 
-  // fused convolution: mode 0 out = Phi(x), mode 1 out = (oz ? 0 : out) + scale Phi(x)
+  // fused convolution: mode 0 out = Phi(x), mode 1 out = (oz ? 0 : out) + scale Phi(x);
+  // with xsc, x_i xsc_i in place of x_i
   template <class TX, class TO>
   mg_status conv_tile(int l, const double* c, int K, const TX* x, TO* out, int mode, double scale, int oz,
-                      hipStream_t st) {
+                      hipStream_t st, const C* xsc = nullptr) {
     if constexpr (std::is_same<C, float>::value) {
       const DL& D = d[l];
       TileCoef cf{};
       for (int k = 0; k <= K; ++k) cf.c[k] = (float)c[k];
       const double bytes = nB(l) * (sizeof(TX) + sizeof(TO) * ((mode && !oz) ? 2 : 1)) +
-                           (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C);
+                           (double)D.L.wg * D.L.n * (4 + (wgt() ? sizeof(C) : 0)) + (double)D.L.n * sizeof(C) +
+                           (xsc ? (double)D.L.n * sizeof(C) : 0.0);
       if (l == 0)
         TIMED(MG_KF_CONV, bytes,
               WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<true, WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
                                           D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
-                                          D.tlo[K])));
+                                          D.tlo[K], xsc)));
       else
         TIMED(MG_KF_CONV, bytes,
               WG_SPLIT(hipLaunchKernelGGL((k_conv_tile<false, WGv, TX, TO>), dim3(D.tgrid[K]), dim3(kTileThreads),
                                           D.tlds[K], st, D.td, B(), K, cf, x, out, mode, (float)scale, oz,
-                                          D.tlo[K])));
+                                          D.tlo[K], xsc)));
       return MG_OK;
     } else {
       return fail(MG_ERR_STATE, "fused convolution needs FP32 cycles");
@@ -1227,9 +1229,15 @@ struct Engine final : EngineBase {
     return hop<TH, TH, TU>(l, yin, a, x, c[0], u, 1, scale, oz, st);
   }
 
-  // one learnable smoothing step; s receives D^{-1}(f - A u)
-  mg_status smooth(int l, const TU* f, TU* u, int uz, TH* s, hipStream_t st) {
+  // one learnable smoothing step; s receives D^{-1}(f - A u), except that with
+  // keep_s = false a zero iterate's step runs as one fused convolution of D^{-1} f
+  // (same arithmetic; s is not written)
+  mg_status smooth(int l, const TU* f, TU* u, int uz, TH* s, hipStream_t st, bool keep_s = true) {
     const DL& D = d[l];
+    if constexpr (std::is_same<TH, TU>::value && std::is_same<C, float>::value) {
+      if (uz && !keep_s && pl.KB >= 2 && tiled(l, pl.KB, f, u))
+        return conv_tile<TU, TU>(l, cB(l), pl.KB, f, u, 1, eta(l) * theta(l), 1, st, D.L.invdiag);
+    }
     TIMED(MG_KF_RESID, nB(l) * (sizeof(TU) * (uz ? 1 : 2) + sizeof(TH)) + (uz ? 0.0 : bytes_A(l)) +
                            (double)D.L.n * sizeof(C),
           ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TH), D.L, B(), lbs, f, u, uz, 1, s));
@@ -1312,7 +1320,7 @@ struct Engine final : EngineBase {
     if (l == pl.J - 1) return coarse(f, u, 0, st);
     DL& D = d[l];
     for (int j = 0; j < pl.nu_pre; ++j) {
-      MG_TRY(smooth(l, f, u, uz, D.s, st));
+      MG_TRY(smooth(l, f, u, uz, D.s, st, false));
       uz = 0;
     }
     TU* fn = ck ? ck->f[l + 1] : d[l + 1].f;
