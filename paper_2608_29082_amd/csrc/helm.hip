@@ -1647,13 +1647,20 @@ struct HzEngine final : mgh_ctx {
           }
         int w = 1;
         for (auto& r : rows) w = std::max(w, (int)r.size());
+        // padding slots: weight 0, pointing at a column the row already reads
+        // (not all at column 0, which every row's padding would load)
+        const int ncol = transpose ? M.nrows : M.ncols;
         std::vector<int> col((size_t)w * nr, 0);
         std::vector<T> val((size_t)w * nr, (T)0);
-        for (int i = 0; i < nr; ++i)
+        for (int i = 0; i < nr; ++i) {
           for (size_t s = 0; s < rows[i].size(); ++s) {
             col[s * nr + i] = rows[i][s].first;
             val[s * nr + i] = (T)rows[i][s].second;
           }
+          const int pc = rows[i].empty() ? (int)std::min<long>((long)i * ncol / nr, (long)ncol - 1)
+                                         : rows[i][0].first;
+          for (size_t s = rows[i].size(); s < (size_t)w; ++s) col[s * nr + i] = pc;
+        }
         int* dc;
         T* dv;
         H_TRY(mem.upload(&dc, col, st));

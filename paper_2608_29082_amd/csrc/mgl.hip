@@ -332,6 +332,14 @@ mg_status build_level(const mg_csr* A, const mg_csr* G, HLevel& L, int l, int ag
   return MG_OK;
 }
 
+// Padding slots of a transfer carry weight 0 and point at a column the row
+// already reads (its first entry; for an empty row, a column at the same
+// relative position), so their loads hit lines in flight rather than every
+// row's padding loading the same column 0.
+inline int pad_col(int i, int nrows, int ncols) {
+  return (int)std::min<long>((long)i * ncols / std::max(nrows, 1), (long)ncols - 1);
+}
+
 HEll ell_from_csr(const mg_csr* m, int mult) {
   HEll e;
   e.n = m->nrows;
@@ -348,8 +356,9 @@ HEll ell_from_csr(const mg_csr* m, int mult) {
         e.col[(size_t)k * e.n + i] = m->col[p];
         e.val[(size_t)k * e.n + i] = m->val ? m->val[p] : 0.0;
       }
-      for (; k < w; ++k) {   // padding: column 0, weight 0
-        e.col[(size_t)k * e.n + i] = 0;
+      const int pc = m->rowptr[i] < m->rowptr[i + 1] ? m->col[m->rowptr[i]] : pad_col(i, m->nrows, m->ncols);
+      for (; k < w; ++k) {   // padding: weight 0
+        e.col[(size_t)k * e.n + i] = pc;
         e.val[(size_t)k * e.n + i] = 0.0;
       }
     }
@@ -368,8 +377,7 @@ HEll ell_transpose(const mg_csr* m, int mult) {
   e.w = w;
   e.col.resize((size_t)w * e.n);
   e.val.resize((size_t)w * e.n);
-  par_rows(w, [&](int k0, int k1) {   // padding everywhere first: column 0, weight 0
-    std::fill(e.col.begin() + (size_t)k0 * e.n, e.col.begin() + (size_t)k1 * e.n, 0);
+  par_rows(w, [&](int k0, int k1) {   // weights of the padding slots: 0
     std::fill(e.val.begin() + (size_t)k0 * e.n, e.val.begin() + (size_t)k1 * e.n, 0.0);
   });
   std::vector<int> fill(m->ncols, 0);
@@ -380,6 +388,12 @@ HEll ell_transpose(const mg_csr* m, int mult) {
       e.col[(size_t)k * e.n + j] = i;
       e.val[(size_t)k * e.n + j] = m->val[p];
     }
+  par_rows(e.n, [&](int j0, int j1) {   // padding columns
+    for (int j = j0; j < j1; ++j) {
+      const int pc = fill[j] ? e.col[j] : pad_col(j, m->ncols, m->nrows);
+      for (int k = fill[j]; k < w; ++k) e.col[(size_t)k * e.n + j] = pc;
+    }
+  });
   return e;
 }
 
