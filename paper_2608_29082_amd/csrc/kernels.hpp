@@ -625,6 +625,30 @@ __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, in
   const int i = uni<WIDE>((int)(gt_ >> lbs));
   const int lane = (int)(gt_ & ((1 << lbs) - 1));
   if (i >= R.n) return;
+  if (mode == 0 && R.w <= 8) {
+    // plain restriction of y: every slot's index and weight, then every gather,
+    // issued before the sums (one round trip each instead of one per chunk);
+    // slots past R.w repeat slot 0's index and are not summed
+    int jr[8];
+    C wr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int kk = k < R.w ? k : 0;
+      jr[k] = uni<WIDE>(R.col[(size_t)kk * R.n + i]);
+      wr[k] = uni<WIDE>(R.val[(size_t)kk * R.n + i]);
+    }
+    for (int b = lane; b < B; b += (1 << lbs)) {
+      C v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = ldc<C>(y + (size_t)jr[k] * B + b);
+      C acc = C(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < R.w) acc += (wr[k] != C(0)) ? wr[k] * v[k] : C(0);
+      put(rc + (size_t)i * B + b, scale * acc);
+    }
+    return;
+  }
   for (int b = lane; b < B; b += (1 << lbs)) {
     C acc = C(0);
     for (int k = 0; k < R.w; k += 4) {
@@ -687,10 +711,16 @@ __global__ __launch_bounds__(256) void k_prolong(Xfer<C> P, int B, int lbs, cons
           j[r][q] = uni<WIDE>(P.col[o]);
           w[r][q] = uni<WIDE>(P.val[o]);
         }
+      // every gather of the chunk issued before the sums use them
+      C v[ROWS][2];
 #pragma unroll
       for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[r] += w[r][q] * ldc<C>(ec + (size_t)j[r][q] * B + b);
+        for (int q = 0; q < 2; ++q) v[r][q] = ldc<C>(ec + (size_t)j[r][q] * B + b);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[r] += w[r][q] * v[r][q];
     }
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
