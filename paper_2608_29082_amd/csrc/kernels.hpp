@@ -975,6 +975,13 @@ struct TailArgs {
   int lt;                   // global index of the first tail level
 };
 
+// The tail's operators stay in global memory (L2-resident) while its vectors
+// live in LDS.  Rows of width <= kTailW load all their slots' indices (and
+// values) at once, so a sweep costs one global round trip rather than one per
+// slot; slots past the width repeat slot 0 and are not summed (same sums, same
+// order, as the slot loop).
+constexpr int kTailW = 8;
+
 template <int CPB, class C>
 __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u, int uz, int jacobi, C* out) {
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
@@ -982,7 +989,21 @@ __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u
     C v = f[e];
     if (!uz) {
       C au = L.diag[i] * u[e];
-      for (int k = 0; k < L.w; ++k) au += L.val[(size_t)k * L.ld + i] * u[L.col[(size_t)k * L.ld + i] * CPB + c];
+      if (L.w <= kTailW) {
+        int jj[kTailW];
+        C vv[kTailW];
+#pragma unroll
+        for (int k = 0; k < kTailW; ++k) {
+          const size_t o = (size_t)(k < L.w ? k : 0) * L.ld + i;
+          jj[k] = L.col[o];
+          vv[k] = L.val[o];
+        }
+#pragma unroll
+        for (int k = 0; k < kTailW; ++k)
+          if (k < L.w) au += vv[k] * u[jj[k] * CPB + c];
+      } else {
+        for (int k = 0; k < L.w; ++k) au += L.val[(size_t)k * L.ld + i] * u[L.col[(size_t)k * L.ld + i] * CPB + c];
+      }
       v -= au;
     }
     if (jacobi) v *= L.invdiag[i];
@@ -998,11 +1019,29 @@ __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C sm = C(0);
-    for (int k = 0; k < L.wg; ++k) {
-      const int j = L.gcol[(size_t)k * L.ld + i];
-      C v = yin[j * CPB + c];
-      if constexpr (WG) v *= L.gval[(size_t)k * L.ld + i];
-      if (j != i) sm += v;
+    if (L.wg <= kTailW) {
+      int jj[kTailW];
+      C ww[kTailW];
+#pragma unroll
+      for (int k = 0; k < kTailW; ++k) {
+        const size_t o = (size_t)(k < L.wg ? k : 0) * L.ld + i;
+        jj[k] = L.gcol[o];
+        if constexpr (WG) ww[k] = L.gval[o];
+      }
+#pragma unroll
+      for (int k = 0; k < kTailW; ++k) {
+        if (k >= L.wg) continue;
+        C v = yin[jj[k] * CPB + c];
+        if constexpr (WG) v *= ww[k];
+        if (jj[k] != i) sm += v;
+      }
+    } else {
+      for (int k = 0; k < L.wg; ++k) {
+        const int j = L.gcol[(size_t)k * L.ld + i];
+        C v = yin[j * CPB + c];
+        if constexpr (WG) v *= L.gval[(size_t)k * L.ld + i];
+        if (j != i) sm += v;
+      }
     }
     const C v = a * (L.invdeg[i] * sm) + cc * x[e];
     out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
@@ -1016,9 +1055,23 @@ __device__ __forceinline__ void tl_xfer(const Xfer<C>& X, const C* v, C* out, in
   for (int e = threadIdx.x; e < X.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C acc = C(0);
-    for (int k = 0; k < X.w; ++k) {
-      const C w = X.val[(size_t)k * X.n + i];
-      if (w != C(0)) acc += w * v[X.col[(size_t)k * X.n + i] * CPB + c];
+    if (X.w <= kTailW) {
+      int jj[kTailW];
+      C ww[kTailW];
+#pragma unroll
+      for (int k = 0; k < kTailW; ++k) {
+        const size_t o = (size_t)(k < X.w ? k : 0) * X.n + i;
+        jj[k] = X.col[o];
+        ww[k] = X.val[o];
+      }
+#pragma unroll
+      for (int k = 0; k < kTailW; ++k)
+        if (k < X.w && ww[k] != C(0)) acc += ww[k] * v[jj[k] * CPB + c];
+    } else {
+      for (int k = 0; k < X.w; ++k) {
+        const C w = X.val[(size_t)k * X.n + i];
+        if (w != C(0)) acc += w * v[X.col[(size_t)k * X.n + i] * CPB + c];
+      }
     }
     out[e] = add ? (oz ? C(0) : out[e]) + scale * acc : scale * acc;
   }
