@@ -976,20 +976,71 @@ struct TailArgs {
 };
 
 // The tail's operators stay in global memory (L2-resident) while its vectors
-// live in LDS.  Rows of width <= kTailW load all their slots' indices (and
+// live in LDS.  Rows of width 1 .. kTailW load all their slots' indices (and
 // values) at once, so a sweep costs one global round trip rather than one per
 // slot; slots past the width repeat slot 0 and are not summed (same sums, same
 // order, as the slot loop).
 constexpr int kTailW = 8;
 
-template <int CPB, class C>
-__device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u, int uz, int jacobi, C* out) {
+// One work-item's row of a tail level, held in registers for the sweeps of a
+// level visit when every row has its own work-item (n * CPB <= blockDim.x) and
+// the widths are 1 .. kTailW: the sweeps then read only LDS.
+template <class C, bool WG>
+struct TRow {
+  int ac[kTailW], gc[kTailW];
+  C av[kTailW], gw[WG ? kTailW : 1];
+  C dg, ida, idg;
+};
+template <int CPB, bool WG, class C>
+__device__ __forceinline__ bool tl_cacheable(const Lvl<C>& L) {
+  return L.n * CPB <= (int)blockDim.x && L.w >= 1 && L.w <= kTailW && L.wg >= 1 && L.wg <= kTailW;
+}
+template <int CPB, bool WG, class C>
+__device__ __forceinline__ void tl_load_row(const Lvl<C>& L, TRow<C, WG>& R) {
+  const int e = threadIdx.x;
+  if (e >= L.n * CPB) return;
+  const int i = e / CPB;
+#pragma unroll
+  for (int k = 0; k < kTailW; ++k) {
+    const size_t o = (size_t)(k < L.w ? k : 0) * L.ld + i;
+    const size_t og = (size_t)(k < L.wg ? k : 0) * L.ld + i;
+    R.ac[k] = L.col[o];
+    R.av[k] = L.val[o];
+    R.gc[k] = L.gcol[og];
+    if constexpr (WG) R.gw[k] = L.gval[og];
+  }
+  R.dg = L.diag[i];
+  R.ida = L.invdiag[i];
+  R.idg = L.invdeg[i];
+}
+
+template <int CPB, class C, bool WG>
+__device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u, int uz, int jacobi, C* out,
+                                         const TRow<C, WG>& rc, bool cached) {
+  if (cached) {   // the row in registers (one row per work-item)
+    const int e = threadIdx.x;
+    if (e < L.n * CPB) {
+      const int c = e % CPB;
+      C v = f[e];
+      if (!uz) {
+        C au = rc.dg * u[e];
+#pragma unroll
+        for (int k = 0; k < kTailW; ++k)
+          if (k < L.w) au += rc.av[k] * u[rc.ac[k] * CPB + c];
+        v -= au;
+      }
+      if (jacobi) v *= rc.ida;
+      out[e] = v;
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C v = f[e];
     if (!uz) {
       C au = L.diag[i] * u[e];
-      if (L.w <= kTailW) {
+      if (L.w >= 1 && L.w <= kTailW) {
         int jj[kTailW];
         C vv[kTailW];
 #pragma unroll
@@ -1015,11 +1066,29 @@ __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u
 // out = a (M yin) + c x   (mode 0)   |   out = (oz ? 0 : out) + scale (a (M yin) + c x)   (mode 1)
 template <int CPB, bool WG, class C>
 __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const C* x, C cc, C* out, int mode,
-                                       C scale, int oz) {
+                                       C scale, int oz, const TRow<C, WG>& rc, bool cached) {
+  if (cached) {   // the row in registers (one row per work-item)
+    const int e = threadIdx.x;
+    if (e < L.n * CPB) {
+      const int i = e / CPB, c = e - i * CPB;
+      C sm = C(0);
+#pragma unroll
+      for (int k = 0; k < kTailW; ++k) {
+        if (k >= L.wg) continue;
+        C v = yin[rc.gc[k] * CPB + c];
+        if constexpr (WG) v *= rc.gw[k];
+        if (rc.gc[k] != i) sm += v;
+      }
+      const C v = a * (rc.idg * sm) + cc * x[e];
+      out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C sm = C(0);
-    if (L.wg <= kTailW) {
+    if (L.wg >= 1 && L.wg <= kTailW) {
       int jj[kTailW];
       C ww[kTailW];
 #pragma unroll
@@ -1055,7 +1124,7 @@ __device__ __forceinline__ void tl_xfer(const Xfer<C>& X, const C* v, C* out, in
   for (int e = threadIdx.x; e < X.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C acc = C(0);
-    if (X.w <= kTailW) {
+    if (X.w >= 1 && X.w <= kTailW) {
       int jj[kTailW];
       C ww[kTailW];
 #pragma unroll
@@ -1081,7 +1150,7 @@ __device__ __forceinline__ void tl_xfer(const Xfer<C>& X, const C* v, C* out, in
 // u = (oz ? 0 : u) + scale * sum_k c_k M^k x  (Horner, as the per-level sweeps)
 template <int CPB, bool WG, class C>
 __device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, int K, const C* x, double scale, C* u,
-                                            int oz, C* ya, C* yb) {
+                                            int oz, C* ya, C* yb, const TRow<C, WG>& rc, bool cached) {
   if (K == 0) {
     const C a0 = (C)(scale * c[0]);
     for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) u[e] = (oz ? C(0) : u[e]) + a0 * x[e];
@@ -1093,12 +1162,12 @@ __device__ __forceinline__ void tl_conv_add(const Lvl<C>& L, const double* c, in
   C* buf[2] = {ya, yb};
   int cur = 0;
   for (int k = K - 1; k >= 1; --k) {
-    tl_hop<CPB, WG>(L, yin, a, x, (C)c[k], buf[cur], 0, C(0), 0);
+    tl_hop<CPB, WG>(L, yin, a, x, (C)c[k], buf[cur], 0, C(0), 0, rc, cached);
     yin = buf[cur];
     cur ^= 1;
     a = C(1);
   }
-  tl_hop<CPB, WG>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz);
+  tl_hop<CPB, WG>(L, yin, a, x, (C)c[0], u, 1, (C)scale, oz, rc, cached);
 }
 
 // the coarsest tail level: u = A^{-1} f (FP64 accumulation)
@@ -1128,19 +1197,22 @@ __device__ __forceinline__ void tl_cycle(const TailArgs<C>& T, C* sm, int q0, in
     const double *cB = p + 2, *cR = cB + T.KB + 1;
     C* u = sm + tl.off_u;
     const C* f = sm + tl.off_f;
+    TRow<C, WG> rc;
+    const bool cached = tl_cacheable<CPB, WG>(tl.L);
+    if (cached) tl_load_row<CPB, WG>(tl.L, rc);
     int uz = q == q0 ? uz0 : 1;
     for (int j = 0; j < T.nu_pre; ++j) {
-      tl_resid<CPB>(tl.L, f, u, uz, 1, s);
-      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb);
+      tl_resid<CPB>(tl.L, f, u, uz, 1, s, rc, cached);
+      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, uz, ya, yb, rc, cached);
       uz = 0;
     }
     // r = f - A u (u may still be zero when nu_pre == 0), then y = Phi_R r, f_{l+1} = R y
-    tl_resid<CPB>(tl.L, f, u, uz, 0, t);
+    tl_resid<CPB>(tl.L, f, u, uz, 0, t, rc, cached);
     if (uz) {  // u is logically zero: materialise it for the prolongation's update
       for (int e = threadIdx.x; e < tl.L.n * CPB; e += blockDim.x) u[e] = C(0);
       __syncthreads();
     }
-    tl_conv_add<CPB, WG>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb);
+    tl_conv_add<CPB, WG>(tl.L, cR, T.KR, t, 1.0, s, 1, ya, yb, rc, cached);
     tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
   }
   tl_coarse<CPB>(T, sm);
@@ -1151,11 +1223,14 @@ __device__ __forceinline__ void tl_cycle(const TailArgs<C>& T, C* sm, int q0, in
     const double *cB = p + 2, *cP = cB + T.KB + 1 + T.KR + 1;
     C* u = sm + tl.off_u;
     const C* f = sm + tl.off_f;
+    TRow<C, WG> rc;
+    const bool cached = tl_cacheable<CPB, WG>(tl.L);
+    if (cached) tl_load_row<CPB, WG>(tl.L, rc);
     tl_xfer<CPB>(tl.P, sm + T.lv[q + 1].off_u, t, 0, C(1), 0);
-    tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, u, 0, ya, yb);
+    tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, u, 0, ya, yb, rc, cached);
     for (int j = 0; j < T.nu_post; ++j) {
-      tl_resid<CPB>(tl.L, f, u, 0, 1, s);
-      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb);
+      tl_resid<CPB>(tl.L, f, u, 0, 1, s, rc, cached);
+      tl_conv_add<CPB, WG>(tl.L, cB, T.KB, s, p[1] * p[0], u, 0, ya, yb, rc, cached);
     }
   }
 }
@@ -1185,7 +1260,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
     for (int q = 0; q + 1 < T.nl; ++q) {
       const TailLevel<C>& tl = T.lv[q];
       const double* cR = T.prm + (size_t)q * T.per + 2 + T.KB + 1;
-      tl_conv_add<CPB, WG>(tl.L, cR, T.KR, sm + tl.off_f, 1.0, s, 1, ya, yb);
+      tl_conv_add<CPB, WG>(tl.L, cR, T.KR, sm + tl.off_f, 1.0, s, 1, ya, yb, TRow<C, WG>{}, false);
       tl_xfer<CPB>(tl.R, s, sm + T.lv[q + 1].off_f, 0, C(1), 0);
     }
     tl_coarse<CPB>(T, sm);
@@ -1193,7 +1268,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<C> T, int B, const TU* _
       const TailLevel<C>& tl = T.lv[q];
       const double* cP = T.prm + (size_t)q * T.per + 2 + T.KB + 1 + T.KR + 1;
       tl_xfer<CPB>(tl.P, sm + T.lv[q + 1].off_u, t, 0, C(1), 0);
-      tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, sm + tl.off_u, 1, ya, yb);
+      tl_conv_add<CPB, WG>(tl.L, cP, T.KP, t, 1.0, sm + tl.off_u, 1, ya, yb, TRow<C, WG>{}, false);
       tl_cycle<CPB, WG>(T, sm, q, 0);
     }
   }
