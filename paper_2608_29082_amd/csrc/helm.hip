@@ -95,21 +95,24 @@ __device__ __forceinline__ cx<T> mixw(const W2<T>& W, cx<T> x) {
 constexpr int kSlots = 8;
 template <class AT, class T, class X, int SG = kSlots>
 __device__ __forceinline__ void ell_cmul(const CEll<T>& A, const cx<X>* x, int i, int B, int b, AT& ar, AT& ai) {
+  // a group's slots past the width repeat the group's first slot (loaded, not
+  // summed), so every load of the group is issued before the sums
   for (int s0 = 0; s0 < A.w; s0 += SG) {
     int c[SG];
     cx<T> a[SG];
+    cx<X> t[SG];
 #pragma unroll
     for (int q = 0; q < SG; ++q) {
-      if (s0 + q < A.w) {
-        c[q] = A.col[(size_t)(s0 + q) * A.n + i];
-        a[q] = A.val[(size_t)(s0 + q) * A.n + i];
-      }
+      const size_t o = (size_t)(s0 + q < A.w ? s0 + q : s0) * A.n + i;
+      c[q] = A.col[o];
+      a[q] = A.val[o];
     }
 #pragma unroll
+    for (int q = 0; q < SG; ++q) t[q] = x[(size_t)c[q] * B + b];
+#pragma unroll
     for (int q = 0; q < SG; ++q) {
       if (s0 + q < A.w) {
-        const cx<X> t = x[(size_t)c[q] * B + b];
-        const AT tr = (AT)t.x, ti = (AT)t.y;
+        const AT tr = (AT)t[q].x, ti = (AT)t[q].y;
         ar += (AT)a[q].x * tr - (AT)a[q].y * ti;
         ai += (AT)a[q].x * ti + (AT)a[q].y * tr;
       }
@@ -164,12 +167,20 @@ __global__ __launch_bounds__(256) void k_hz_hop(GEll G, const T* __restrict__ in
   cx<T> v = mixw(W, x[o]);
   if (NB) {
     T mr = 0, mi = 0;
-    for (int q = 0; q < G.w; ++q) {
-      const int j = G.col[(size_t)q * G.n + i];
-      if (j != i) {
-        const cx<T> t = y[(size_t)j * B + b];
-        mr += t.x;
-        mi += t.y;
+    // slots in groups, every load of a group issued before its sums
+    for (int q0 = 0; q0 < G.w; q0 += kSlots) {
+      int j[kSlots];
+      cx<T> t[kSlots];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) j[q] = G.col[(size_t)(q0 + q < G.w ? q0 + q : q0) * G.n + i];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) t[q] = y[(size_t)j[q] * B + b];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        if (q0 + q < G.w && j[q] != i) {
+          mr += t[q].x;
+          mi += t[q].y;
+        }
       }
     }
     const T r = invdeg[i];
@@ -328,21 +339,22 @@ __device__ __forceinline__ void gm_sweep1(int n, int w_, const int* __restrict__
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     T ar = 0, ai = 0;
     for (int s0 = 0; s0 < w_; s0 += SG) {
+      // slots past the width repeat the group's first (loaded, not summed)
       int c[SG];
-      cx<T> a[SG];
+      cx<T> a[SG], t[SG];
 #pragma unroll
       for (int q = 0; q < SG; ++q) {
-        if (s0 + q < w_) {
-          c[q] = col[(size_t)(s0 + q) * n + i];
-          a[q] = val[(size_t)(s0 + q) * n + i];
-        }
+        const size_t o = (size_t)(s0 + q < w_ ? s0 + q : s0) * n + i;
+        c[q] = col[o];
+        a[q] = val[o];
       }
 #pragma unroll
+      for (int q = 0; q < SG; ++q) t[q] = x[c[q]];
+#pragma unroll
       for (int q = 0; q < SG; ++q) {
         if (s0 + q < w_) {
-          const cx<T> t = x[c[q]];
-          ar += a[q].x * t.x - a[q].y * t.y;
-          ai += a[q].x * t.y + a[q].y * t.x;
+          ar += a[q].x * t[q].x - a[q].y * t[q].y;
+          ai += a[q].x * t[q].y + a[q].y * t[q].x;
         }
       }
     }
@@ -454,12 +466,19 @@ __global__ __launch_bounds__(MODE == 1 ? kGT : kGTH) void k_hz_gmres(CEll<T> A, 
       const cx<T>* yc = k == K - 1 ? R : V + (size_t)(1 + cur) * NB;
       for (int i = t0; i < n; i += nt) {
         T mr = 0, mi = 0;
-        for (int q = 0; q < G.w; ++q) {
-          const int j = G.col[(size_t)q * n + i];
-          if (j != i) {
-            const cx<T> t = yc[j];
-            mr += t.x;
-            mi += t.y;
+        for (int q0 = 0; q0 < G.w; q0 += kSlots) {   // every load of a group before its sums
+          int jj[kSlots];
+          cx<T> tv[kSlots];
+#pragma unroll
+          for (int q = 0; q < kSlots; ++q) jj[q] = G.col[(size_t)(q0 + q < G.w ? q0 + q : q0) * n + i];
+#pragma unroll
+          for (int q = 0; q < kSlots; ++q) tv[q] = yc[jj[q]];
+#pragma unroll
+          for (int q = 0; q < kSlots; ++q) {
+            if (q0 + q < G.w && jj[q] != i) {
+              mr += tv[q].x;
+              mi += tv[q].y;
+            }
           }
         }
         cx<T> t = mixw(W.w[k], R[i]);
