@@ -104,7 +104,9 @@ mg_status fail(mg_status s, const std::string& m) {
       hipLaunchKernelGGL((k_restrict<false, MGL_UNPAREN TARGS>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__);     \
   } while (0)
 
-constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 4096;
+// kOuterBlocks: the FP64 outer residual runs at most this many blocks (1024 fill the chip in one
+// round on the 513 workload; 4096 were 1.3 % slower end to end)
+constexpr int kMaxK = 8, kMaxNu = 8, kMaxB = 256, kMaxW = 64, kOuterBlocks = 1024;
 
 inline int round_up(int w, int m) { return (w + m - 1) / m * m; }
 
