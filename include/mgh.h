@@ -10,8 +10,8 @@
  *     Phi(x)_i = sum_{k=0..K} W_k (M^k x)_i ,   M = D_g^{-1} A_g
  * (the neighbour mean on the graph of A_l acting on nodes, W_k acting on the
  * two features of a node).  K = 1 is SAGEConv with mean aggregation, whose
- * self weight is W_0 here and whose neighbour weight is W_1 (Sec. 3.3); the
- * higher orders follow the polynomial remark of Sec. 3.5.
+ * self weight is W_0 here and whose neighbour weight is W_1 (Sec. 3.2); the
+ * higher orders follow the polynomial remark of Sec. 3.3.
  * Per level the smoother is either
  *   Jacobi:  delta = theta_l D_A^{-1} (f - A_l u),  u <- u + eta_l Phi_B,l(delta)
  *            (D_A the complex diagonal; Sec. 3, learnable smoother), or

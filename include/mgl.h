@@ -11,9 +11,9 @@
  * restriction is r_c = R_l Phi_R,l(f - A_l u) and the prolongation adds
  * Phi_P,l(P_l e_c) (Sec. 3, learnable transfers), and level J-1 is solved
  * exactly.  Every graph convolution is a polynomial in the neighbour-mean
- * operator M_l = D_g^{-1} A_g of the level's graph (Sec. 3.5 eq. graph-conv-
- * matrix; K = 1 is SAGEConv with mean aggregation, Sec. 3.3; order K per the
- * polynomial-smoother remark of Sec. 3.5):
+ * operator M_l = D_g^{-1} A_g of the level's graph (Sec. 3.3 eq. graph-conv-
+ * matrix; K = 1 is SAGEConv with mean aggregation, Sec. 3.2; order K per the
+ * polynomial-smoother remark of Sec. 3.3):
  *     Phi(x) = sum_{k=0..K} c_k M^k x .
  * The graph of level l is {(i, j): A_ij != 0, i != j} unless given (Sec. 2.1).
  * mg_params selects the aggregation operator G in place of M (weighted or
@@ -96,12 +96,12 @@ typedef struct {
  * are returned with respect to the coefficients in the chosen basis. */
 typedef enum {
     MG_BASIS_MONOMIAL = 0,   /* Phi(x) = sum_k c_k G^k x (SAGEConv for K = 1) */
-    MG_BASIS_CHEBYSHEV = 1   /* Phi(x) = sum_k c_k T_k(-G) x: the ChebConv layer (Sec. 3.3) with the
+    MG_BASIS_CHEBYSHEV = 1   /* Phi(x) = sum_k c_k T_k(-G) x: the ChebConv layer (Sec. 3.2) with the
                                 rescaled Laplacian 2 (I - G) / lambda_max - I, lambda_max = 2 */
 } mg_basis;
 
 typedef enum {
-    MG_AGG_MEAN = 0,         /* G = D_g^{-1} A_g, the neighbour mean (Sec. 3.3) */
+    MG_AGG_MEAN = 0,         /* G = D_g^{-1} A_g, the neighbour mean (Sec. 3.2) */
     MG_AGG_WEIGHTED = 1,     /* G = D_w^{-1} W, W_ij = |A_ij| on the graph of A (|G_ij| for a given
                                 graph, which then needs values); D_w = diag(sum_j W_ij): edge
                                 weights from matrix entries (Sec. 2.1) */

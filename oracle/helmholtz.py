@@ -11,8 +11,8 @@ Plain NumPy/SciPy code written from the paper:
     W_2 = 0 at initialisation, off-diagonal entries trainable).  A convolution
     of order K is  Phi(x) = sum_k W_k (M^k x)  with M = D_g^{-1} A_g the
     neighbour mean acting on nodes and W_k acting on the two features of every
-    node (K = 1 is SAGEConv with mean aggregation, Sec. 3.3; the K-order form is
-    the polynomial-smoother remark of Sec. 3.5).  M and the W_k commute, so it
+    node (K = 1 is SAGEConv with mean aggregation, Sec. 3.2; the K-order form is
+    the polynomial-smoother remark of Sec. 3.3).  M and the W_k commute, so it
     is evaluated by Horner's rule  y = W_K x;  y <- M y + W_k x.
   * Jacobi smoothing (Sec. 3, learnable smoother with B_l = D_A^{-1}, the
     complex diagonal of A_l):  delta = theta D_A^{-1} (f - A u),

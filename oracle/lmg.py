@@ -4,17 +4,17 @@ Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
 may import this module.  The GPU product path never calls it.
 
 Plain, slow, obviously-correct NumPy/SciPy code written from the paper:
-  * neighbour mean  M = D_g^{-1} A_g  on the graph of A_l (Sec. 2.1; Sec. 3.3
-    SAGEConv with mean aggregation; Sec. 3.5 eq. (graph-conv-matrix)),
+  * neighbour mean  M = D_g^{-1} A_g  on the graph of A_l (Sec. 2.1; Sec. 3.2
+    SAGEConv with mean aggregation; Sec. 3.3 eq. (graph-conv-matrix)),
   * a graph convolution of order K as the polynomial  sum_k c_k M^k x
-    (K = 1 is SAGEConv with w1 = c_0, w2 = c_1; Sec. 3.5 remark on
+    (K = 1 is SAGEConv with w1 = c_0, w2 = c_1; Sec. 3.3 remark on
     polynomial smoothers for the K-order case), evaluated by Horner's rule,
   * the learnable V-cycle LMG (Alg. 2) with B_l = D_A^{-1} (damped-Jacobi
     smoother of Sec. 2.3, eq. for the Jacobi update),
   * the classical V-cycle MG (Alg. 1), written separately,
   * the stationary iteration u^m = u^{m-1} + B (f - A u^{m-1}) with per-column
     stopping (Sec. 1).
-Variants of the convolution (Sec. 3.3, other operators such as ChebConv;
+Variants of the convolution (Sec. 3.2, other operators such as ChebConv;
 Sec. 2.1, edge weights that encode matrix entries):
   * aggregation "weighted": G = D_w^{-1} W with W_ij = |A_ij| on the graph
     (|G_ij| for a given weighted graph), D_w = diag(sum_j W_ij);

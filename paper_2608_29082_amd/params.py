@@ -35,7 +35,7 @@ def map_levels(theta: np.ndarray, J_src: int, J_dst: int, KB: int, KR: int, KP: 
     Target level l takes source level l + shift, clamped to the source's
     parameterised levels: shift = 0 aligns the finest levels, and a target
     level past the deepest source level copies it (the partial-transfer rule
-    of Sec. 4.2.4: extra coarse levels copy the deepest compatible source
+    of Sec. 4.2.3: extra coarse levels copy the deepest compatible source
     weights).  With shift = J_src - J_dst on nested grids levels of equal mesh
     size are matched (the paper matches levels by a mesh-size criterion).
     """

@@ -1,5 +1,5 @@
 """Pins of the convolution variants: Chebyshev basis (the ChebConv layer of
-Sec. 3.3 with the symmetric or random-walk normalisation) and weighted
+Sec. 3.2 with the symmetric or random-walk normalisation) and weighted
 aggregation (edge weights from matrix entries, Sec. 2.1)."""
 import numpy as np
 import numpy.polynomial.chebyshev as npc

@@ -1,12 +1,12 @@
 """Pins of the CPU oracle against facts fixed by the paper and by mathematics.
 
 Each test pins a part of the oracle to something other than the oracle itself:
-closed forms (eigenvalues of the learnable smoother, Sec. 3.5), textbook
+closed forms (eigenvalues of the learnable smoother, Sec. 3.3), textbook
 properties (Galerkin orthogonality of the coarse-grid correction, O(h^2)
 nodal error of P1 on a uniform mesh, symmetry of the V-cycle with a symmetric
 smoother), exact rational brute force on a tiny grid, the classical V-cycle
 (Alg. 1) that identity initialisation must recover (Sec. 3.4 and the recovery
-remark of Sec. 3.5), and dense linear algebra on tiny grids.
+remark of Sec. 3.3), and dense linear algebra on tiny grids.
 """
 from fractions import Fraction
 import json
@@ -105,7 +105,7 @@ def test_smoother_eigenvalues_closed_form(coefs):
     D_g^{-1} A_g share the sine eigenbasis, and one learnable smoothing step maps
     the error mode v_pq to sigma v_pq with
     sigma = 1 - eta theta (sum_k c_k lam_hat^k) lam,  lam_hat = (cos p pi h + cos q pi h)/2,
-    lam = 1 - lam_hat  (Sec. 3.5, eq. eigenvalue-S; K > 1 per the ChebConv remark)."""
+    lam = 1 - lam_hat  (Sec. 3.3, eq. eigenvalue-S; K > 1 per the ChebConv remark)."""
     side = 17
     h = H.square_hierarchy(side)
     lv = levels_of(h, ghost_degree=4)
@@ -317,7 +317,7 @@ def test_exact_rational_cycle_tiny():
 # ----------------------------------------------------------------------------- P6 proposition
 def test_proposition_learnable_smoothing_factor_not_worse():
     """min over (w1, w2, theta, eta) of rho(S_w) <= min over omega of rho(S_omega)
-    (Sec. 3.5, Proposition), with S built column by column from the oracle."""
+    (Sec. 3.3, Proposition), with S built column by column from the oracle."""
     h = H.square_hierarchy(9, H.block_field(C.rng(9, 1, 5), 2, -1, 1))
     lv = levels_of(h)
     J, n = h.nlevels, h.sizes[0]
