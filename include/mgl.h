@@ -183,6 +183,29 @@ mg_status mg_vcycle_backward(mg_ctx* ctx, const void* ckpt, const void* gu_out,
 mg_status mg_residual(mg_ctx* ctx, const double* f, const double* u, double* r,
                       double* norms, void* stream);
 
+/* Residual loss of training (paper Sec. 3.1, Alg. 3: the loss is the residual
+ * of the linear system after the unrolled cycles) and its gradients, all in
+ * FP64 on the device.  With r_b = f_b - A_0 u_b per column b:
+ *   MG_LOSS_MEAN_REL_SQ: L = (1/B) sum_b ||r_b||^2 / ||f_b||^2  (a column with
+ *       f_b = 0 contributes 0 and gets zero gradients)
+ *       dL/du_b = -(2/B) A_0^T r_b / ||f_b||^2
+ *       dL/df_b = (2/B) (r_b / ||f_b||^2 - ||r_b||^2 f_b / ||f_b||^4)
+ *   MG_LOSS_RESID_NORM:  L = sum_b ||r_b||_2  (Alg. 3's residual norm, summed
+ *       over the columns), dL/du_b = -A_0^T r_b / ||r_b||, dL/df_b = r_b / ||r_b||
+ *       (zero for a column with r_b = 0).
+ * f, u: device double [n_0 x B].  gseed: device double [1], a factor on both
+ * gradients (the cotangent of L from the caller's graph), or NULL for 1.
+ * loss: device double [1] or NULL.  gu, gf: device double [n_0 x B] or NULL;
+ * they must not overlap f, u or each other.  gu needs a symmetric A_0 and a
+ * context set up with MG_FLAG_BACKWARD (MG_ERR_UNSUPPORTED otherwise).
+ * Overwrites the context's FP64 scratch vector (not f or u). */
+typedef enum {
+    MG_LOSS_MEAN_REL_SQ = 0,
+    MG_LOSS_RESID_NORM = 1
+} mg_loss_kind;
+mg_status mg_residual_loss(mg_ctx* ctx, int32_t kind, const double* f, const double* u, const double* gseed,
+                           double* loss, double* gu, double* gf, void* stream);
+
 /* One outer iteration of the solver in refinement form:
  *     u_out = u_in + LMG_p(A_0, fl_p(f - A_0 u_in), 0)
  * with the residual and the update in FP64 and the cycle in the context

@@ -159,3 +159,42 @@ def unrolled_loss_and_grad(levels, prm: OParams, f, cycles: int = 10, u0=None):
     for m in range(cycles, 0, -1):
         _, g = lmg_vjp(levels, prm, 0, f, us[m - 1], g, grads)
     return loss, grads
+
+
+def residual_loss_grads(A, f, u, kind: str = "mean_rel_sq"):
+    """Alg. 3's residual loss (Sec. 3.1) and its gradients with respect to u and
+    f, written out by hand.  With r_b = f_b - A u_b per column:
+      mean_rel_sq: L = (1/B) sum_b ||r_b||^2 / ||f_b||^2,
+          dL/du_b = -(2/B) A^T r_b / ||f_b||^2,
+          dL/df_b = (2/B) (r_b / ||f_b||^2 - ||r_b||^2 f_b / ||f_b||^4)
+          (the second term from the f-dependence of the denominator);
+          a column with f_b = 0 contributes 0 and has zero gradients;
+      resid_norm: L = sum_b ||r_b||_2, dL/du_b = -A^T r_b / ||r_b||,
+          dL/df_b = r_b / ||r_b|| (zero where r_b = 0).
+    Returns (L, gu, gf)."""
+    f = np.asarray(f, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    B = f.shape[1]
+    r = f - A @ u
+    rn2 = np.sum(r * r, axis=0)
+    fn2 = np.sum(f * f, axis=0)
+    gu = np.zeros_like(f)
+    gf = np.zeros_like(f)
+    if kind == "mean_rel_sq":
+        L = 0.0
+        for b in range(B):
+            if fn2[b] == 0.0:
+                continue
+            L += rn2[b] / fn2[b]
+            gu[:, b] = -(2.0 / B) * (A.T @ r[:, b]) / fn2[b]
+            gf[:, b] = (2.0 / B) * (r[:, b] / fn2[b] - rn2[b] * f[:, b] / fn2[b] ** 2)
+        return L / B, gu, gf
+    if kind == "resid_norm":
+        rn = np.sqrt(rn2)
+        for b in range(B):
+            if rn[b] == 0.0:
+                continue
+            gu[:, b] = -(A.T @ r[:, b]) / rn[b]
+            gf[:, b] = r[:, b] / rn[b]
+        return float(np.sum(rn)), gu, gf
+    raise ValueError(f"unknown loss kind {kind}")

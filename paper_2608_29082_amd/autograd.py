@@ -59,35 +59,38 @@ class VCycle(torch.autograd.Function):
 
 
 class ResidualLoss(torch.autograd.Function):
-    """L = mean_b ||f_b - A u_b||^2 / ||f_b||^2 (FP64 residual in the library)."""
+    """Alg. 3's residual loss through mg_residual_loss: kind "mean_rel_sq"
+    L = mean_b ||f_b - A u_b||^2 / ||f_b||^2 (the training workload's loss) or
+    "resid_norm" L = sum_b ||f_b - A u_b||_2.  The loss, both gradients and
+    their scaling by the incoming cotangent are computed by the library in
+    FP64; this node only passes tensors."""
 
     @staticmethod
-    def forward(ac, mg, f, u):
-        r, norms = mg.residual(f.contiguous(), u.contiguous())
-        _, fn = mg.residual(f.contiguous(), torch.zeros_like(u), want_r=False)
-        fn2 = fn * fn
-        ac.mg, ac.r, ac.fn2 = mg, r, fn2
-        return torch.mean(norms * norms / fn2)
+    def forward(ac, mg, f, u, kind="mean_rel_sq"):
+        f, u = f.contiguous(), u.contiguous()
+        loss, _, _ = mg.residual_loss(f, u, kind=kind)
+        ac.mg, ac.kind = mg, kind
+        ac.save_for_backward(f, u)
+        return loss.reshape(())
 
     @staticmethod
     def backward(ac, g):
-        mg, r, fn2 = ac.mg, ac.r, ac.fn2
-        B = r.shape[1]
-        # dL/du = -(2/B) A^T (r / ||f||^2) = (2/B) * (0 - A (r / ||f||^2))  (A symmetric)
-        scaled = (r / fn2[None, :]).contiguous()
-        neg_Ar, _ = mg.residual(torch.zeros_like(r), scaled)
-        gu = (2.0 / B) * g * neg_Ar
-        gf = (2.0 / B) * g * scaled if ac.needs_input_grad[1] else None
-        return None, gf, gu
+        f, u = ac.saved_tensors
+        need = ac.needs_input_grad
+        seed = g.detach().to(device=f.device, dtype=torch.float64).reshape(1).contiguous()
+        _, gu, gf = ac.mg.residual_loss(f, u, kind=ac.kind, gseed=seed, want_loss=False, want_gu=need[2],
+                                        want_gf=need[1])
+        return None, gf, gu, None
 
 
-def unrolled_loss(mg, theta: torch.Tensor, f: torch.Tensor, cycles: int = 10, u0=None) -> torch.Tensor:
+def unrolled_loss(mg, theta: torch.Tensor, f: torch.Tensor, cycles: int = 10, u0=None,
+                  kind: str = "mean_rel_sq") -> torch.Tensor:
     """Loss after `cycles` refinement steps from u0 (zero by default)."""
     mg.set_params(theta.detach().double().cpu().numpy())
     u = torch.zeros_like(f) if u0 is None else u0
     for _ in range(cycles):
         u = RefineStep.apply(mg, theta, f, u)
-    return ResidualLoss.apply(mg, f, u)
+    return ResidualLoss.apply(mg, f, u, kind)
 
 
 def train_rprop(mg, theta0, f, cycles: int = 10, steps: int = 100, lr: float = 0.01, tol: float = 1e-6,

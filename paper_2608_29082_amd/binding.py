@@ -26,12 +26,13 @@ FLAG_NO_TAIL = 2
 FLAG_NO_TILES = 4
 
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
-            "mg_vcycle_backward", "mg_residual", "mg_refine_step", "mg_refine_step_backward",
+            "mg_vcycle_backward", "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward",
             "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
             "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error",
             "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres"]
 KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6, "conv": 7}
 PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
+LOSS_KINDS = {"mean_rel_sq": 0, "resid_norm": 1}
 # default threshold of the second Gram-Schmidt pass: run it for a vector when
 # the first pass left less than a tenth of its norm (orthogonality to about
 # ten units of roundoff per vector; 1/sqrt 2 is the "twice is enough" bound)
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.mg_vcycle_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.mg_residual.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mg_refine_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mg_residual_loss.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.mg_refine_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.mg_solve.argtypes = [vp, vp, vp, C.POINTER(RhsInfo), vp]
     lib.mg_level_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
@@ -117,7 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.mg_destroy.restype = None
     lib.mg_last_error.restype = C.c_char_p
     for name in ("mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle", "mg_vcycle_backward",
-                 "mg_residual", "mg_refine_step", "mg_refine_step_backward", "mg_solve", "mg_level_info",
+                 "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward", "mg_solve", "mg_level_info",
                  "mg_timing_start", "mg_timing_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -329,6 +331,23 @@ class Context:
         norms = self.torch.empty(self.B, dtype=self.torch.float64, device=self.device)
         _check(self.lib.mg_residual(self._h, _ptr(f), _ptr(u), _ptr(r), _ptr(norms), self._s()), "mg_residual")
         return r, norms
+
+    def residual_loss(self, f, u, kind="mean_rel_sq", gseed=None, want_loss=True, want_gu=False, want_gf=False):
+        """mg_residual_loss: (loss [1], dL/du, dL/df) as device float64 tensors (None
+        where not requested).  kind "mean_rel_sq": mean_b ||r_b||^2/||f_b||^2;
+        "resid_norm": sum_b ||r_b||_2.  gseed: device float64 tensor [1] scaling
+        both gradients (None: 1)."""
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u, self.torch.float64, "u")
+        if gseed is not None and (gseed.device.type != "cuda" or gseed.dtype != self.torch.float64
+                                  or gseed.numel() != 1 or not gseed.is_contiguous()):
+            raise ValueError("gseed: expected a contiguous float64 CUDA tensor with one element")
+        loss = self.torch.empty(1, dtype=self.torch.float64, device=self.device) if want_loss else None
+        gu = self.empty(self.torch.float64) if want_gu else None
+        gf = self.empty(self.torch.float64) if want_gf else None
+        _check(self.lib.mg_residual_loss(self._h, LOSS_KINDS[kind], _ptr(f), _ptr(u), _ptr(gseed), _ptr(loss),
+                                         _ptr(gu), _ptr(gf), self._s()), "mg_residual_loss")
+        return loss, gu, gf
 
     def refine_step(self, f, u_in, u_out=None, ckpt=None):
         self._vec(f, self.torch.float64, "f")

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "chebtab.hpp"
+
 namespace mgl {
 
 struct bf16_t { uint16_t bits; };
@@ -891,6 +893,110 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
   if (threadIdx.x == 0) norms[b] = sqrt(red[0]);
 }
 
+// ------------------------------------------------------------------ residual loss (Alg. 3)
+// Per-block, per-column partial sums of x^2 over the outer residual's row
+// chunks (block b owns rows [b*chunk, (b+1)*chunk)), fixed order.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_colsq(int n, int B, int lbs, int chunk, const double* __restrict__ x,
+                                               double* __restrict__ part) {
+  __shared__ double red[256 * 4];
+  const int LB = 1 << lbs, rpb = 256 >> lbs;
+  const int lane = threadIdx.x & (LB - 1), rg = uni<WIDE>((int)(threadIdx.x >> lbs));
+  const int blk = xcd_block();
+  const long lo = (long)blk * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long i0 = lo + (long)rg * 4; i0 < hi; i0 += 4L * rpb) {
+    int q = 0;
+    for (int b = lane; b < B; b += LB, ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (i0 + r < hi) {
+          const double v = x[(size_t)(i0 + r) * B + b];
+          acc[q] += v * v;
+        }
+  }
+  for (int q = 0; q < 4; ++q) red[q * 256 + threadIdx.x] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < LB) {
+    int q = 0;
+    for (int b = lane; b < B; b += LB, ++q) {
+      double s = 0.0;
+      for (int g = 0; g < rpb; ++g) s += red[q * 256 + g * LB + lane];
+      part[(size_t)blk * B + b] = s;
+    }
+  }
+}
+
+// Loss and per-column gradient coefficients from the column norms rn = ||r_b||,
+// fn = ||f_b|| (one block of 256 work-items, B <= 256, fixed summation tree):
+//   kind 0: L = (1/B) sum_b rn_b^2 / fn_b^2,  alpha_b = 2 g / (B fn_b^2),
+//           beta_b = 2 g rn_b^2 / (B fn_b^4); a column with fn_b = 0 adds 0
+//           and gets alpha_b = beta_b = 0
+//   kind 1: L = sum_b rn_b,  alpha_b = g / rn_b (0 when rn_b = 0),  beta_b = 0
+// so that dL/du_b = -alpha_b A^T r_b and dL/df_b = alpha_b r_b - beta_b f_b,
+// scaled by the incoming cotangent g = *gseed (1 when gseed is null).
+__global__ __launch_bounds__(256) void k_loss_coef(const double* __restrict__ rn, const double* __restrict__ fn,
+                                                   int B, int kind, const double* __restrict__ gseed,
+                                                   double* __restrict__ alpha, double* __restrict__ beta,
+                                                   double* __restrict__ loss) {
+  __shared__ double red[256];
+  const int b = threadIdx.x;
+  const double g = gseed ? gseed[0] : 1.0;
+  double term = 0.0;
+  if (b < B) {
+    const double r = rn[b], q = fn[b];
+    double a = 0.0, c = 0.0;
+    if (kind == 0) {
+      if (q > 0.0) {
+        const double q2 = q * q;
+        term = r * r / q2;
+        a = 2.0 * g / ((double)B * q2);
+        c = a * term;
+      }
+    } else {
+      term = r;
+      a = r > 0.0 ? g / r : 0.0;
+    }
+    if (alpha) alpha[b] = a;
+    if (beta) beta[b] = c;
+  }
+  red[threadIdx.x] = term;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) loss[0] = kind == 0 ? red[0] / (double)B : red[0];
+}
+
+// gu_b = -alpha_b (A r_b)  (A symmetric, so A^T r = A r),  gf_b = alpha_b r_b - beta_b f_b;
+// either output may be null.
+template <int ROWS, bool WIDE>
+__global__ __launch_bounds__(256) void k_loss_grad(Lvl<double> L, int B, int lbs, const double* __restrict__ r,
+                                                   const double* __restrict__ f, const double* __restrict__ alpha,
+                                                   const double* __restrict__ beta, double* __restrict__ gu,
+                                                   double* __restrict__ gf) {
+  const Tile<ROWS, WIDE> t(L.n, lbs);
+  if (WIDE && !t.any) return;
+  for (int b = t.lane; b < B; b += t.LB) {
+    const double a = alpha[b];
+    double rv[ROWS], s[ROWS];
+#pragma unroll
+    for (int q = 0; q < ROWS; ++q) {
+      rv[q] = r[(size_t)t.row[q] * B + b];
+      s[q] = 0.0;
+    }
+    if (gu) ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, t.row, t.row0, r, B, b, s);
+#pragma unroll
+    for (int q = 0; q < ROWS; ++q) {
+      if (!t.ok[q]) continue;
+      const size_t o = (size_t)t.row[q] * B + b;
+      if (gu) gu[o] = -a * (s[q] + uni<WIDE>(L.diag[t.row[q]]) * rv[q]);
+      if (gf) gf[o] = a * rv[q] - beta[b] * f[o];
+    }
+  }
+}
+
 // Per-column solver bookkeeping after the residual of iterate m.
 // st: [0,B) active, [B,2B) iters, [2B,3B) status; 3B: active count.
 __global__ void k_solve_check(const double* __restrict__ norms, double* __restrict__ fnorm,
@@ -1406,12 +1512,6 @@ __global__ void k_grad_combine(const double* __restrict__ dots, const int* __res
     }
   }
 }
-
-// Power-series coefficients of the Chebyshev polynomials,
-// T_k(t) = sum_m t[k][m] t^m for k, m <= 8.
-struct ChebTab {
-  double t[9][9];
-};
 
 // Gradients with respect to Chebyshev coefficients from those with respect to
 // the power-series coefficients the cycle ran with:

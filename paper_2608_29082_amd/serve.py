@@ -84,7 +84,7 @@ class Server:
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", slots=4, setup_threads=4,
                  hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0",
-                 solver="refine", restart=30):
+                 solver="refine", restart=30, fail_setup=None):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -99,6 +99,9 @@ class Server:
         if solver not in ("refine", "fgmres"):
             raise ValueError("solver must be 'refine' or 'fgmres'")
         self.solver, self.restart = solver, restart
+        # fail_setup(request) -> bool: make that request's setup fail after admission (tests of the
+        # error path: the budget it took must come back)
+        self.fail_setup = fail_setup
 
     def _params(self, J, side):
         K = self.K
@@ -142,14 +145,19 @@ class Server:
                 if item is None:
                     return
                 req, t_arr = item
+                hier = ctx = None
+                fp = 0
                 try:
                     hier = Bd.SquareHierarchy(req.side, req.blocks)
                     params = self._params(hier.nlevels, req.side)
-                    fp = self._footprint(hier, params, hier.sizes[0])
-                    self.budget.acquire(fp)
+                    need = self._footprint(hier, params, hier.sizes[0])
+                    self.budget.acquire(need)
+                    fp = need
                     with lock:
                         self.peak_used = max(self.peak_used, self.budget.used)
                     t_adm = now()
+                    if self.fail_setup is not None and self.fail_setup(req):
+                        raise RuntimeError(f"setup of request {req.rid} failed (injected)")
                     with torch.cuda.stream(stream):
                         ctx = Bd.Context(None, None, params, self.K, self.K, self.K, precision=self.precision,
                                          nrhs=1, max_outer=self.max_outer, check_every=10, rtol=self.rtol,
@@ -164,7 +172,13 @@ class Server:
                     stream.synchronize()
                     hier.close()
                     ready.put((t_arr, req.rid, (req, ctx, f, fp, t_arr, t_adm, work)))
-                except Exception as e:  # report and keep serving
+                except Exception as e:  # report, give back what was taken and keep serving
+                    if ctx is not None:
+                        ctx.close()
+                    if hier is not None:
+                        hier.close()
+                    if fp:
+                        self.budget.release(fp)
                     with lock:
                         errors.append((req.rid, repr(e)))
                     ready.put((t_arr, req.rid, None))

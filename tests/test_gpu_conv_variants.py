@@ -8,7 +8,7 @@ import scipy.sparse as sp
 from mginputs import configs as C
 from oracle import adjoint as AD
 from oracle import lmg as O
-from tests.gpu_util import ctx_for, rel, small_cases, to_dev, to_np
+from tests.gpu_util import ctx_for, elem_rel, small_cases, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -41,9 +41,9 @@ def test_variant_cycle_matches_oracle(prec, agg, basis, name, hier):
     ctx = ctx_for(hier, flat, 3, B, prec, basis=basis, aggregation=agg)
     ud = to_dev(u, ctx.cycle_dtype)
     ctx.vcycle(to_dev(f, ctx.cycle_dtype), ud)
-    err = rel(to_np(ud), want)
+    err = elem_rel(to_np(ud), want)
     e = ctx.refine_step(to_dev(f, torch.float64), torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda"))
-    err2 = rel(to_np(e), O.lmg(lv, prm, 0, f, np.zeros_like(f)))
+    err2 = elem_rel(to_np(e), O.lmg(lv, prm, 0, f, np.zeros_like(f)))
     print(f"{name} {agg}/{basis} {prec}: cycle {err:.2e} refine {err2:.2e}", flush=True)
     assert err <= TOL[prec] and err2 <= TOL[prec]
 
@@ -62,7 +62,7 @@ def test_variant_gradient_matches_oracle(agg, basis):
     L = AG.unrolled_loss(ctx, th, to_dev(f, torch.float64), cycles=3)
     L.backward()
     Lo, go = AD.unrolled_loss_and_grad(_oracle(hier, agg), O.unpack(flat, J, 3, 3, 3, basis=basis), f, cycles=3)
-    err = rel(th.grad.numpy(), O.pack(go))
+    err = elem_rel(th.grad.numpy(), O.pack(go))
     print(f"grad {agg}/{basis}: loss {L.item():.6e} vs {Lo:.6e} rel {err:.2e}", flush=True)
     assert abs(L.item() - Lo) <= 1e-10 * Lo
     assert err <= 1e-9
@@ -86,6 +86,6 @@ def test_given_weighted_graph_matches_oracle():
     want = O.lmg(_oracle(hier, "weighted", G), O.unpack(flat, J, 2, 2, 2), 0, f, np.zeros_like(f))
     ctx = ctx_for(hier, flat, 2, 2, "fp64", G=G, aggregation="weighted")
     e = ctx.refine_step(to_dev(f, torch.float64), torch.zeros((hier.sizes[0], 2), dtype=torch.float64, device="cuda"))
-    err = rel(to_np(e), want)
+    err = elem_rel(to_np(e), want)
     print(f"given weighted graph: rel {err:.2e}", flush=True)
     assert err <= 1e-12

@@ -6,7 +6,7 @@ import pytest
 from mginputs import configs as C
 from oracle import adjoint as AD
 from oracle import lmg as O
-from tests.gpu_util import ctx_for, oracle_levels, oracle_params, rel, to_dev, to_np
+from tests.gpu_util import ctx_for, oracle_levels, oracle_params, elem_rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -34,9 +34,9 @@ def test_training_257_gradient_full_size_fd_and_oracle():
     L0, g = loss(flat, True)
     Lo, go = AD.unrolled_loss_and_grad(oracle_levels(w.hier), O.unpack(flat, J, 3, 3, 3), w.f, cycles=10)
     go = O.pack(go)
-    print(f"loss gpu {L0:.6e} oracle {Lo:.6e}; grad rel {rel(g, go):.2e}", flush=True)
+    print(f"loss gpu {L0:.6e} oracle {Lo:.6e}; grad rel {elem_rel(g, go):.2e}", flush=True)
     assert abs(L0 - Lo) <= 1e-9 * Lo
-    assert rel(g, go) <= 1e-7
+    assert elem_rel(g, go) <= 1e-7
     step = 1e-6
     for i in list(np.argsort(-np.abs(g))[:6]) + [0, 1, 2 + 1, 2 + 3 + 1 + 2]:
         pp, pm = flat.copy(), flat.copy()
@@ -61,7 +61,7 @@ def test_training_257_fp32_gradient_close_to_fp64():
         L = AG.unrolled_loss(ctx, th, to_dev(w.f, torch.float64), cycles=10)
         L.backward()
         grads[prec] = th.grad.numpy().copy()
-    assert rel(grads["fp32"], grads["fp64"]) <= 1e-3
+    assert elem_rel(grads["fp32"], grads["fp64"]) <= 1e-3
 
 
 def test_lshape_full_size_cycle_and_mixed_solve():
@@ -79,7 +79,7 @@ def test_lshape_full_size_cycle_and_mixed_solve():
     ud = to_dev(u, torch.float64)
     ctx.vcycle(to_dev(w.f, torch.float64), ud)
     kappa = np.linalg.cond(h.A[-1].toarray())
-    err = rel(to_np(ud), want)
+    err = elem_rel(to_np(ud), want)
     print(f"lshape fp64 cycle rel {err:.2e} (kappa(A_J) = {kappa:.1e})", flush=True)
     assert err <= max(1e-12, 50 * kappa * np.finfo(float).eps)
     ctx32 = ctx_for(h, C.identity_params(J, 3, 3, 3), 3, 1, "fp32", max_outer=20000)
@@ -107,6 +107,6 @@ def test_diffusion_513_bench_configuration_cycle():
     e = torch.zeros_like(f)
     ctx.refine_step(f, torch.zeros_like(f), e)          # e = LMG_32(A, f, 0)
     want = O.lmg(oracle_levels(h), oracle_params(flat, J, 3), 0, w.f, np.zeros_like(w.f))
-    err = rel(to_np(e), want)
+    err = elem_rel(to_np(e), want)
     print(f"513 fp32 bench-config cycle rel {err:.2e}", flush=True)
     assert err <= 2e-5

@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 from mginputs import configs as C
 from oracle import krylov as KR
 from oracle import lmg as O
-from tests.gpu_util import ctx_for, oracle_levels, oracle_params, rel, small_cases, to_dev, to_np
+from tests.gpu_util import ctx_for, oracle_levels, oracle_params, elem_rel, small_cases, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def test_fmg_matches_oracle(prec, name, hier, B, tail):
     u = ctx.empty()
     u.fill_(float("nan"))             # the input value of u must not be used
     ctx.fmg(to_dev(f, ctx.cycle_dtype), u)
-    err = rel(to_np(u), want)
+    err = elem_rel(to_np(u), want)
     print(f"fmg {name} {prec} B={B} tail={tail}: rel {err:.2e}", flush=True)
     assert err <= TOL[prec]
 
@@ -52,7 +52,7 @@ def test_fgmres_fixed_iterations_match_oracle(precond, name, hier):
         want, it, _, _ = KR.fgmres(lv, prm, f, restart=4, rtol=0.0, max_iter=k, precond=precond)
         x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
         info = ctx.fgmres(to_dev(f, torch.float64), x, restart=4, max_iter=k, rtol=0.0, precond=precond)
-        err = rel(to_np(x), want)
+        err = elem_rel(to_np(x), want)
         print(f"fgmres {precond} {name} k={k}: rel {err:.2e} iters {info.iters}", flush=True)
         assert list(info.iters) == list(it) == [k] * B
         assert info.code == 5 and np.all(info.status == 5)
@@ -76,7 +76,7 @@ def test_fgmres_wide_batches_match_oracle(B):
     ctx = ctx_for(hier, flat, 2, B, "fp64")
     x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
     info = ctx.fgmres(to_dev(f, torch.float64), x, restart=4, max_iter=6, rtol=0.0, precond="vcycle")
-    err = rel(to_np(x)[:, cols], want)
+    err = elem_rel(to_np(x)[:, cols], want)
     print(f"fgmres B={B}: rel {err:.2e}", flush=True)
     assert np.all(info.iters == 6) and err <= 1e-9
 
@@ -96,7 +96,7 @@ def test_fgmres_reorthogonalisation_policies_match_oracle(reorth):
     ctx = ctx_for(hier, flat, 2, B, "fp64")
     x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
     info = ctx.fgmres(to_dev(f, torch.float64), x, restart=4, max_iter=7, rtol=0.0, precond="vcycle", reorth=reorth)
-    err = rel(to_np(x), want)
+    err = elem_rel(to_np(x), want)
     print(f"fgmres reorth={reorth}: rel {err:.2e}", flush=True)
     assert list(info.iters) == [7] * B
     assert err <= 1e-9
@@ -117,7 +117,7 @@ def test_fgmres_long_restart_matches_oracle(restart, k):
     ctx = ctx_for(hier, flat, 2, B, "fp64")
     x = torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda")
     info = ctx.fgmres(to_dev(f, torch.float64), x, restart=restart, max_iter=k, rtol=0.0, precond="none")
-    err = rel(to_np(x), want)
+    err = elem_rel(to_np(x), want)
     print(f"fgmres none m={restart} k={k}: rel {err:.2e}", flush=True)
     assert list(info.iters) == list(it) == [k] * B
     assert err <= 1e-9
@@ -174,7 +174,7 @@ def test_fgmres_caller_workspace_and_restart_growth():
         assert info.code == 0
         xs.append(to_np(x))
     assert np.array_equal(xs[1], xs[2])
-    assert rel(xs[0], xs[1]) <= 1e-7
+    assert elem_rel(xs[0], xs[1]) <= 1e-7
     with pytest.raises(Exception):
         ctx.fgmres(fd, torch.zeros_like(fd), restart=12,
                    work=torch.empty(16, dtype=torch.uint8, device="cuda"))
@@ -210,11 +210,11 @@ def test_fgmres_benchmark_configuration():
     ctx64 = ctx_for(h, flat, 3, 2, "fp64")
     u64 = ctx64.empty()
     ctx64.fmg(to_dev(f2, torch.float64), u64)
-    err64 = rel(to_np(u64), want)
+    err64 = elem_rel(to_np(u64), want)
     ctx2 = ctx_for(h, flat, 3, 2, "fp32")
     u = ctx2.empty()
     ctx2.fmg(to_dev(f2, torch.float32), u)
-    err = rel(to_np(u), want)
+    err = elem_rel(to_np(u), want)
     print(f"513 fmg fp64 rel {err64:.2e}, fp32 rel {err:.2e}", flush=True)
     assert err64 <= 1e-12
     assert err <= (J - 1) * 2e-5

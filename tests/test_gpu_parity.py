@@ -12,7 +12,7 @@ import pytest
 
 from mginputs import configs as C, hierarchy as H
 from oracle import lmg as O
-from tests.gpu_util import ctx_for, oracle_levels, oracle_params, rel, small_cases, to_dev, to_np
+from tests.gpu_util import ctx_for, oracle_levels, oracle_params, elem_rel, small_cases, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _cycle_case(hier, K, B, seed, precision="fp64", nu=(2, 2), identity=False, R
     ctx.vcycle(fd, ud)
     torch.cuda.synchronize()
     got = to_np(ud)
-    return rel(got, want), got, want
+    return elem_rel(got, want), got, want
 
 
 @pytest.mark.parametrize("case", ["poisson33", "blocks65", "lshape"])
@@ -62,7 +62,7 @@ def test_identity_theta_is_classical_vcycle_on_gpu():
     f = g.standard_normal((hier.sizes[0], 2))
     u = g.standard_normal((hier.sizes[0], 2))
     classical = O.classical_mg(oracle_levels(hier), 2 / 3, 2, 0, f, u)
-    assert rel(got, classical) <= TOL["fp64"]
+    assert elem_rel(got, classical) <= TOL["fp64"]
 
 
 @pytest.mark.parametrize("nu", [(0, 1), (1, 0), (3, 2), (0, 0)])
@@ -139,7 +139,7 @@ def test_refine_step_equals_cycle_fp64():
     want = O.lmg(oracle_levels(hier), oracle_params(flat, J, 2), 0, f, u)
     ctx = ctx_for(hier, flat, 2, 3)
     out = ctx.refine_step(to_dev(f, torch.float64), to_dev(u, torch.float64))
-    assert rel(to_np(out), want) <= 1e-11
+    assert elem_rel(to_np(out), want) <= 1e-11
 
 
 def test_set_params_changes_cycle():
@@ -156,7 +156,7 @@ def test_set_params_changes_cycle():
     ud = to_dev(u, torch.float64)
     ctx.vcycle(to_dev(f, torch.float64), ud)
     want = O.lmg(oracle_levels(hier), oracle_params(p2, J, 2), 0, f, u)
-    assert rel(to_np(ud), want) <= TOL["fp64"]
+    assert elem_rel(to_np(ud), want) <= TOL["fp64"]
 
 
 def test_deterministic_and_column_independent():
@@ -203,5 +203,5 @@ def test_lds_coarse_tail_matches_per_level_sweeps(precision):
             outs.append((to_np(u), to_np(v)))
         want = O.lmg(oracle_levels(hier), oracle_params(flat, J, 3), 0, f, np.zeros_like(f))
         for a, b in zip(outs[0], outs[1]):
-            assert rel(a, b) <= TOL[precision]
-            assert rel(a, want) <= TOL[precision]
+            assert elem_rel(a, b) <= TOL[precision]
+            assert elem_rel(a, want) <= TOL[precision]

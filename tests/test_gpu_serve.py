@@ -80,3 +80,21 @@ def test_fgmres_serving_converges_and_is_invariant():
         alone, e2, _ = _server(slots=1, setup_threads=1, solver="fgmres").run([q], open_loop=False)
         assert not e2 and alone[0].iters == byid[q.rid].iters
         assert np.array_equal(alone[0].u, byid[q.rid].u)
+
+
+def test_failed_setup_returns_its_budget():
+    """A request whose setup fails after admission is reported as an error and
+    gives its HBM budget back: with a budget of one request, later requests are
+    still admitted and served, and nothing is held at the end."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(5, 0.0, seed=6, sides=(65,))
+    probe = _server(slots=1, setup_threads=1)
+    res, errs, _ = probe.run(reqs, open_loop=False)
+    assert not errs
+    srv = _server(slots=2, setup_threads=2, hbm_budget=max(r.footprint for r in res),
+                  fail_setup=lambda q: q.rid in (0, 2))
+    res2, errs2, _ = srv.run(reqs, open_loop=False)
+    assert sorted(r for r, _ in errs2) == [0, 2]
+    assert sorted(r.rid for r in res2) == [1, 3, 4]
+    assert all(r.status == 0 for r in res2)
+    assert srv.budget.used == 0

@@ -14,7 +14,7 @@ import pytest
 
 from mginputs import configs as C, hierarchy as H
 from oracle import lmg as O
-from tests.gpu_util import ctx_for, rel, to_dev, to_np
+from tests.gpu_util import ctx_for, elem_rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -94,10 +94,10 @@ def test_fused_conv_cycle_matches_oracle(prec, B):
     ctx = ctx_for(hier, flat, 3, B, prec)
     ud = to_dev(u, torch.float32)
     ctx.vcycle(to_dev(f, torch.float32), ud)
-    err = rel(to_np(ud), want)
+    err = elem_rel(to_np(ud), want)
     # a refinement step from zero: the cycle from a zero iterate, with the coarse tail
     e = ctx.refine_step(to_dev(f, torch.float64), torch.zeros((hier.sizes[0], B), dtype=torch.float64, device="cuda"))
-    err2 = rel(to_np(e), O.lmg(O.make_levels(hier.A, hier.P, hier.R), O.unpack(flat, J, 3, 3, 3), 0, f,
+    err2 = elem_rel(to_np(e), O.lmg(O.make_levels(hier.A, hier.P, hier.R), O.unpack(flat, J, 3, 3, 3), 0, f,
                                np.zeros_like(f)))
     assert _conv_launches(ctx, to_dev(f, torch.float32), to_dev(u, torch.float32)) > 0
     print(f"{name} {prec} B={B}: cycle rel {err:.2e}, refinement step rel {err2:.2e}", flush=True)
@@ -193,8 +193,53 @@ def test_fused_conv_high_order_and_given_graph(K, graph):
     assert _conv_launches(on, to_dev(f, torch.float32), to_dev(u, torch.float32)) > 0
     want = O.lmg(O.make_levels(hier.A, hier.P, hier.R, G), O.unpack(flat, J, *K), 0, f, u)
     d = float(np.abs(outs[0] - outs[1]).max())
-    err = rel(outs[0], want)
+    err = elem_rel(outs[0], want)
     print(f"{name} K={K} graph={graph}: max diff {d:.1e}, rel to oracle {err:.2e}", flush=True)
     assert d == 0.0
     assert err <= TOL["fp32"]
+    on.close(); off.close()
+
+
+@pytest.mark.parametrize("B", [64, 48])
+def test_fused_conv_equals_hop_chain_bench_hierarchy(B):
+    """The benchmark's hierarchy (513 x 513, log10 a ~ U(-3, 3), 8 levels, four
+    tiled levels) with the shipped trained parameters at B = 64 (four column
+    groups per tile, the benchmark's launch) and B = 48 (three).  A cycle from a
+    random iterate runs the smoothing update (out += scale Phi(s)), Phi_R
+    (out = Phi(r)) and Phi_P (u += Phi(P e)); a refinement step from zero runs
+    the zero-iterate smoothing launch on D^{-1} f (row scales applied as the
+    input enters LDS).  Every element must equal the per-hop chain's bit for
+    bit, and the fused context must have launched the tile kernel on every
+    tiled level."""
+    import torch
+    from paper_2608_29082_amd import params as PR
+    w = C.diffusion_513(B=B)
+    h = w.hier
+    J = h.nlevels
+    theta, meta = PR.load(PR.default_file("diffusion-513", 3))
+    flat = PR.map_levels(theta, meta["J"], J, 3, 3, 3)
+    g = C.rng(6, 26, B)
+    u = g.standard_normal((h.sizes[0], B))
+    on, off = _pair(h, flat, 3, B, "fp32")
+    outs = []
+    for ctx in (on, off):
+        ud = to_dev(u, torch.float32)
+        ctx.vcycle(to_dev(w.f, torch.float32), ud)
+        e = ctx.refine_step(to_dev(w.f, torch.float64), torch.zeros((h.sizes[0], B), dtype=torch.float64,
+                                                                     device="cuda"))
+        outs.append((to_np(ud), to_np(e)))
+    per_level = []
+    for l in range(4):
+        on.timing_start("conv", l)
+        on.vcycle(to_dev(w.f, torch.float32), to_dev(u, torch.float32))
+        torch.cuda.synchronize()
+        per_level.append(on.timing_read()[0])
+    on.timing_start(None)
+    n_off = _conv_launches(off, to_dev(w.f, torch.float32), to_dev(u, torch.float32))
+    d1 = np.abs(outs[0][0] - outs[1][0])
+    d2 = np.abs(outs[0][1] - outs[1][1])
+    print(f"513 B={B}: fused launches per level {per_level}, untiled {n_off}; "
+          f"differing elements {int((d1 > 0).sum())} / {int((d2 > 0).sum())}", flush=True)
+    assert all(c == 6 for c in per_level) and n_off == 0
+    assert d1.max() == 0.0 and d2.max() == 0.0
     on.close(); off.close()

@@ -8,7 +8,7 @@ from mginputs import configs as C, darcy as D
 from oracle import adjoint as AD
 from oracle import lmg as O
 from oracle import variants as V
-from tests.gpu_util import ctx_for, oracle_levels, oracle_params, rel, to_dev, to_np
+from tests.gpu_util import ctx_for, oracle_levels, oracle_params, elem_rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def test_darcy_cycle_matches_oracle(prec, tol):
     ctx = ctx_for(h, flat, 3, 3, prec, nu=(4, 4))
     ud = to_dev(u, ctx.cycle_dtype)
     ctx.vcycle(to_dev(f, ctx.cycle_dtype), ud)
-    err = rel(to_np(ud), want)
+    err = elem_rel(to_np(ud), want)
     print(f"darcy {prec} cycle rel {err:.2e}", flush=True)
     assert err <= tol
 
@@ -78,7 +78,7 @@ def test_variant_gradient_matches_oracle(name):
     Lo, go = AD.unrolled_loss_and_grad(oracle_levels(h), V.expand(name, phi0, J, K, K, K, nu_pre=4, nu_post=4), f,
                                        cycles=4, u0=u0)
     want = V.grad_phi(name, go, J, K, K, K)
-    err = rel(phi.grad.numpy(), want)
+    err = elem_rel(phi.grad.numpy(), want)
     print(f"variant {name}: loss {L.item():.6e} vs {Lo:.6e}, grad rel {err:.2e}", flush=True)
     assert abs(L.item() - Lo) <= 1e-10 * Lo
     assert err <= 1e-9

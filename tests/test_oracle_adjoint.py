@@ -120,3 +120,84 @@ def test_vector_vjp_exact_difference_quotient():
     lhs = np.sum(g * (O.lmg(lv, prm, 0, f + df, u + du) - O.lmg(lv, prm, 0, f, u)))
     rhs = np.sum(fbar * df) + np.sum(ubar * du)
     assert abs(lhs - rhs) <= 1e-11 * (abs(rhs) + np.linalg.norm(g) * np.linalg.norm(df))
+
+
+@pytest.mark.parametrize("kind", ["mean_rel_sq", "resid_norm"])
+def test_residual_loss_values_closed_form(kind):
+    """The loss at iterates whose residual is known exactly: u = 0 gives r = f
+    (L = 1 for the mean relative square, sum_b ||f_b|| for the norm), u = A^{-1} f
+    gives r = 0 (L = 0, zero gradients), u = A^{-1} (f / 2) gives r = f / 2."""
+    h = H.square_hierarchy(9)
+    A = h.A[0].toarray()
+    f = C.rng(6, 90, 0).standard_normal((A.shape[0], 3))
+    fn = np.linalg.norm(f, axis=0)
+    L0, _, gf0 = AD.residual_loss_grads(A, f, np.zeros_like(f), kind)
+    want0 = 1.0 if kind == "mean_rel_sq" else fn.sum()
+    assert abs(L0 - want0) <= 1e-14 * want0
+    ustar = np.linalg.solve(A, f)
+    L1, gu1, gf1 = AD.residual_loss_grads(A, f, ustar, kind)
+    assert L1 <= 1e-24 if kind == "mean_rel_sq" else L1 <= 1e-12
+    Lh, _, _ = AD.residual_loss_grads(A, f, np.linalg.solve(A, f / 2), kind)
+    wanth = 0.25 if kind == "mean_rel_sq" else fn.sum() / 2
+    assert abs(Lh - wanth) <= 1e-13 * wanth
+    if kind == "mean_rel_sq":
+        # at u = 0 the loss is 1 for every f, so dL/df vanishes (the two terms cancel)
+        assert np.abs(gf0).max() <= 1e-15 * np.abs(f).max()
+        assert np.abs(gu1).max() <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["mean_rel_sq", "resid_norm"])
+def test_residual_loss_gradients_match_torch_autograd_and_fd(kind):
+    """Hand gradients against torch CPU autograd of the loss definition and
+    against central differences; a zero right-hand side (mean_rel_sq) and a
+    zero residual (resid_norm) take no part."""
+    h = H.square_hierarchy(17, H.block_field(C.rng(6, 91, 1), 4, -1, 1))
+    A = h.A[0].toarray()
+    g = C.rng(6, 91, 0)
+    f = g.standard_normal((A.shape[0], 3))
+    u = g.standard_normal((A.shape[0], 3))
+    if kind == "mean_rel_sq":
+        f[:, 2] = 0.0
+    else:
+        f[:, 2] = 0.0
+        u[:, 2] = 0.0          # r = 0 exactly
+    L, gu, gf = AD.residual_loss_grads(A, f, u, kind)
+    At = torch.tensor(A)
+    ft = torch.tensor(f[:, :2], requires_grad=True)
+    ut = torch.tensor(u[:, :2], requires_grad=True)
+    r = ft - At @ ut
+    if kind == "mean_rel_sq":
+        Lt = ((r * r).sum(0) / (ft * ft).sum(0)).sum() / 3
+    else:
+        Lt = torch.sqrt((r * r).sum(0)).sum()
+    Lt.backward()
+    assert abs(L - Lt.item()) <= 1e-13 * abs(L)
+    assert np.abs(gu[:, :2] - ut.grad.numpy()).max() <= 1e-12 * np.abs(gu).max()
+    assert np.abs(gf[:, :2] - ft.grad.numpy()).max() <= 1e-12 * np.abs(gf).max()
+    assert np.abs(gu[:, 2]).max() == 0.0 and np.abs(gf[:, 2]).max() == 0.0
+    d = g.standard_normal(f.shape)
+    d[:, 2] = 0.0
+    eps = 1e-6
+    for which, grad in (("u", gu), ("f", gf)):
+        def Lat(s):
+            ff, uu = (f, u + s * d) if which == "u" else (f + s * d, u)
+            return AD.residual_loss_grads(A, ff, uu, kind)[0]
+        fd = (Lat(eps) - Lat(-eps)) / (2 * eps)
+        assert abs(fd - np.sum(grad * d)) <= 1e-6 * abs(fd)
+
+
+def test_residual_loss_planted_mistake_fails_fd():
+    """Dropping the denominator term of dL/df (a plausible slip) fails the
+    central-difference check."""
+    h = H.square_hierarchy(9)
+    A = h.A[0].toarray()
+    g = C.rng(6, 92, 0)
+    f = g.standard_normal((A.shape[0], 2))
+    u = g.standard_normal((A.shape[0], 2))
+    L, gu, gf = AD.residual_loss_grads(A, f, u)
+    r = f - A @ u
+    wrong = (2.0 / 2) * r / np.sum(f * f, axis=0)
+    d = g.standard_normal(f.shape)
+    fd = (AD.residual_loss_grads(A, f + 1e-6 * d, u)[0] - AD.residual_loss_grads(A, f - 1e-6 * d, u)[0]) / 2e-6
+    assert abs(fd - np.sum(gf * d)) <= 1e-6 * abs(fd)
+    assert abs(fd - np.sum(wrong * d)) > 1e-3 * abs(fd)
