@@ -282,6 +282,23 @@ mg_status mg_fgmres_workspace_bytes(const mg_ctx* ctx, const mg_krylov_options* 
 mg_status mg_fgmres(mg_ctx* ctx, const double* f, double* u, const mg_krylov_options* o,
                     void* work, size_t work_bytes, mg_rhs_info* info, void* stream);
 
+/* Allocation-free form of mg_fgmres, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as mg_fgmres without the
+ * workspace: the Krylov workspace is a static buffer of
+ * MG_FGMRES_STATIC_MAX_BYTES inside the library, one per GPU, held until the
+ * process ends; the call allocates no device or host memory.  Returns
+ * MG_ERR_OOM, before any device work, when mg_fgmres_workspace_bytes for these
+ * options exceeds that size (e.g. 129 x 129 unknowns with 16 columns fit a
+ * restart of 30; the 513 x 513 workload with 64 columns does not fit any).
+ * No part of the buffer needs to start at zero (each solve initialises what
+ * it reads), and it keeps the last call's contents.  Every call on one GPU
+ * shares the buffer: calls that overlap on one GPU, from any context or
+ * stream, race and must be serialised by the caller. */
+#define MG_FGMRES_STATIC_MAX_BYTES (64u << 20)
+mg_status mg_fgmres_static(mg_ctx* ctx, const double* f, double* u, const mg_krylov_options* o,
+                           mg_rhs_info* info, void* stream);
+
 /* Per-level sizes: n_l for l < J (out: host int64 [J]) plus ELL widths of
  * A_l (wA: host int32 [J], may be NULL). */
 mg_status mg_level_info(const mg_ctx* ctx, int64_t* n, int32_t* wA);

@@ -29,7 +29,7 @@ EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", 
             "mg_vcycle_backward", "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward",
             "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
             "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error",
-            "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres"]
+            "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres", "mg_fgmres_static"]
 KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6, "conv": 7}
 PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
 LOSS_KINDS = {"mean_rel_sq": 0, "resid_norm": 1}
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.mg_fmg.argtypes = [vp, vp, vp, vp]
     lib.mg_fgmres_workspace_bytes.argtypes = [vp, C.POINTER(_KrylovOptions), C.POINTER(sz)]
     lib.mg_fgmres.argtypes = [vp, vp, vp, C.POINTER(_KrylovOptions), vp, sz, C.POINTER(RhsInfo), vp]
+    lib.mg_fgmres_static.argtypes = [vp, vp, vp, C.POINTER(_KrylovOptions), C.POINTER(RhsInfo), vp]
     lib.mg_timing_start.argtypes = [vp, C.c_int32, C.c_int32]
     lib.mg_timing_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.mg_square_hierarchy.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(vp)]
@@ -407,6 +408,21 @@ class Context:
                                 0 if work is None else work.numel(), info, self._s())
         if st not in (0, 5, 6) or (raise_on_failure and st != 0):
             _check(st, "mg_fgmres")
+        return SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
+                         np.array([x.relres for x in info]), st)
+
+    def fgmres_static(self, f, u, restart=30, max_iter=500, rtol=None, precond="vcycle", reorth=None,
+                      raise_on_failure=False) -> SolveInfo:
+        """mg_fgmres_static: fgmres with the library's static per-GPU workspace
+        (no device allocation; calls on one GPU must not overlap)."""
+        self._vec(f, self.torch.float64, "f")
+        self._vec(u, self.torch.float64, "u")
+        o = _KrylovOptions(restart, max_iter, self._o.rtol if rtol is None else rtol, PRECONDITIONERS[precond],
+                           REORTH_DEFAULT if reorth is None else reorth)
+        info = (RhsInfo * self.B)()
+        st = self.lib.mg_fgmres_static(self._h, _ptr(f), _ptr(u), C.byref(o), info, self._s())
+        if st not in (0, 5, 6) or (raise_on_failure and st != 0):
+            _check(st, "mg_fgmres_static")
         return SolveInfo(np.array([x.iters for x in info]), np.array([x.status for x in info]),
                          np.array([x.relres for x in info]), st)
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -1292,11 +1293,12 @@ struct Engine final : EngineBase {
                          (const double*)k.y, x);
       LAUNCH_OK();
     }
-    std::vector<int> hst(3 * Bn + 1);
-    std::vector<double> hb(Bn), hf(Bn);
-    HIP_TRY(hipMemcpyAsync(hst.data(), k.S.st, hst.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hb.data(), k.beta, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hf.data(), k.S.fnorm, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    // fixed-size host buffers (B <= kMaxB): the solve allocates nothing when the caller brings the workspace
+    int hst[3 * kMaxB + 1];
+    double hb[kMaxB], hf[kMaxB];
+    HIP_TRY(hipMemcpyAsync(hst, k.S.st, (3 * (size_t)Bn + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hb, k.beta, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf, k.S.fnorm, Bn * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     mg_status ret = MG_OK;
     for (int b = 0; b < Bn; ++b) {
@@ -1471,6 +1473,40 @@ struct mg_ctx {
   std::unique_ptr<EngineBase> e;
 };
 
+namespace {
+
+// Krylov workspace of the allocation-free entry point mg_fgmres_static: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes `scratch` itself to a kernel or a copy (in host code
+// the name is only a stand-in for the symbol): it uses the device address
+// that hipGetSymbolAddress returns for the current device, taken once per
+// device at the library's set-up (mg_setup) or on the entry point's first call
+// on a device.
+constexpr size_t kStaticScratchBytes = (size_t)MG_FGMRES_STATIC_MAX_BYTES;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch`
+mg_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MG_ERR_HIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MG_OK;
+}
+
+}  // namespace
+
 static EngineBase* make_engine(int prec) {
   switch (prec) {
     case MG_FP64: return new Engine<double, double, double>();
@@ -1507,6 +1543,13 @@ mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* 
   if (ws && ws_bytes < need)
     return fail(MG_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
   MG_TRY(e->setup(ws, static_cast<hipStream_t>(stream)));
+  // once per device: the static scratch's address on this device (mg_fgmres_static retries on
+  // its first call if this fails; no other entry point needs it)
+  void* sp = nullptr;
+  if (scratch_address(&sp) != MG_OK) {
+    (void)hipGetLastError();
+    g_err.clear();
+  }
   mg_ctx* c = new mg_ctx;
   c->e = std::move(e);
   *out = c;
@@ -1596,6 +1639,20 @@ mg_status mg_fgmres(mg_ctx* c, const double* f, double* u, const mg_krylov_optio
   if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
   MG_TRY(check_krylov(o));
   return c->e->fgmres(f, u, o, work, work_bytes, info, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_fgmres_static(mg_ctx* c, const double* f, double* u, const mg_krylov_options* o, mg_rhs_info* info,
+                           void* stream) {
+  g_err.clear();
+  if (!c || !f || !u) return fail(MG_ERR_INVALID_ARG, "null argument");
+  MG_TRY(check_krylov(o));
+  const size_t need = c->e->fgmres_bytes(o->restart);
+  if (need > kStaticScratchBytes)
+    return fail(MG_ERR_OOM, "Krylov workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                                std::to_string(kStaticScratchBytes) + " bytes");
+  void* sp = nullptr;
+  MG_TRY(scratch_address(&sp));
+  return c->e->fgmres(f, u, o, sp, kStaticScratchBytes, info, static_cast<hipStream_t>(stream));
 }
 
 mg_status mg_level_info(const mg_ctx* c, int64_t* n, int32_t* wA) {
