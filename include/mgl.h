@@ -119,7 +119,10 @@ typedef struct {
 enum {
     MG_FLAG_BACKWARD = 1,   /* reserve buffers for mg_*_backward */
     MG_FLAG_NO_TAIL = 2,    /* never run the coarse levels as one LDS-resident kernel */
-    MG_FLAG_NO_TILES = 4    /* never run a K-hop convolution as one fused LDS-tile kernel */
+    MG_FLAG_NO_TILES = 4,   /* never run a K-hop convolution as one fused LDS-tile kernel */
+    MG_FLAG_NO_COMPACT = 8  /* mg_solve: keep cycling all nrhs columns (by default, at its periodic
+                               checks the solver narrows the cycle to the columns still iterating,
+                               rounded up to 16; a column's arithmetic and result do not change) */
 };
 
 typedef struct {

@@ -24,6 +24,7 @@ AGGREGATIONS = {"mean": 0, "weighted": 1, "sym": 2}
 FLAG_BACKWARD = 1
 FLAG_NO_TAIL = 2
 FLAG_NO_TILES = 4
+FLAG_NO_COMPACT = 8
 
 EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle",
             "mg_vcycle_backward", "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward",
@@ -230,12 +231,13 @@ class Context:
     normalisation), the graph operator of the convolutions.
     tail / tiles: allow the LDS-resident coarse tail / the fused K-hop
     convolution over LDS tiles (FP32/BF16 cycles with nrhs a multiple of 16).
+    compact: let solve() narrow the cycle to the columns still iterating.
     """
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
                  backward=False, device=None, stream=None, workspace=True, tail=True, native=None,
-                 basis="monomial", aggregation="mean", tiles=True):
+                 basis="monomial", aggregation="mean", tiles=True, compact=True):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -265,7 +267,7 @@ class Context:
                           BASES[basis], AGGREGATIONS[aggregation])
         self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
                            (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL) |
-                           (0 if tiles else FLAG_NO_TILES))
+                           (0 if tiles else FLAG_NO_TILES) | (0 if compact else FLAG_NO_COMPACT))
         ws, ck = C.c_size_t(), C.c_size_t()
         _check(self.lib.mg_workspace_bytes(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
                                            C.byref(ws), C.byref(ck)), "mg_workspace_bytes")

@@ -189,6 +189,46 @@ __device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ c
   }
 }
 
+// As ell_dot on the iterate v = u + e of one column (u: that column's entries
+// at stride su, e: at stride se), each neighbour's sum formed in FP64 as it is
+// read (the FP64 outer residual of the solver's fused update).
+template <bool WIDE, bool CONSEC, int NR, class TE>
+__device__ __forceinline__ void ell_dot_upd(int W, int ld, const int* __restrict__ col,
+                                            const double* __restrict__ val, const int (&row)[NR], int row0,
+                                            const double* __restrict__ u, int su, const TE* __restrict__ e, int se,
+                                            double (&s)[NR]) {
+  for (int k = 0; k < W; k += 4) {
+    int j[NR][4];
+    double v[NR][4];
+    if constexpr (CONSEC && NR == 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const V4<int> jj = ld4(col + (size_t)(k + q) * ld + row0);
+        const V4<double> vv = ld4(val + (size_t)(k + q) * ld + row0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          j[r][q] = uni<WIDE>(jj.v[r]);
+          v[r][q] = uni<WIDE>(vv.v[r]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const size_t o = (size_t)(k + q) * ld + row[r];
+          j[r][q] = uni<WIDE>(col[o]);
+          v[r][q] = uni<WIDE>(val[o]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        s[r] += v[r][q] * (u[(size_t)j[r][q] * su] + (double)e[(size_t)j[r][q] * se]);
+  }
+}
+
 // Neighbour sums over the graph (W multiple of 4, padding col == row):
 //   TRANS = false: s[r] += sum_{j in N(row)} [w_{row,j}] y_j         ((G y) = r_row * s)
 //   TRANS = true:  s[r] += sum_{j in N(row)} [w_{row,j}] r_j y_j     ((G^T y) = s, symmetric
@@ -198,6 +238,7 @@ __device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ c
 template <bool WIDE, bool CONSEC, int NR, bool TRANS, bool WG, class C, class TY>
 __device__ __forceinline__ void graph_sum(const Lvl<C>& L, const int (&row)[NR], int row0, const TY* __restrict__ y,
                                           int B, int b, C (&s)[NR]) {
+#pragma clang fp contract(off)
   for (int k = 0; k < L.wg; k += 4) {
     int j[NR][4];
     C ew[NR][4];
@@ -296,6 +337,24 @@ __global__ __launch_bounds__(256) void k_resid(Lvl<C> L, int B, int lbs, const T
   }
 }
 
+// Arithmetic of one Horner hop at one node and column, with the roundings
+// fixed (no contraction left to the compiler), so that the per-hop sweeps
+// and the fused tile kernel give the same bits:
+//   hop_value:  v = fma(c, x, a * (r * s))     (s the neighbour sum, r the row scale)
+//   hop_value1: the same with a == 1 (a * t == t exactly, so the product is skipped)
+//   hop_update: u + scale * v = fma(scale, v, u)
+__device__ __forceinline__ float hop_value(float a, float r, float s, float c, float x) {
+  return __builtin_fmaf(c, x, __fmul_rn(a, __fmul_rn(r, s)));
+}
+__device__ __forceinline__ double hop_value(double a, double r, double s, double c, double x) {
+  return __builtin_fma(c, x, __dmul_rn(a, __dmul_rn(r, s)));
+}
+__device__ __forceinline__ float hop_value1(float r, float s, float c, float x) {
+  return __builtin_fmaf(c, x, __fmul_rn(r, s));
+}
+__device__ __forceinline__ float hop_update(float u, float scale, float v) { return __builtin_fmaf(scale, v, u); }
+__device__ __forceinline__ double hop_update(double u, double scale, double v) { return __builtin_fma(scale, v, u); }
+
 // Horner hop v = a * (M yin)_i + c * x_i.
 //   mode 0: out = v (type TO)
 //   mode 1: out = (oz ? 0 : out) + scale * v
@@ -321,8 +380,8 @@ __global__ __launch_bounds__(256) void k_hop(Lvl<C> L, int B, int lbs, const TY*
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (!t.ok[r]) continue;
-      const C v = a * (idg[r] * s[r]) + c * xv[r];
-      put(out + (size_t)t.row[r] * B + b, mode == 0 ? v : ov[r] + scale * v);
+      const C v = hop_value(a, idg[r], s[r], c, xv[r]);
+      put(out + (size_t)t.row[r] * B + b, mode == 0 ? v : hop_update(ov[r], scale, v));
     }
   }
 }
@@ -406,10 +465,13 @@ __device__ __forceinline__ void st4v(bf16_t* p, const float (&v)[4]) {
 }
 
 // s += sum over the graph slots of local row r of [w] y_j; columns from LDS,
-// y in LDS, weights (WG) from the tile's slot array in global memory
+// y in LDS, weights (WG) from the tile's slot array in global memory.  A
+// padding slot holds the row's own index and adds +0, as in the per-hop sweep;
+// weighted terms are rounded before they are added (no fused multiply-add).
 template <bool WG>
 __device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const float* __restrict__ gw, int r,
                                             const float4* y, int q, float (&s)[4]) {
+#pragma clang fp contract(off)
   for (int k = 0; k < wg; k += 4) {
     const ushort4 jj = *reinterpret_cast<const ushort4*>(lc + k);
     const int j[4] = {jj.x, jj.y, jj.z, jj.w};
@@ -551,11 +613,13 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
     if (itnn < i1) head(itnn, hn);
     const int* cn = T.cnt + (size_t)h.t * (KM + 1);
     const float* gw = WG ? T.lgw + h.m0 : nullptr;
-    // hops 1 .. K-1 on the nodes at distance <= K - hop
+    // hops 1 .. K-1 on the nodes at distance <= K - hop; the first applies c_K, the
+    // others continue Horner's rule with factor 1 (hop_value, a == 1 exactly)
     const float4* yin = S;
     for (int hp = 1; hp < K; ++hp) {
       const int rows = cn[K - hp];
       const float a = hp == 1 ? cf.c[K] : 1.f;
+      const bool scaled = hp == 1;
       const float cc = cf.c[K - hp];
       float4* yo = conv_smem + ((hp & 1) ? lo.y0 : lo.y1);
       for (int r = p0; r < rows; r += kTileNp) {
@@ -566,14 +630,13 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
         float o[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[c] = a * (idg * s[c]) + cc * xs[c];
+        for (int c = 0; c < 4; ++c) o[c] = scaled ? hop_value(a, idg, s[c], cc, xs[c]) : hop_value1(idg, s[c], cc, xs[c]);
         yo[r * kTileQ + q] = make_float4(o[0], o[1], o[2], o[3]);
       }
       __syncthreads();
       yin = yo;
     }
-    // last hop on the own nodes, fused with the output update
-    const float a = K == 1 ? cf.c[1] : 1.f;
+    // last hop on the own nodes, fused with the output update (factor 1: K >= 2)
     const float c0 = cf.c[0];
     const int col = h.g * kTileCols + q * 4;
 #pragma unroll
@@ -588,8 +651,8 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
         float v[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const float w = a * (idg * s[c]) + c0 * xs[c];
-          v[c] = mode == 0 ? w : ov[e][c] + scale * w;
+          const float w = hop_value1(idg, s[c], c0, xs[c]);
+          v[c] = mode == 0 ? w : hop_update(ov[e][c], scale, w);
         }
         st4v(out + (size_t)h.nd[e] * B + col, v);
       }
@@ -670,7 +733,7 @@ __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, in
         for (int q = 0; q < 4; ++q) xv[q] = ldc<C>(x + (size_t)jr[q] * B + b);
         graph_sum<WIDE, false, 4, false, WG>(L, jr, 0, y, B, b, sm);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = a * (uni<WIDE>(L.invdeg[jr[q]]) * sm[q]) + c * xv[q];
+        for (int q = 0; q < 4; ++q) v[q] = hop_value(a, uni<WIDE>(L.invdeg[jr[q]]), sm[q], c, xv[q]);
       } else {
         C fv[4], sa[4];
 #pragma unroll
@@ -816,11 +879,19 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* W, int* in
 // Block b (XCD-remapped) owns the contiguous rows [b*chunk, (b+1)*chunk) and
 // walks them four rows per work-item at a time, so neighbour rows are reused
 // from L2; the summation order is fixed (deterministic).  B <= 256.
-template <bool WIDE, class TR>
+//
+// UPD (the solver's update fused into the next residual): the iterate is
+// v = u + e in the columns with act[b] != 0 and v = u in the others, formed on
+// the fly for the row and its neighbours (the same FP64 sum for every
+// reader, so the same bits as storing it first); v is written to uo (which
+// must not alias u: neighbours still read u) and the residual is f - A v.
+template <bool WIDE, bool UPD, class TR, class TE>
 __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, int chunk,
                                                      const double* __restrict__ f, const double* __restrict__ u,
                                                      double* __restrict__ r64, TR* __restrict__ rc,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, const TE* __restrict__ e,
+                                                     const int* __restrict__ act, double* __restrict__ uo, int Bc,
+                                                     const int* __restrict__ cmap) {
   __shared__ double red[256 * 4];
   const int LB = 1 << lbs, rpb = 256 >> lbs;
   const int lane = threadIdx.x & (LB - 1), rg = uni<WIDE>((int)(threadIdx.x >> lbs));
@@ -844,22 +915,30 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
     row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
+      // UPD: a stopped column is not touched (its iterate stays where it was last written)
+      if (UPD && act[b] == 0) continue;
+      // the cycle-type vectors (rc, e) may hold only the columns still iterating: column b
+      // at slot cmap[b] of Bc
+      const int sb = cmap ? cmap[b] : b;
       // own f and u loaded first, consumed after the off-diagonal gathers
       double fv[4], uv[4], s[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         fv[r] = f[(size_t)row[r] * B + b];
         uv[r] = u[(size_t)row[r] * B + b];
+        if constexpr (UPD) uv[r] += (double)e[(size_t)row[r] * Bc + sb];
         s[r] = 0.0;
       }
-      ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
+      if constexpr (UPD) ell_dot_upd<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u + b, B, e + sb, Bc, s);
+      else ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (!ok[r]) continue;
         const size_t o = (size_t)row[r] * B + b;
         const double v = fv[r] - (s[r] + dg[r] * uv[r]);
+        if constexpr (UPD) uo[o] = uv[r];
         if (r64) r64[o] = v;
-        if (rc) put(rc + o, v);
+        if (rc) put(rc + (size_t)row[r] * Bc + sb, v);
         acc[q] += v * v;
       }
     }
@@ -879,9 +958,10 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
 // norms[b] = sqrt(sum over blocks of part[block][b]); one block per column,
 // fixed strided order and fixed tree (deterministic).
 __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nblk, int B,
-                                                    double* __restrict__ norms) {
+                                                    double* __restrict__ norms, const int* __restrict__ act) {
   __shared__ double red[256];
   const int b = blockIdx.x;
+  if (act && act[b] == 0) return;   // a stopped column keeps its last norm
   double s = 0.0;
   for (int g = threadIdx.x; g < nblk; g += 256) s += part[(size_t)g * B + b];
   red[threadIdx.x] = s;
@@ -1041,6 +1121,28 @@ __global__ __launch_bounds__(256) void k_update(int n, int B, int lbs, const TU*
   }
 }
 
+// dst[i][s] = src[i][from[s]] (0 where from[s] < 0): columns of an [n][Bo]
+// array gathered into an [n][Bn] one (the solver's active-column compaction)
+template <class T>
+__global__ __launch_bounds__(256) void k_repack(int n, int Bo, int Bn, const int* __restrict__ from,
+                                                const T* __restrict__ src, T* __restrict__ dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * Bn) return;
+  const long i = t / Bn;
+  const int c = (int)(t - i * Bn);
+  const int k = from[c];
+  dst[t] = k >= 0 ? src[i * Bo + k] : T(0);
+}
+
+// u[i][b] = w[i][b] for the columns whose update count iters[b] is odd (the
+// solver alternates the iterate between u and w, one buffer per update)
+__global__ __launch_bounds__(256) void k_copy_odd(int n, int B, int lbs, const int* __restrict__ iters,
+                                                  const double* __restrict__ w, double* __restrict__ u) {
+  MGL_ROW_LANE(n)
+  for (int b = lane; b < B; b += (1 << lbs))
+    if (iters[b] & 1) u[(size_t)i * B + b] = w[(size_t)i * B + b];
+}
+
 template <class TI, class TO>
 __global__ __launch_bounds__(256) void k_copy(long cnt, const TI* __restrict__ in, TO* __restrict__ out) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1185,8 +1287,8 @@ __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const
         if constexpr (WG) v *= rc.gw[k];
         if (rc.gc[k] != i) sm += v;
       }
-      const C v = a * (rc.idg * sm) + cc * x[e];
-      out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
+      const C v = hop_value(a, rc.idg, sm, cc, x[e]);
+      out[e] = mode == 0 ? v : hop_update(oz ? C(0) : out[e], scale, v);
     }
     __syncthreads();
     return;
@@ -1218,8 +1320,8 @@ __device__ __forceinline__ void tl_hop(const Lvl<C>& L, const C* yin, C a, const
         if (j != i) sm += v;
       }
     }
-    const C v = a * (L.invdeg[i] * sm) + cc * x[e];
-    out[e] = mode == 0 ? v : (oz ? C(0) : out[e]) + scale * v;
+    const C v = hop_value(a, L.invdeg[i], sm, cc, x[e]);
+    out[e] = mode == 0 ? v : hop_update(oz ? C(0) : out[e], scale, v);
   }
   __syncthreads();
 }

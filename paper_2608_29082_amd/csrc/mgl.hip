@@ -205,6 +205,7 @@ struct Engine final : EngineBase {
     TileLds tlo[kTileMaxK + 1] = {};  // LDS layout of a fused convolution of order K
     size_t tlds[kTileMaxK + 1] = {};  // and its size in bytes
     unsigned tgrid[kTileMaxK + 1] = {};  // persistent grid (a multiple of 8 blocks)
+    int tocc[kTileMaxK + 1] = {};        // resident workgroups per compute unit
   };
   std::vector<DL> d;
   Lvl<double> L64{};                // level-0 operator in FP64 (outer residual)
@@ -233,7 +234,16 @@ struct Engine final : EngineBase {
   std::vector<size_t> tail_bytes;
   char* wsbase = nullptr;
   bool owns_ws = false;
-  int lbs = 0;
+  int lbs = 0;                      // lanes per row (log2) of the cycle's sweeps at the current width
+  int lbsF = 0;                     // the same at the full width (outer residual, solver bookkeeping)
+  int curB = 0;                     // columns the cycle runs on: nrhs, or fewer while compacted
+  int ncu = 0;                      // compute units of the device
+  // active-column compaction of mg_solve: column b's cycle data at slot cmap[b] of curB
+  int* cmap = nullptr;              // device [nrhs]
+  int* cfrom = nullptr;             // device [nrhs]: old slot of each new slot (repack)
+  int* hmap = nullptr;              // pinned host [3 nrhs]: flags, new map, repack sources
+  std::vector<int> hcur;            // host copy of cmap
+  bool compacted = false;
   // device-side host copies kept alive during setup
   std::vector<uvector<char>> staging;
 
@@ -242,6 +252,7 @@ struct Engine final : EngineBase {
     if (kr_own) (void)hipFree(kr_own);
     if (tile_mem) (void)hipFree(tile_mem);
     if (hcount) (void)hipHostFree(hcount);
+    if (hmap) (void)hipHostFree(hmap);
   }
 
   bool bwd() const { return (pl.flags & MG_FLAG_BACKWARD) != 0; }
@@ -271,24 +282,52 @@ struct Engine final : EngineBase {
     for (int j = 0; j < pl.nu_pre; ++j) add(0, pl.KB);
   }
 
+  // launch shapes of level l's row sweeps at the current cycle width
+  void level_launch(int l) {
+    DL& x = d[l];
+    const int n = pl.lv[l].n;
+    x.blocks = nblocks((long)n << lbs);
+    const long rpb = 256 >> lbs;
+    const long b4 = (n + 4 * rpb - 1) / (4 * rpb);
+    x.rows4 = b4 >= 512 ? 1 : 0;   // 2048 was 0.7 % slower on the 513 workload
+    x.rblocks = (unsigned)(x.rows4 ? b4 : (n + rpb - 1) / rpb);
+  }
+  // persistent grid of level l's fused convolution of order K: the resident workgroups of
+  // every XCD, or fewer when there are fewer (tile, column group) items
+  void tile_grid(int l, int K) {
+    DL& x = d[l];
+    const long W = (long)x.td.ntiles * x.td.ngroups;
+    const long per = std::min<long>((W + 7) / 8, (long)std::max(1, ncu / 8) * x.tocc[K]);
+    x.tgrid[K] = (unsigned)(8 * std::max<long>(per, 1));
+  }
+  // run the cycle on Bc columns (Bc <= nrhs): every row sweep's lanes and blocks, and the
+  // fused convolution's column groups and grid
+  void set_width(int Bc) {
+    curB = Bc;
+    lbs = lb_shift(Bc);
+    for (int l = 0; l < pl.J; ++l) {
+      level_launch(l);
+      if (d[l].td.ntiles) {
+        d[l].td.ngroups = Bc / kTileCols;
+        for (int K = 2; K <= d[l].td.KM; ++K) tile_grid(l, K);
+      }
+    }
+  }
+
   // assign device pointers (base == nullptr: sizes only)
   size_t carve(char* base) {
     Bump bp;
     bp.base = base;
     const int J = pl.J, B = pl.B;
     d.assign(J, DL{});
-    lbs = lb_shift(B);
+    lbs = lbsF = lb_shift(B);
+    curB = B;
+    compacted = false;
     for (int l = 0; l < J; ++l) {
       const HLevel& H = pl.lv[l];
       DL& x = d[l];
       const int n = H.n;
-      x.blocks = nblocks((long)n << lbs);
-      {
-        const long rpb = 256 >> lbs;
-        const long b4 = (n + 4 * rpb - 1) / (4 * rpb);
-        x.rows4 = b4 >= 512 ? 1 : 0;   // 2048 was 0.7 % slower on the 513 workload
-        x.rblocks = (unsigned)(x.rows4 ? b4 : (n + rpb - 1) / rpb);
-      }
+      level_launch(l);
       const int ld = round_up(n, 4);
       x.L.n = n;
       x.L.ld = ld;
@@ -355,6 +394,8 @@ struct Engine final : EngineBase {
     lalpha = bp.take<double>(B);
     lbeta = bp.take<double>(B);
     dstat = bp.take<int>(3 * B + 1);
+    cmap = bp.take<int>(B);
+    cfrom = bp.take<int>(B);
     dprm = bp.take<double>(pl.params.size());
     if (bwd()) {
       h_off.clear(); h_cnt.clear(); h_desc.clear();
@@ -423,6 +464,7 @@ struct Engine final : EngineBase {
     }
     carve(wsbase);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&hcount), sizeof(int) * 4, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&hmap), sizeof(int) * 3 * pl.B, hipHostMallocDefault));
     const int J = pl.J;
     for (int l = 0; l < J; ++l) {
       const HLevel& H = pl.lv[l];
@@ -666,12 +708,11 @@ struct Engine final : EngineBase {
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)maxlds));
     // persistent grid: resident workgroups per XCD (the instances share one
     // register and LDS footprint up to the weights; take the smallest)
-    int dev = 0, ncu = 0;
+    int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     for (int l = 0; l < pl.J; ++l) {
       if (!d[l].td.ntiles) continue;
-      const long W = (long)d[l].td.ntiles * d[l].td.ngroups;
       for (int K = 2; K <= d[l].td.KM; ++K) {
         int occ = 1 << 30;
         for (const void* fn : fns) {
@@ -680,8 +721,8 @@ struct Engine final : EngineBase {
           occ = std::min(occ, nb);
         }
         if (occ < 1) return fail(MG_ERR_STATE, "fused convolution does not fit one compute unit");
-        const long per = std::min<long>((W + 7) / 8, (long)std::max(1, ncu / 8) * occ);
-        d[l].tgrid[K] = (unsigned)(8 * per);
+        d[l].tocc[K] = occ;
+        tile_grid(l, K);
       }
     }
     HIP_TRY(hipStreamSynchronize(st));   // the host lists are freed on return
@@ -742,7 +783,8 @@ struct Engine final : EngineBase {
   }
 
   // ---------------------------------------------------------------- forward building blocks
-  int B() const { return pl.B; }
+  int B() const { return curB; }     // columns of the cycle's vectors
+  int BF() const { return pl.B; }    // columns of the solver-level (FP64) vectors
 
   template <class TY, class TX, class TO>
   mg_status hop(int l, const TY* yin, double a, const TX* x, double c, TO* out, int mode, double scale, int oz,
@@ -912,7 +954,7 @@ struct Engine final : EngineBase {
   // outer residual: contiguous row chunks (a multiple of 4 rows), at most kOuterBlocks blocks
   int outer_chunk() const {
     const long n = pl.lv[0].n;
-    const long rows_per_pass = 4L * (256 >> lbs);
+    const long rows_per_pass = 4L * (256 >> lbsF);
     long chunk = std::max<long>(rows_per_pass, (n + kOuterBlocks - 1) / kOuterBlocks);
     chunk = (chunk + 3) / 4 * 4;
     return (int)chunk;
@@ -922,23 +964,87 @@ struct Engine final : EngineBase {
     return (unsigned)((pl.lv[0].n + c - 1) / c);
   }
 
+  // r = f - A u (FP64, all nrhs columns) with per-column norms; rc receives fl_p(r).  With e
+  // (the solver's fused update): the iterate is u + e in the active columns, written to uo
+  // (!= u), and stopped columns are not touched.  While the cycle runs compacted, rc and e
+  // hold column b at slot cmap[b] of the current width.
   template <class TR>
-  mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st) {
+  mg_status outer_resid(const double* f, const double* u, double* r64, TR* rc, double* nrm, hipStream_t st,
+                        const TU* e = nullptr, const int* act = nullptr, double* uo = nullptr) {
     const int l = 0;   // timing level of the finest-level outer residual
     const unsigned g = outer_blocks();
-    const double nb0 = (double)L64.n * B();
+    const int Bc = (e && compacted) ? B() : BF();
+    const int* map = (e && compacted) ? cmap : nullptr;
+    const double nb0 = (double)L64.n * BF();
     const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
-                      (rc ? nb0 * sizeof(TR) : 0.0);
-    TIMED(MG_KF_OUTER, ob,
-          if (lbs == 6) hipLaunchKernelGGL((k_outer_resid<true, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs,
-                                           outer_chunk(), f, u, r64, rc, part);
-          else hipLaunchKernelGGL((k_outer_resid<false, TR>), dim3(g), dim3(256), 0, st, L64, B(), lbs, outer_chunk(),
-                                  f, u, r64, rc, part));
+                      (rc ? nb0 * sizeof(TR) : 0.0) + (e ? nb0 * (sizeof(TU) + 8) : 0.0);
+    if (e) {
+      TIMED(MG_KF_OUTER, ob,
+            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, true, TR, TU>), dim3(g), dim3(256), 0, st, L64,
+                                              BF(), lbsF, outer_chunk(), f, u, r64, rc, part, e, act, uo, Bc, map);
+            else hipLaunchKernelGGL((k_outer_resid<false, true, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
+                                    lbsF, outer_chunk(), f, u, r64, rc, part, e, act, uo, Bc, map));
+    } else {
+      TIMED(MG_KF_OUTER, ob,
+            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, false, TR, TU>), dim3(g), dim3(256), 0, st, L64,
+                                              BF(), lbsF, outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr,
+                                              (const int*)nullptr, (double*)nullptr, Bc, map);
+            else hipLaunchKernelGGL((k_outer_resid<false, false, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
+                                    lbsF, outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr, (const int*)nullptr,
+                                    (double*)nullptr, Bc, map));
+    }
     if (nrm) {
-      hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), nrm);
+      hipLaunchKernelGGL(k_norm_final, dim3(BF()), dim3(256), 0, st, part, (int)g, BF(), nrm, e ? act : nullptr);
       LAUNCH_OK();
     }
     return MG_OK;
+  }
+
+  // Compact the cycle to the columns still iterating (act flags on the device), rounded up to
+  // a multiple of kTileCols columns: a new column map, the pending cycle input r0 gathered
+  // into the new layout, and the narrower launch shapes.  Every kernel treats the columns
+  // independently, so a column's arithmetic does not change.
+  mg_status compact(int active, hipStream_t st) {
+    const int Bn = round_up(std::max(active, 1), kTileCols);
+    if (Bn >= B()) return MG_OK;
+    const int F = BF();
+    int* hact = hmap;
+    int* hnew = hmap + F;
+    int* hfrom = hmap + 2 * F;
+    HIP_TRY(hipMemcpyAsync(hact, st_ptr(), F * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hcur.empty()) {
+      hcur.resize(F);
+      for (int b = 0; b < F; ++b) hcur[b] = b;
+    }
+    int slot = 0;
+    for (int c = 0; c < Bn; ++c) hfrom[c] = -1;
+    for (int b = 0; b < F; ++b) {
+      if (hact[b] && slot < Bn) {
+        hnew[b] = slot;
+        hfrom[slot] = hcur[b];
+        ++slot;
+      } else {
+        hnew[b] = -1;
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(cfrom, hfrom, Bn * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(cmap, hnew, F * sizeof(int), hipMemcpyHostToDevice, st));
+    const long cnt = (long)pl.lv[0].n * Bn;
+    hipLaunchKernelGGL((k_repack<TU>), dim3(nblocks(cnt)), dim3(256), 0, st, pl.lv[0].n, B(), Bn, (const int*)cfrom,
+                       (const TU*)r0, e0);
+    LAUNCH_OK();
+    std::swap(r0, e0);
+    for (int b = 0; b < F; ++b) hcur[b] = hnew[b];
+    compacted = true;
+    set_width(Bn);
+    return MG_OK;
+  }
+  void uncompact() {
+    if (!compacted) return;
+    compacted = false;
+    hcur.clear();
+    set_width(BF());
   }
 
   mg_status residual(const double* f, const double* u, double* r, double* nrm, hipStream_t st) override {
@@ -959,7 +1065,7 @@ struct Engine final : EngineBase {
     if (lbs == 6) hipLaunchKernelGGL((k_colsq<true>), dim3(g), dim3(256), 0, st, n0, B(), lbs, outer_chunk(), f, part);
     else hipLaunchKernelGGL((k_colsq<false>), dim3(g), dim3(256), 0, st, n0, B(), lbs, outer_chunk(), f, part);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), fnorm);
+    hipLaunchKernelGGL(k_norm_final, dim3(B()), dim3(256), 0, st, part, (int)g, B(), fnorm, (const int*)nullptr);
     LAUNCH_OK();
     hipLaunchKernelGGL(k_loss_coef, dim3(1), dim3(256), 0, st, (const double*)norms, (const double*)fnorm, B(), kind,
                        gseed, lalpha, lbeta, loss);
@@ -1000,44 +1106,57 @@ struct Engine final : EngineBase {
   mg_status solve(const double* f, double* u, mg_rhs_info* info, hipStream_t st) override {
     const int n0 = pl.lv[0].n;
     // ||f|| per column: residual of u = 0 is f itself
-    hipLaunchKernelGGL((k_fill0<double>), dim3(nblocks((long)n0 * B())), dim3(256), 0, st, (long)n0 * B(), dbuf);
+    hipLaunchKernelGGL((k_fill0<double>), dim3(nblocks((long)n0 * BF())), dim3(256), 0, st, (long)n0 * BF(), dbuf);
     LAUNCH_OK();
     MG_TRY(outer_resid<TU>(f, dbuf, nullptr, (TU*)nullptr, fnorm, st));
+    // iterate m of a column that is still updating lives in ua = (m even ? u : dbuf); each
+    // update u + e is written to the other buffer by the next residual sweep (fused)
+    MG_TRY(outer_resid<TU>(f, u, nullptr, r0, norms, st));
+    double* ua = u;
+    double* ub = dbuf;
+    struct Restore {   // the cycle is back at full width however the loop ends
+      Engine* e;
+      ~Restore() { e->uncompact(); }
+    } restore{this};
     int m = 0;
     for (; m < pl.max_outer; ++m) {
-      MG_TRY(outer_resid<TU>(f, u, nullptr, r0, norms, st));
-      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf,
+      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), BF(), pl.rtol, pl.divf,
                          m == 0 ? 1 : 0);
       LAUNCH_OK();
       if ((m + 1) % pl.check_every == 0 || m == 0) {
-        HIP_TRY(hipMemcpyAsync(hcount, st_ptr() + 3 * B(), sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hcount, st_ptr() + 3 * BF(), sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (hcount[0] == 0) break;
+        if (!(pl.flags & MG_FLAG_NO_COMPACT)) MG_TRY(compact(hcount[0], st));
       }
       MG_TRY(fwd(0, r0, e0, 1, nullptr, st));
-      hipLaunchKernelGGL((k_update<TU>), dim3(d[0].blocks), dim3(256), 0, st, n0, B(), lbs, (const TU*)e0, u,
-                         (const int*)st_ptr(), 1.0);
-      LAUNCH_OK();
+      MG_TRY(outer_resid<TU>(f, ua, nullptr, r0, norms, st, e0, st_ptr(), ub));
+      std::swap(ua, ub);
     }
+    uncompact();
+    // columns that ended after an odd number of updates hold their iterate in dbuf (the update
+    // counts are the solver's per-column counts before the cap's final check below)
+    hipLaunchKernelGGL(k_copy_odd, dim3(d[0].blocks), dim3(256), 0, st, n0, BF(), lbsF, (const int*)(st_ptr() + BF()),
+                       (const double*)dbuf, u);
+    LAUNCH_OK();
     if (m == pl.max_outer) {
-      // account for the last iterate
-      MG_TRY(outer_resid<TU>(f, u, nullptr, (TU*)nullptr, norms, st));
-      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), B(), pl.rtol, pl.divf, 0);
+      // the last iterate's residual is in norms: account for it
+      hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(256), 0, st, norms, fnorm, init, st_ptr(), BF(), pl.rtol, pl.divf, 0);
       LAUNCH_OK();
     }
-    std::vector<int> hst(3 * B() + 1);
-    std::vector<double> hn(B()), hf(B());
+    std::vector<int> hst(3 * BF() + 1);
+    std::vector<double> hn(BF()), hf(BF());
     HIP_TRY(hipMemcpyAsync(hst.data(), st_ptr(), hst.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hn.data(), norms, B() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hf.data(), fnorm, B() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hn.data(), norms, BF() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf.data(), fnorm, BF() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     mg_status ret = MG_OK;
-    for (int b = 0; b < B(); ++b) {
+    for (int b = 0; b < BF(); ++b) {
       // iters counted for columns still active after a check: they were updated
       // only if a cycle followed; a column active at the end ran every cycle
-      int it = hst[B() + b];
+      int it = hst[BF() + b];
       if (hst[b]) it = std::min(it, m);
-      const int s = hst[2 * B() + b];
+      const int s = hst[2 * BF() + b];
       if (info) {
         info[b].iters = it;
         info[b].status = s;

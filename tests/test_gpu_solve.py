@@ -86,3 +86,44 @@ def test_zero_rhs_converges_immediately():
     u = torch.zeros_like(f)
     info = ctx.solve(f, u)
     assert info.code == 0 and np.all(info.iters == 0)
+
+
+@pytest.mark.parametrize("precision,B,max_outer", [("fp32", 64, 4000), ("fp32", 64, 7), ("bf16", 48, 4000),
+                                                   ("fp64", 32, 4000)])
+def test_column_compaction_changes_nothing(precision, B, max_outer):
+    """mg_solve narrows the cycle to the columns still iterating at its periodic
+    checks (rounded up to 16) and fuses the update into the next FP64 residual
+    sweep, alternating the iterate between the caller's u and a scratch vector.
+    Against the same solve without compaction: the same iteration counts,
+    statuses and residuals, and every element of u the same bits.  A third of
+    the columns have f = 0 (stopped at the first check: compaction at once);
+    the others are spread by scaling; max_outer = 7 ends at the cap with
+    columns still iterating (odd update count: the iterate is copied back)."""
+    import torch
+    w = C.block_diffusion(2, 129, -2, 2, B=B, K=3)
+    f = w.f.copy()
+    f[:, : B // 3] = 0.0
+    f[:, B // 3:] *= np.linspace(1e-3, 1e3, B - B // 3)[None, :]
+    out = []
+    for compact in (True, False):
+        ctx = ctx_for(w.hier, w.params, 3, B, precision, max_outer=max_outer, check_every=3, compact=compact)
+        fd = to_dev(f, torch.float64)
+        u = torch.zeros_like(fd)
+        info = ctx.solve(fd, u)
+        out.append((info, to_np(u)))
+        ctx.close()
+    (i1, u1), (i2, u2) = out
+    print(f"{precision} B={B} cap={max_outer}: code {i1.code}/{i2.code}, iters {sorted(set(i1.iters.tolist()))}",
+          flush=True)
+    assert i1.code == i2.code
+    assert np.array_equal(i1.iters, i2.iters) and np.array_equal(i1.status, i2.status)
+    assert np.array_equal(i1.relres, i2.relres)
+    assert np.array_equal(u1, u2)
+    assert np.all(u1[:, : B // 3] == 0.0)
+    if max_outer > 100:
+        assert i1.code == 0
+        relres = np.linalg.norm(f[:, B // 3:] - w.hier.A[0] @ u1[:, B // 3:], axis=0) / np.linalg.norm(
+            f[:, B // 3:], axis=0)
+        assert np.all(relres <= 1e-8)
+    else:
+        assert i1.code == 5 and np.all(i1.iters[B // 3:] == max_outer)
