@@ -6,6 +6,7 @@ import scipy.sparse.linalg as spla
 
 from mginputs import configs as C
 from oracle import krylov as KR
+from oracle import mixed as MX
 from oracle import lmg as O
 from tests.gpu_util import ctx_for, oracle_levels, oracle_params, elem_rel, small_cases, to_dev, to_np
 
@@ -202,11 +203,16 @@ def test_fgmres_benchmark_configuration():
     assert info.code == 0 and rr.max() <= 1e-8 * (1 + 1e-6)
     assert info.iters.max() < 200
     # FMG on the benchmark hierarchy, two columns, against the oracle: exact
-    # in FP64; in FP32 nested iteration chains J - 1 cycles (one per level,
-    # each started from the previous level's FP32 result), so the bound is
-    # J - 1 times the one-cycle FP32 bound (2e-5)
+    # in FP64; in FP32 the bound comes from the oracle's float32 emulation of
+    # the same FMG (oracle/mixed.py): an FP32 execution whose operation order
+    # differs from the emulation's lands within a few times the emulation's
+    # own distance from the FP64 result
     f2 = np.ascontiguousarray(w.f[:, :2])
-    want = KR.fmg(oracle_levels(h), oracle_params(flat, J, 3), f2)
+    lv = oracle_levels(h)
+    prm = oracle_params(flat, J, 3)
+    want = KR.fmg(lv, prm, f2)
+    emu = MX.fmg32(MX.make_levels32(lv), prm, f2.astype(np.float32))
+    err_emu = elem_rel(emu.astype(np.float64), want)
     ctx64 = ctx_for(h, flat, 3, 2, "fp64")
     u64 = ctx64.empty()
     ctx64.fmg(to_dev(f2, torch.float64), u64)
@@ -215,6 +221,6 @@ def test_fgmres_benchmark_configuration():
     u = ctx2.empty()
     ctx2.fmg(to_dev(f2, torch.float32), u)
     err = elem_rel(to_np(u), want)
-    print(f"513 fmg fp64 rel {err64:.2e}, fp32 rel {err:.2e}", flush=True)
+    print(f"513 fmg fp64 rel {err64:.2e}, fp32 rel {err:.2e} (float32 emulation {err_emu:.2e})", flush=True)
     assert err64 <= 1e-12
-    assert err <= (J - 1) * 2e-5
+    assert 0.0 < err_emu and err <= 4.0 * err_emu
