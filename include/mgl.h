@@ -82,6 +82,17 @@ typedef struct {
     const mg_csr* R;         /* [J-1] restrictions n_{l+1} x n_l, or NULL for R_l = P_l^T */
     const mg_csr* G;         /* [J] graph patterns (diagonal ignored), or NULL for the
                                 off-diagonal nonzero pattern of A_l */
+    int32_t ncolumn_values;  /* 0: every column solves with A_l's values.  nrhs: column b solves
+                                its own operators A_l^(b) on the pattern of A_l (a batch of
+                                requests of one grid: per-request values, shared pattern, graph,
+                                P and R; A_l's own values are then not read).  Every column's
+                                off-diagonal values on the pattern and its diagonal must be
+                                nonzero, so the graph (A_l's off-diagonal pattern) is the same as
+                                each column's own.  Mean aggregation only; no reverse sweep and no
+                                FGMRES in such a context (MG_ERR_UNSUPPORTED) */
+    const double* const* column_values;  /* [J * nrhs] when ncolumn_values > 0:
+                                column_values[l * nrhs + b] points at the nnz(A_l) values of
+                                A_l^(b) in the CSR order of A_l's pattern (may repeat pointers) */
 } mg_hierarchy;
 
 /* Learnable parameters Theta (paper Sec. 3, parameter set).  values is a host
@@ -166,6 +177,23 @@ mg_status mg_setup(const mg_hierarchy* h, const mg_params* p, const mg_options* 
 
 /* Replace Theta (same layout and orders as at setup).  Synchronises `stream`. */
 mg_status mg_set_params(mg_ctx* ctx, const double* values, void* stream);
+
+/* Per-column operator contexts (mg_hierarchy.ncolumn_values = nrhs): replace
+ * column b's operators A_l^(b) on every level, e.g. to start a new request in a
+ * column slot that a finished one left (continuous batching of requests of
+ * one grid).  values: host array [J] of pointers to nnz(A_l) doubles in the
+ * CSR order of the pattern given at setup, with the same rules as at setup
+ * (finite, nonzero on the pattern); the coarsest inverse is recomputed.  The
+ * other columns are not touched.  Synchronises `stream`; must not overlap a
+ * solve on the context.  MG_ERR_STATE for a context with shared operators,
+ * MG_ERR_SHAPE (context unchanged) for values off the rules or a singular
+ * coarsest operator. */
+mg_status mg_load_column(mg_ctx* ctx, int32_t b, const double* const* values, void* stream);
+
+/* Change mg_solve's options after setup (same meaning and limits as the
+ * mg_options fields). */
+mg_status mg_set_solver_options(mg_ctx* ctx, int32_t max_outer, int32_t check_every, double rtol,
+                                double diverge_factor);
 
 /* One learnable V-cycle on the finest level, in place:
  *     u <- LMG(A_0, f, u, Theta)                                 (Alg. 2)

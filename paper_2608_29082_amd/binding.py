@@ -30,7 +30,8 @@ EXPORTED = ["mg_num_params", "mg_workspace_bytes", "mg_setup", "mg_set_params", 
             "mg_vcycle_backward", "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward",
             "mg_solve", "mg_level_info", "mg_timing_start", "mg_timing_read", "mg_square_hierarchy",
             "mg_host_hierarchy_view", "mg_host_hierarchy_free", "mg_destroy", "mg_last_error",
-            "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres", "mg_fgmres_static"]
+            "mg_fmg", "mg_fgmres_workspace_bytes", "mg_fgmres", "mg_fgmres_static", "mg_load_column",
+            "mg_set_solver_options"]
 KERNEL_FAMILIES = {"hop": 1, "resid": 2, "restrict": 3, "prolong": 4, "outer": 5, "krylov": 6, "conv": 7}
 PRECONDITIONERS = {"none": 0, "vcycle": 1, "fmg": 2}
 LOSS_KINDS = {"mean_rel_sq": 0, "resid_norm": 1}
@@ -54,7 +55,8 @@ class _CSR(C.Structure):
 
 class _Hier(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("A", C.POINTER(_CSR)), ("P", C.POINTER(_CSR)),
-                ("R", C.POINTER(_CSR)), ("G", C.POINTER(_CSR))]
+                ("R", C.POINTER(_CSR)), ("G", C.POINTER(_CSR)), ("ncolumn_values", C.c_int32),
+                ("column_values", C.POINTER(C.POINTER(C.c_double)))]
 
 
 class _Params(C.Structure):
@@ -97,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.mg_setup.argtypes = [C.POINTER(_Hier), C.POINTER(_Params), C.POINTER(_Options), vp, sz, vp,
                              C.POINTER(vp)]
     lib.mg_set_params.argtypes = [vp, C.POINTER(C.c_double), vp]
+    lib.mg_load_column.argtypes = [vp, C.c_int32, C.POINTER(C.POINTER(C.c_double)), vp]
+    lib.mg_set_solver_options.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double]
     lib.mg_vcycle.argtypes = [vp, vp, vp, vp, vp]
     lib.mg_vcycle_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.mg_residual.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -120,7 +124,8 @@ def load_library(path: str = LIB_PATH):
     lib.mg_destroy.argtypes = [vp]
     lib.mg_destroy.restype = None
     lib.mg_last_error.restype = C.c_char_p
-    for name in ("mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_vcycle", "mg_vcycle_backward",
+    for name in ("mg_workspace_bytes", "mg_setup", "mg_set_params", "mg_load_column", "mg_set_solver_options",
+                 "mg_vcycle", "mg_vcycle_backward",
                  "mg_residual", "mg_residual_loss", "mg_refine_step", "mg_refine_step_backward", "mg_solve", "mg_level_info",
                  "mg_timing_start", "mg_timing_read"):
         getattr(lib, name).restype = C.c_int
@@ -164,6 +169,26 @@ class _HostHierarchy:
                           va.ctypes.data_as(C.POINTER(C.c_double)))
         self._keep.append(arr)
         return arr
+
+
+def _level_values(src):
+    """Per-level pointers to the CSR values of a column's operators: src is a
+    SquareHierarchy (native arrays, no copy) or a list of scipy matrices A_l.
+    Returns (pointer list, objects to keep alive)."""
+    if isinstance(src, SquareHierarchy):
+        return [src.view.A[l].val for l in range(src.nlevels)], [src]
+    keep, ptrs = [], []
+    for a in src:
+        v = np.ascontiguousarray(a.tocsr().data, dtype=np.float64)
+        keep.append(v)
+        ptrs.append(v.ctypes.data_as(C.POINTER(C.c_double)))
+    return ptrs, keep
+
+
+def _level_nnz(src):
+    if isinstance(src, SquareHierarchy):
+        return [int(src.view.A[l].nnz) for l in range(src.nlevels)]
+    return [int(a.nnz) for a in src]
 
 
 class SquareHierarchy:
@@ -232,12 +257,16 @@ class Context:
     tail / tiles: allow the LDS-resident coarse tail / the fused K-hop
     convolution over LDS tiles (FP32/BF16 cycles with nrhs a multiple of 16).
     compact: let solve() narrow the cycle to the columns still iterating.
+    columns: per-column operators (a batch of requests on one grid): a list of
+    nrhs sources, each a SquareHierarchy or a list of scipy A_l on the pattern
+    of the given A (or native) hierarchy; column b then solves with its own
+    A_l^(b) (mg_hierarchy.ncolumn_values).
     """
 
     def __init__(self, A, P, params, KB, KR, KP, nu_pre=2, nu_post=2, precision="fp64", nrhs=1,
                  R=None, G=None, rtol=1e-8, max_outer=10000, check_every=10, diverge_factor=1e6,
                  backward=False, device=None, stream=None, workspace=True, tail=True, native=None,
-                 basis="monomial", aggregation="mean", tiles=True, compact=True):
+                 basis="monomial", aggregation="mean", tiles=True, compact=True, columns=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -268,6 +297,31 @@ class Context:
         self._o = _Options(PRECISIONS[precision], nrhs, max_outer, check_every, rtol, diverge_factor,
                            (FLAG_BACKWARD if backward else 0) | (0 if tail else FLAG_NO_TAIL) |
                            (0 if tiles else FLAG_NO_TILES) | (0 if compact else FLAG_NO_COMPACT))
+        self._colkeep = None
+        self.nnz = [int(self._hh.h.A[l].nnz) for l in range(self.J)]
+        if columns is not None:
+            if len(columns) != nrhs:
+                raise ValueError("columns: one operator source per right-hand side")
+            arr = (C.POINTER(C.c_double) * (self.J * nrhs))()
+            keep = [arr]
+            for b, src in enumerate(columns):
+                if _level_nnz(src) != self.nnz:
+                    raise ValueError(f"columns[{b}]: pattern sizes differ from the context's")
+                ptrs, k = _level_values(src)
+                if len(ptrs) != self.J:
+                    raise ValueError("columns: wrong level count")
+                keep += k
+                for l in range(self.J):
+                    arr[l * nrhs + b] = ptrs[l]
+            hh = _Hier()
+            C.memmove(C.byref(hh), C.byref(self._hh.h), C.sizeof(_Hier))
+            hh.ncolumn_values = nrhs
+            hh.column_values = arr
+            self._colkeep = (hh, keep, self._hh)
+
+            class _ColView:
+                h = hh
+            self._hh = _ColView()
         ws, ck = C.c_size_t(), C.c_size_t()
         _check(self.lib.mg_workspace_bytes(C.byref(self._hh.h), C.byref(self._p), C.byref(self._o),
                                            C.byref(ws), C.byref(ck)), "mg_workspace_bytes")
@@ -279,6 +333,7 @@ class Context:
                                  _ptr(self._ws), self.workspace_bytes, self._s(), C.byref(h)), "mg_setup")
         self._h = h
         self._hh = None   # the library copied what it needs
+        self._colkeep = None
 
     # ------------------------------------------------------------------ helpers
     def _s(self):
@@ -306,6 +361,25 @@ class Context:
             raise ValueError("wrong parameter count")
         _check(self.lib.mg_set_params(self._h, self._params.ctypes.data_as(C.POINTER(C.c_double)), self._s()),
                "mg_set_params")
+
+    def load_column(self, b: int, src):
+        """mg_load_column: column b solves with the operators of `src` from now on
+        (a SquareHierarchy or a list of scipy A_l on the context's pattern)."""
+        nnz = _level_nnz(src)
+        if nnz != self.nnz:
+            raise ValueError(f"load_column: the source's pattern sizes {nnz} differ from the context's {self.nnz}")
+        ptrs, keep = _level_values(src)
+        arr = (C.POINTER(C.c_double) * len(ptrs))(*ptrs)
+        _check(self.lib.mg_load_column(self._h, b, arr, self._s()), "mg_load_column")
+
+    def set_solver_options(self, max_outer=None, check_every=None, rtol=None, diverge_factor=None):
+        o = self._o
+        o.max_outer = o.max_outer if max_outer is None else max_outer
+        o.check_every = o.check_every if check_every is None else check_every
+        o.rtol = o.rtol if rtol is None else rtol
+        o.diverge_factor = o.diverge_factor if diverge_factor is None else diverge_factor
+        _check(self.lib.mg_set_solver_options(self._h, o.max_outer, o.check_every, o.rtol, o.diverge_factor),
+               "mg_set_solver_options")
 
     @property
     def params(self):

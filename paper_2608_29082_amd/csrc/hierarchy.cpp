@@ -339,6 +339,8 @@ mg_status mg_host_hierarchy_view(const mg_host_hierarchy* h, mg_hierarchy* v) {
   v->P = h->Pv.data();
   v->R = nullptr;
   v->G = nullptr;
+  v->ncolumn_values = 0;
+  v->column_values = nullptr;
   return MG_OK;
 }
 

@@ -64,7 +64,18 @@ template <class C> struct Lvl {
                             // node) for the mean, 1/sum_j w_ij for weighted, 1 for symmetric
   const C* gval;            // edge weights w_ij in the graph's slots (padding 0), or null
                             // for the unweighted mean
+  int vs;                   // 0: val, diag, invdiag shared by all columns; else per-column
+                            // operators: entry (k, i) of column c at (k*ld + i) * vs + c, and
+                            // diag / invdiag of row i at i * vs + c
+  const int* vmap;          // per-column operators with a compacted cycle: the operator column
+                            // of vector column b is vmap[b] (null: b)
 };
+
+// operator column of vector column b (per-column operators)
+template <class C>
+__device__ __forceinline__ int vcol(const Lvl<C>& L, int b) {
+  return L.vmap ? L.vmap[b] : b;
+}
 
 // Transfer operator (P, R or their transposes) in ELL form, padding val == 0.
 template <class C> struct Xfer {
@@ -189,6 +200,30 @@ __device__ __forceinline__ void ell_dot(int W, int ld, const int* __restrict__ c
   }
 }
 
+// ell_dot with per-column operator values (Lvl::vs): the values of operator
+// column vb; indices as in ell_dot, same sums in the same order
+template <bool WIDE, int NR, class C, class TX>
+__device__ __forceinline__ void ell_dot_v(int W, int ld, int vs, int vb, const int* __restrict__ col,
+                                          const C* __restrict__ val, const int (&row)[NR],
+                                          const TX* __restrict__ x, int B, int b, C (&s)[NR]) {
+  for (int k = 0; k < W; k += 4) {
+    int j[NR][4];
+    C v[NR][4];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t o = (size_t)(k + q) * ld + row[r];
+        j[r][q] = uni<WIDE>(col[o]);
+        v[r][q] = val[o * vs + vb];
+      }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[r] += v[r][q] * ldc<C>(x + (size_t)j[r][q] * B + b);
+  }
+}
+
 // As ell_dot on the iterate v = u + e of one column (u: that column's entries
 // at stride su, e: at stride se), each neighbour's sum formed in FP64 as it is
 // read (the FP64 outer residual of the solver's fused update).
@@ -196,11 +231,20 @@ template <bool WIDE, bool CONSEC, int NR, class TE>
 __device__ __forceinline__ void ell_dot_upd(int W, int ld, const int* __restrict__ col,
                                             const double* __restrict__ val, const int (&row)[NR], int row0,
                                             const double* __restrict__ u, int su, const TE* __restrict__ e, int se,
-                                            double (&s)[NR]) {
+                                            double (&s)[NR], int vs = 0, int vb = 0) {
   for (int k = 0; k < W; k += 4) {
     int j[NR][4];
     double v[NR][4];
-    if constexpr (CONSEC && NR == 4) {
+    if (vs) {   // per-column operator values
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const size_t o = (size_t)(k + q) * ld + row[r];
+          j[r][q] = uni<WIDE>(col[o]);
+          v[r][q] = val[o * vs + vb];
+        }
+    } else if constexpr (CONSEC && NR == 4) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const V4<int> jj = ld4(col + (size_t)(k + q) * ld + row0);
@@ -293,40 +337,48 @@ __device__ __forceinline__ void row_vals(const C* __restrict__ p, const int (&ro
 // out = [invdiag *] (f - A u); uz: u is identically zero.
 // FINE only tags finest-level launches with their own kernel symbol (for
 // per-level profiles); the code is the same.
-template <int ROWS, bool WIDE, bool FINE, class C, class TU, class TO>
+// PCV: per-column operators (Lvl::vs), the diagonal and values of each column's own operator.
+template <int ROWS, bool WIDE, bool FINE, bool PCV, class C, class TU, class TO>
 __global__ __launch_bounds__(256) void k_resid(Lvl<C> L, int B, int lbs, const TU* __restrict__ f,
                                                const TU* __restrict__ u, int uz, int jacobi,
                                                TO* __restrict__ out) {
-  constexpr bool CS = WIDE && ROWS == 4;
+  constexpr bool CS = WIDE && ROWS == 4 && !PCV;
   const Tile<ROWS, WIDE> t(L.n, lbs);
   if (WIDE && !t.any) return;
   C dinv[ROWS];
-  if (jacobi) row_vals<WIDE, CS>(L.invdiag, t.row, t.row0, dinv);
+  if (!PCV && jacobi) row_vals<WIDE, CS>(L.invdiag, t.row, t.row0, dinv);
   if (uz) {
     for (int b = t.lane; b < B; b += t.LB) {
+      const int vb = PCV ? vcol(L, b) : 0;
 #pragma unroll
       for (int r = 0; r < ROWS; ++r) {
         if (!t.ok[r]) continue;
         C v = ldc<C>(f + (size_t)t.row[r] * B + b);
-        if (jacobi) v *= dinv[r];
+        if (jacobi) v *= PCV ? L.invdiag[(size_t)t.row[r] * L.vs + vb] : dinv[r];
         put(out + (size_t)t.row[r] * B + b, v);
       }
     }
     return;
   }
   C dg[ROWS];
-  row_vals<WIDE, CS>(L.diag, t.row, t.row0, dg);
+  if (!PCV) row_vals<WIDE, CS>(L.diag, t.row, t.row0, dg);
   for (int b = t.lane; b < B; b += t.LB) {
     // the row's own f and u are loaded first but consumed only at the end, so
     // their loads overlap the index loads and the off-diagonal gathers
     C fv[ROWS], uv[ROWS], s[ROWS];
+    const int vb = PCV ? vcol(L, b) : 0;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       fv[r] = ldc<C>(f + (size_t)t.row[r] * B + b);
       uv[r] = ldc<C>(u + (size_t)t.row[r] * B + b);
       s[r] = C(0);
+      if constexpr (PCV) {
+        dg[r] = L.diag[(size_t)t.row[r] * L.vs + vb];
+        if (jacobi) dinv[r] = L.invdiag[(size_t)t.row[r] * L.vs + vb];
+      }
     }
-    ell_dot<WIDE, CS>(L.w, L.ld, L.col, L.val, t.row, t.row0, u, B, b, s);
+    if constexpr (PCV) ell_dot_v<WIDE>(L.w, L.ld, L.vs, vb, L.col, L.val, t.row, u, B, b, s);
+    else ell_dot<WIDE, CS>(L.w, L.ld, L.col, L.val, t.row, t.row0, u, B, b, s);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (!t.ok[r]) continue;
@@ -736,12 +788,17 @@ __global__ __launch_bounds__(256) void k_restrict(Xfer<C> R, Lvl<C> L, int B, in
         for (int q = 0; q < 4; ++q) v[q] = hop_value(a, uni<WIDE>(L.invdeg[jr[q]]), sm[q], c, xv[q]);
       } else {
         C fv[4], sa[4];
+        const int vb = L.vs ? vcol(L, b) : 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           fv[q] = ldc<C>(f + (size_t)jr[q] * B + b);
-          sa[q] = uz ? C(0) : uni<WIDE>(L.diag[jr[q]]) * ldc<C>(u + (size_t)jr[q] * B + b);
+          const C dq = L.vs ? L.diag[(size_t)jr[q] * L.vs + vb] : uni<WIDE>(L.diag[jr[q]]);
+          sa[q] = uz ? C(0) : dq * ldc<C>(u + (size_t)jr[q] * B + b);
         }
-        if (!uz) ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, jr, 0, u, B, b, sa);
+        if (!uz) {
+          if (L.vs) ell_dot_v<WIDE>(L.w, L.ld, L.vs, vb, L.col, L.val, jr, u, B, b, sa);
+          else ell_dot<WIDE, false>(L.w, L.ld, L.col, L.val, jr, 0, u, B, b, sa);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = fv[q] - sa[q];
       }
@@ -798,10 +855,13 @@ __global__ __launch_bounds__(256) void k_prolong(Xfer<C> P, int B, int lbs, cons
 // Coarsest level: u = Ainv f (or Ainv^T f), Ainv dense row-major FP64.
 template <class TU>
 __global__ __launch_bounds__(256) void k_coarse(int n, int B, const double* __restrict__ Ainv,
-                                                const TU* __restrict__ f, TU* __restrict__ u, int trans) {
+                                                const TU* __restrict__ f, TU* __restrict__ u, int trans,
+                                                int pcv, const int* __restrict__ vmap) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)n * B) return;
   const int i = (int)(t / B), b = (int)(t % B);
+  // per-column operators: column b's own inverse
+  if (pcv) Ainv += (size_t)(vmap ? vmap[b] : b) * n * n;
   double acc = 0.0;
   for (int j = 0; j < n; ++j) {
     const double a = trans ? Ainv[(size_t)j * n + i] : Ainv[(size_t)i * n + j];
@@ -885,7 +945,7 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* W, int* in
 // the fly for the row and its neighbours (the same FP64 sum for every
 // reader, so the same bits as storing it first); v is written to uo (which
 // must not alias u: neighbours still read u) and the residual is f - A v.
-template <bool WIDE, bool UPD, class TR, class TE>
+template <bool WIDE, bool UPD, bool PCV, class TR, class TE>
 __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int lbs, int chunk,
                                                      const double* __restrict__ f, const double* __restrict__ u,
                                                      double* __restrict__ r64, TR* __restrict__ rc,
@@ -912,7 +972,7 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
     // the diagonal are one 16-byte scalar load per row quadruple
     const int r0 = uni<WIDE>((int)i0);
     double dg[4];
-    row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
+    if (!PCV) row_vals<WIDE, WIDE>(L.diag, row, r0, dg);
     int q = 0;
     for (int b = lane; b < B; b += LB, ++q) {
       // UPD: a stopped column is not touched (its iterate stays where it was last written)
@@ -927,9 +987,12 @@ __global__ __launch_bounds__(256) void k_outer_resid(Lvl<double> L, int B, int l
         fv[r] = f[(size_t)row[r] * B + b];
         uv[r] = u[(size_t)row[r] * B + b];
         if constexpr (UPD) uv[r] += (double)e[(size_t)row[r] * Bc + sb];
+        if constexpr (PCV) dg[r] = L.diag[(size_t)row[r] * L.vs + b];
         s[r] = 0.0;
       }
-      if constexpr (UPD) ell_dot_upd<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u + b, B, e + sb, Bc, s);
+      if constexpr (UPD)
+        ell_dot_upd<WIDE, WIDE && !PCV>(L.w, L.ld, L.col, L.val, row, r0, u + b, B, e + sb, Bc, s, PCV ? L.vs : 0, b);
+      else if constexpr (PCV) ell_dot_v<WIDE>(L.w, L.ld, L.vs, b, L.col, L.val, row, u, B, b, s);
       else ell_dot<WIDE, WIDE>(L.w, L.ld, L.col, L.val, row, r0, u, B, b, s);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1134,6 +1197,26 @@ __global__ __launch_bounds__(256) void k_repack(int n, int Bo, int Bn, const int
   dst[t] = k >= 0 ? src[i * Bo + k] : T(0);
 }
 
+// Column b of a level's per-column operator arrays from one column's FP64
+// arrays (off: [w][ld] slot values, dg: [ld] diagonal): values, diagonal and
+// inverse diagonal in the cycle type, and (val64 / diag64 non-null) the FP64
+// copies of the finest level.  Rows [n, ld) are padding (inverse diagonal 0).
+template <class C>
+__global__ __launch_bounds__(256) void k_put_column(int w, int ld, int n, int nv, int b, const double* __restrict__ off,
+                                                    const double* __restrict__ dg, C* val, C* diag, C* invdiag,
+                                                    double* val64, double* diag64) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (long)w * ld) {
+    val[t * nv + b] = (C)off[t];
+    if (val64) val64[t * nv + b] = off[t];
+  }
+  if (t < ld) {
+    diag[t * nv + b] = (C)dg[t];
+    invdiag[t * nv + b] = t < n ? (C)(1.0 / dg[t]) : C(0);
+    if (diag64) diag64[t * nv + b] = dg[t];
+  }
+}
+
 // u[i][b] = w[i][b] for the columns whose update count iters[b] is odd (the
 // solver alternates the iterate between u and w, one buffer per update)
 __global__ __launch_bounds__(256) void k_copy_odd(int n, int B, int lbs, const int* __restrict__ iters,
@@ -1208,17 +1291,19 @@ __device__ __forceinline__ void tl_load_row(const Lvl<C>& L, TRow<C, WG>& R) {
   const int e = threadIdx.x;
   if (e >= L.n * CPB) return;
   const int i = e / CPB;
+  // per-column operators (one column per workgroup): the operator column of this workgroup's column
+  const int vs = L.vs, vb = vs ? vcol(L, (int)blockIdx.x) : 0;
 #pragma unroll
   for (int k = 0; k < kTailW; ++k) {
     const size_t o = (size_t)(k < L.w ? k : 0) * L.ld + i;
     const size_t og = (size_t)(k < L.wg ? k : 0) * L.ld + i;
     R.ac[k] = L.col[o];
-    R.av[k] = L.val[o];
+    R.av[k] = vs ? L.val[o * vs + vb] : L.val[o];
     R.gc[k] = L.gcol[og];
     if constexpr (WG) R.gw[k] = L.gval[og];
   }
-  R.dg = L.diag[i];
-  R.ida = L.invdiag[i];
+  R.dg = vs ? L.diag[(size_t)i * vs + vb] : L.diag[i];
+  R.ida = vs ? L.invdiag[(size_t)i * vs + vb] : L.invdiag[i];
   R.idg = L.invdeg[i];
 }
 
@@ -1243,11 +1328,14 @@ __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u
     __syncthreads();
     return;
   }
+  // per-column operators (one column per workgroup, CPB == 1): value (o) of the workgroup's column
+  const int vs = L.vs, vb = vs ? vcol(L, (int)blockIdx.x) : 0;
+  auto vi = [&](size_t o) { return vs ? o * vs + vb : o; };
   for (int e = threadIdx.x; e < L.n * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     C v = f[e];
     if (!uz) {
-      C au = L.diag[i] * u[e];
+      C au = L.diag[vi(i)] * u[e];
       if (L.w >= 1 && L.w <= kTailW) {
         int jj[kTailW];
         C vv[kTailW];
@@ -1255,17 +1343,18 @@ __device__ __forceinline__ void tl_resid(const Lvl<C>& L, const C* f, const C* u
         for (int k = 0; k < kTailW; ++k) {
           const size_t o = (size_t)(k < L.w ? k : 0) * L.ld + i;
           jj[k] = L.col[o];
-          vv[k] = L.val[o];
+          vv[k] = L.val[vi(o)];
         }
 #pragma unroll
         for (int k = 0; k < kTailW; ++k)
           if (k < L.w) au += vv[k] * u[jj[k] * CPB + c];
       } else {
-        for (int k = 0; k < L.w; ++k) au += L.val[(size_t)k * L.ld + i] * u[L.col[(size_t)k * L.ld + i] * CPB + c];
+        for (int k = 0; k < L.w; ++k)
+          au += L.val[vi((size_t)k * L.ld + i)] * u[L.col[(size_t)k * L.ld + i] * CPB + c];
       }
       v -= au;
     }
-    if (jacobi) v *= L.invdiag[i];
+    if (jacobi) v *= L.invdiag[vi(i)];
     out[e] = v;
   }
   __syncthreads();
@@ -1384,10 +1473,13 @@ __device__ __forceinline__ void tl_coarse(const TailArgs<C>& T, C* sm) {
   const TailLevel<C>& tl = T.lv[T.nl - 1];
   const C* f = sm + tl.off_f;
   C* u = sm + tl.off_u;
+  // per-column operators (CPB == 1): the inverse of this workgroup's column
+  const Lvl<C>& LJ = tl.L;
+  const double* Ai = LJ.vs ? T.Ainv + (size_t)vcol(LJ, (int)blockIdx.x) * T.nJ * T.nJ : T.Ainv;
   for (int e = threadIdx.x; e < T.nJ * CPB; e += blockDim.x) {
     const int i = e / CPB, c = e - i * CPB;
     double acc = 0.0;
-    for (int j = 0; j < T.nJ; ++j) acc += T.Ainv[(size_t)i * T.nJ + j] * (double)f[j * CPB + c];
+    for (int j = 0; j < T.nJ; ++j) acc += Ai[(size_t)i * T.nJ + j] * (double)f[j * CPB + c];
     u[e] = (C)acc;
   }
   __syncthreads();

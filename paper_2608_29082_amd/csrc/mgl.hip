@@ -64,6 +64,17 @@ namespace {
       __VA_ARGS__;                         \
     }                                      \
   } while (0)
+// run `...` with the compile-time flag PCVv = (the columns have their own operator values)
+#define PCV_SPLIT(...)                     \
+  do {                                     \
+    if (pl.nv) {                           \
+      constexpr bool PCVv = true;          \
+      __VA_ARGS__;                         \
+    } else {                               \
+      constexpr bool PCVv = false;         \
+      __VA_ARGS__;                         \
+    }                                      \
+  } while (0)
 // launch row-tile kernel KERN<ROWS, TARGS...> over the rows of level record D
 #define ROWS_LAUNCH(D, KERN, TARGS, ...)                                                                        \
   do {                                                                                                          \
@@ -129,6 +140,7 @@ struct EngineBase {
                            mg_rhs_info* info, hipStream_t st) = 0;
   virtual size_t fgmres_bytes(int restart) = 0;
   virtual mg_status set_params(const double* v, hipStream_t st) = 0;
+  virtual mg_status load_column(int b, const double* const* vals, hipStream_t st) = 0;
   virtual mg_status setup(void* ws, hipStream_t st) = 0;
   virtual size_t ws_bytes() = 0;
   virtual size_t ck_bytes() = 0;
@@ -240,6 +252,8 @@ struct Engine final : EngineBase {
   int ncu = 0;                      // compute units of the device
   // active-column compaction of mg_solve: column b's cycle data at slot cmap[b] of curB
   int* cmap = nullptr;              // device [nrhs]
+  int* vmapd = nullptr;             // per-column operators: device [nrhs], operator column of each slot
+  double* colstage = nullptr;       // per-column operators: one column's level arrays (mg_load_column)
   int* cfrom = nullptr;             // device [nrhs]: old slot of each new slot (repack)
   int* hmap = nullptr;              // pinned host [3 nrhs]: flags, new map, repack sources
   std::vector<int> hcur;            // host copy of cmap
@@ -333,9 +347,12 @@ struct Engine final : EngineBase {
       x.L.ld = ld;
       x.L.w = H.off.w;
       x.L.col = bp.take<int>((size_t)H.off.w * ld);
-      x.L.val = bp.take<C>((size_t)H.off.w * ld);
-      x.L.diag = bp.take<C>(ld);
-      x.L.invdiag = bp.take<C>(ld);
+      const size_t nvv = pl.nv ? (size_t)pl.nv : 1;   // operator columns (per-column operators: nrhs)
+      x.L.vs = pl.nv;
+      x.L.vmap = nullptr;
+      x.L.val = bp.take<C>((size_t)H.off.w * ld * nvv);
+      x.L.diag = bp.take<C>(ld * nvv);
+      x.L.invdiag = bp.take<C>(ld * nvv);
       x.L.invdeg = bp.take<C>(ld);
       if (H.graph_is_A) {
         x.L.wg = H.off.w;
@@ -373,15 +390,26 @@ struct Engine final : EngineBase {
     } else {
       L64.n = d[0].L.n; L64.ld = d[0].L.ld; L64.w = d[0].L.w; L64.col = d[0].L.col; L64.wg = d[0].L.wg;
       L64.gcol = d[0].L.gcol;
-      L64.val = bp.take<double>((size_t)pl.lv[0].off.w * d[0].L.ld);
-      L64.diag = bp.take<double>(d[0].L.ld);
+      L64.vs = pl.nv;
+      L64.vmap = nullptr;
+      const size_t nvv = pl.nv ? (size_t)pl.nv : 1;
+      L64.val = bp.take<double>((size_t)pl.lv[0].off.w * d[0].L.ld * nvv);
+      L64.diag = bp.take<double>(d[0].L.ld * nvv);
       L64.invdiag = nullptr;
       L64.invdeg = nullptr;
       L64.gval = nullptr;
     }
     const int nJ = pl.lv[J - 1].n;
-    Ainv = bp.take<double>((size_t)nJ * nJ);
+    Ainv = bp.take<double>((size_t)nJ * nJ * (pl.nv ? pl.nv : 1));
     gj = bp.take<double>((size_t)nJ * 2 * nJ);
+    if (pl.nv) {
+      // mg_load_column: one column's operator of the largest level, staged in FP64, and the
+      // vector-to-operator column map of a compacted cycle
+      size_t st = 0;
+      for (int l = 0; l < J; ++l) st = std::max(st, (size_t)(pl.lv[l].off.w + 1) * round_up(pl.lv[l].n, 4));
+      colstage = bp.take<double>(st);
+      vmapd = bp.take<int>(B);
+    }
     dinfo = bp.take<int>(1);
     const size_t n0B = (size_t)pl.lv[0].n * B;
     r0 = bp.take<TU>(n0B);
@@ -454,6 +482,23 @@ struct Engine final : EngineBase {
     return MG_OK;
   }
 
+  // Ainv (operator column b) = A^{-1} of the dense coarsest operator Ad (row-major n_J x n_J):
+  // Gauss-Jordan with partial pivoting in FP64 on the device; *dinfo != 0 if singular
+  mg_status coarse_inverse(const double* Ad, int b, hipStream_t st) {
+    const int nJ = pl.lv[pl.J - 1].n;
+    std::vector<double> W((size_t)nJ * 2 * nJ, 0.0);
+    for (int i = 0; i < nJ; ++i) {
+      for (int j = 0; j < nJ; ++j) W[(size_t)i * 2 * nJ + j] = Ad[(size_t)i * nJ + j];
+      W[(size_t)i * 2 * nJ + nJ + i] = 1.0;
+    }
+    MG_TRY(up(gj, W, st));
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, nJ, gj, dinfo);
+    LAUNCH_OK();
+    HIP_TRY(hipMemcpy2DAsync(Ainv + (size_t)b * nJ * nJ, nJ * sizeof(double), gj + nJ, 2 * nJ * sizeof(double),
+                             nJ * sizeof(double), nJ, hipMemcpyDeviceToDevice, st));
+    return MG_OK;
+  }
+
   mg_status setup(void* ws, hipStream_t st) override {
     const size_t need = ws_bytes();
     if (ws) {
@@ -470,16 +515,27 @@ struct Engine final : EngineBase {
       const HLevel& H = pl.lv[l];
       DL& x = d[l];
       MG_TRY(upi(x.L.col, H.off.col, st));
-      MG_TRY(up(const_cast<C*>(x.L.val), H.off.val, st));
-      std::vector<double> dg(x.L.ld, 1.0), inv(x.L.ld, 0.0), ideg(x.L.ld, 0.0);
-      for (int i = 0; i < H.n; ++i) {
-        dg[i] = H.diag[i];
-        inv[i] = 1.0 / H.diag[i];
-        ideg[i] = H.invdeg[i];
-      }
-      MG_TRY(up(const_cast<C*>(x.L.diag), dg, st));
-      MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
+      std::vector<double> ideg(x.L.ld, 0.0);
+      for (int i = 0; i < H.n; ++i) ideg[i] = H.invdeg[i];
       MG_TRY(up(const_cast<C*>(x.L.invdeg), ideg, st));
+      if (pl.nv) {
+        // per-column operators: [slot][row][column] values, [row][column] diagonals
+        MG_TRY(up(const_cast<C*>(x.L.val), H.offv, st));
+        std::vector<double> inv(H.diagv.size(), 0.0);
+        for (int i = 0; i < H.n; ++i)
+          for (int b = 0; b < pl.nv; ++b) inv[(size_t)i * pl.nv + b] = 1.0 / H.diagv[(size_t)i * pl.nv + b];
+        MG_TRY(up(const_cast<C*>(x.L.diag), H.diagv, st));
+        MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
+      } else {
+        MG_TRY(up(const_cast<C*>(x.L.val), H.off.val, st));
+        std::vector<double> dg(x.L.ld, 1.0), inv(x.L.ld, 0.0);
+        for (int i = 0; i < H.n; ++i) {
+          dg[i] = H.diag[i];
+          inv[i] = 1.0 / H.diag[i];
+        }
+        MG_TRY(up(const_cast<C*>(x.L.diag), dg, st));
+        MG_TRY(up(const_cast<C*>(x.L.invdiag), inv, st));
+      }
       if (!H.graph_is_A) MG_TRY(upi(x.L.gcol, H.graph.col, st));
       if (x.L.gval) MG_TRY(up(const_cast<C*>(x.L.gval), H.gval, st));
     }
@@ -497,23 +553,27 @@ struct Engine final : EngineBase {
       }
     }
     if (!std::is_same<C, double>::value) {
-      MG_TRY(up(const_cast<double*>(L64.val), pl.lv[0].off.val, st));
-      std::vector<double> dg(L64.ld, 1.0);
-      for (int i = 0; i < L64.n; ++i) dg[i] = pl.lv[0].diag[i];
-      MG_TRY(up(const_cast<double*>(L64.diag), dg, st));
+      if (pl.nv) {
+        MG_TRY(up(const_cast<double*>(L64.val), pl.lv[0].offv, st));
+        MG_TRY(up(const_cast<double*>(L64.diag), pl.lv[0].diagv, st));
+      } else {
+        MG_TRY(up(const_cast<double*>(L64.val), pl.lv[0].off.val, st));
+        std::vector<double> dg(L64.ld, 1.0);
+        for (int i = 0; i < L64.n; ++i) dg[i] = pl.lv[0].diag[i];
+        MG_TRY(up(const_cast<double*>(L64.diag), dg, st));
+      }
     }
-    // coarsest inverse: W = [A | I], Gauss-Jordan on the device
+    // coarsest inverse (one per operator column): W = [A | I], Gauss-Jordan on the device
     const int nJ = pl.lv[J - 1].n;
-    std::vector<double> W((size_t)nJ * 2 * nJ, 0.0);
-    for (int i = 0; i < nJ; ++i) {
-      for (int j = 0; j < nJ; ++j) W[(size_t)i * 2 * nJ + j] = pl.Acoarse[(size_t)i * nJ + j];
-      W[(size_t)i * 2 * nJ + nJ + i] = 1.0;
+    for (int b = 0; b < (pl.nv ? pl.nv : 1); ++b) {
+      MG_TRY(coarse_inverse(pl.nv ? &pl.AcoarseV[(size_t)b * nJ * nJ] : pl.Acoarse.data(), b, st));
+      if (pl.nv) {
+        HIP_TRY(hipMemcpyAsync(hcount, dinfo, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hcount[0] != 0)
+          return fail(MG_ERR_SHAPE, "coarsest matrix of column " + std::to_string(b) + " is singular");
+      }
     }
-    MG_TRY(up(gj, W, st));
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, nJ, gj, dinfo);
-    LAUNCH_OK();
-    HIP_TRY(hipMemcpy2DAsync(Ainv, nJ * sizeof(double), gj + nJ, 2 * nJ * sizeof(double), nJ * sizeof(double), nJ,
-                             hipMemcpyDeviceToDevice, st));
     MG_TRY(up(dprm, pl.params, st));
     if (bwd()) {
       HIP_TRY(hipMemcpyAsync(doff, h_off.data(), h_off.size() * sizeof(long), hipMemcpyHostToDevice, st));
@@ -772,6 +832,50 @@ struct Engine final : EngineBase {
     return MG_OK;
   }
 
+  // replace column b's operators on every level (per-column operator contexts)
+  mg_status load_column(int b, const double* const* vals, hipStream_t st) override {
+    if (!pl.nv) return fail(MG_ERR_STATE, "context was set up without per-column operators");
+    if (b < 0 || b >= pl.nv) return fail(MG_ERR_INVALID_ARG, "column out of range");
+    if (!vals) return fail(MG_ERR_INVALID_ARG, "null values");
+    for (int l = 0; l < pl.J; ++l)
+      if (!vals[l]) return fail(MG_ERR_INVALID_ARG, "null values of level " + std::to_string(l));
+    const int J = pl.J;
+    // validate every level first, so a refused column leaves the context unchanged
+    std::vector<std::vector<double>> hs(J);
+    for (int l = 0; l < J; ++l) {
+      const HLevel& H = pl.lv[l];
+      const int w = H.off.w, ld = H.off.ld;
+      mg_csr pat{H.n, H.n, (int64_t)pl.pcol[l].size(), pl.prow[l].data(), pl.pcol[l].data(), nullptr};
+      hs[l].assign((size_t)(w + 1) * ld, 0.0);
+      MG_TRY(column_arrays(&pat, vals[l], H, hs[l].data(), hs[l].data() + (size_t)w * ld, l, b));
+    }
+    for (int l = 0; l < J; ++l) {
+      const HLevel& H = pl.lv[l];
+      const int w = H.off.w, ld = H.off.ld;
+      HIP_TRY(hipMemcpyAsync(colstage, hs[l].data(), hs[l].size() * sizeof(double), hipMemcpyHostToDevice, st));
+      const bool f64 = l == 0 && !std::is_same<C, double>::value;
+      const long cnt = std::max<long>((long)w * ld, ld);
+      hipLaunchKernelGGL((k_put_column<C>), dim3(nblocks(cnt)), dim3(256), 0, st, w, ld, H.n, pl.nv, b,
+                         (const double*)colstage, (const double*)(colstage + (size_t)w * ld), const_cast<C*>(d[l].L.val),
+                         const_cast<C*>(d[l].L.diag), const_cast<C*>(d[l].L.invdiag),
+                         f64 ? const_cast<double*>(L64.val) : nullptr, f64 ? const_cast<double*>(L64.diag) : nullptr);
+      LAUNCH_OK();
+      HIP_TRY(hipStreamSynchronize(st));   // colstage is reused by the next level
+    }
+    const int nJ = pl.lv[J - 1].n;
+    std::vector<double> Ad((size_t)nJ * nJ, 0.0);
+    const std::vector<int32_t>& rp = pl.prow[J - 1];
+    const std::vector<int32_t>& cl = pl.pcol[J - 1];
+    for (int i = 0; i < nJ; ++i)
+      for (int q = rp[i]; q < rp[i + 1]; ++q) Ad[(size_t)i * nJ + cl[q]] = vals[J - 1][q];
+    MG_TRY(coarse_inverse(Ad.data(), b, st));
+    HIP_TRY(hipMemcpyAsync(hcount, dinfo, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    staging.clear();
+    if (hcount[0] != 0) return fail(MG_ERR_SHAPE, "coarsest matrix of the new column is singular");
+    return MG_OK;
+  }
+
   mg_status set_params(const double* v, hipStream_t st) override {
     for (size_t i = 0; i < pl.params.size(); ++i)
       if (!std::isfinite(v[i])) return fail(MG_ERR_INVALID_ARG, "non-finite parameter");
@@ -833,12 +937,12 @@ struct Engine final : EngineBase {
   mg_status smooth(int l, const TU* f, TU* u, int uz, TH* s, hipStream_t st, bool keep_s = true) {
     const DL& D = d[l];
     if constexpr (std::is_same<TH, TU>::value && std::is_same<C, float>::value) {
-      if (uz && !keep_s && pl.KB >= 2 && tiled(l, pl.KB, f, u))
+      if (uz && !keep_s && pl.KB >= 2 && !pl.nv && tiled(l, pl.KB, f, u))
         return conv_tile<TU, TU>(l, cB(l), pl.KB, f, u, 1, eta(l) * theta(l), 1, st, D.L.invdiag);
     }
     TIMED(MG_KF_RESID, nB(l) * (sizeof(TU) * (uz ? 1 : 2) + sizeof(TH)) + (uz ? 0.0 : bytes_A(l)) +
                            (double)D.L.n * sizeof(C),
-          ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TH), D.L, B(), lbs, f, u, uz, 1, s));
+          PCV_SPLIT(ROWS_LAUNCH_F(D, l == 0, k_resid, (PCVv, C, TU, TH), D.L, B(), lbs, f, u, uz, 1, s)));
     return conv_add(l, cB(l), pl.KB, s, eta(l) * theta(l), u, uz, st);
   }
 
@@ -856,8 +960,8 @@ struct Engine final : EngineBase {
       return MG_OK;
     }
     TIMED(MG_KF_RESID, nB(l) * sizeof(TU) * (uz ? 2 : 3) + (uz ? 0.0 : bytes_A(l)),
-          ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TU), D.L, B(), lbs, f, u, uz, 0,
-                             D.r));
+          PCV_SPLIT(ROWS_LAUNCH_F(D, l == 0, k_resid, (PCVv, C, TU, TU), D.L, B(), lbs, f, u, uz, 0,
+                             D.r)));
     const double rbytes = nB(l) * 2 * sizeof(TU) + (double)D.L.wg * D.L.n * 4 + (double)D.L.n * sizeof(C) +
                           bytes_X(D.R) + nB(l + 1) * sizeof(TU);
     if (K == 1) {
@@ -907,7 +1011,8 @@ struct Engine final : EngineBase {
 
   mg_status coarse(const TU* f, TU* u, int trans, hipStream_t st) {
     const int n = pl.lv[pl.J - 1].n;
-    hipLaunchKernelGGL((k_coarse<TU>), dim3(nblocks((long)n * B())), dim3(256), 0, st, n, B(), Ainv, f, u, trans);
+    hipLaunchKernelGGL((k_coarse<TU>), dim3(nblocks((long)n * B())), dim3(256), 0, st, n, B(), Ainv, f, u, trans,
+                       pl.nv ? 1 : 0, (const int*)d[pl.J - 1].L.vmap);
     LAUNCH_OK();
     return MG_OK;
   }
@@ -979,19 +1084,19 @@ struct Engine final : EngineBase {
     const double ob = nb0 * 16 + (double)L64.w * L64.n * 12 + (double)L64.n * 8 + (r64 ? nb0 * 8 : 0.0) +
                       (rc ? nb0 * sizeof(TR) : 0.0) + (e ? nb0 * (sizeof(TU) + 8) : 0.0);
     if (e) {
-      TIMED(MG_KF_OUTER, ob,
-            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, true, TR, TU>), dim3(g), dim3(256), 0, st, L64,
+      TIMED(MG_KF_OUTER, ob, PCV_SPLIT(
+            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, true, PCVv, TR, TU>), dim3(g), dim3(256), 0, st, L64,
                                               BF(), lbsF, outer_chunk(), f, u, r64, rc, part, e, act, uo, Bc, map);
-            else hipLaunchKernelGGL((k_outer_resid<false, true, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
-                                    lbsF, outer_chunk(), f, u, r64, rc, part, e, act, uo, Bc, map));
+            else hipLaunchKernelGGL((k_outer_resid<false, true, PCVv, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
+                                    lbsF, outer_chunk(), f, u, r64, rc, part, e, act, uo, Bc, map)));
     } else {
-      TIMED(MG_KF_OUTER, ob,
-            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, false, TR, TU>), dim3(g), dim3(256), 0, st, L64,
+      TIMED(MG_KF_OUTER, ob, PCV_SPLIT(
+            if (lbsF == 6) hipLaunchKernelGGL((k_outer_resid<true, false, PCVv, TR, TU>), dim3(g), dim3(256), 0, st, L64,
                                               BF(), lbsF, outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr,
                                               (const int*)nullptr, (double*)nullptr, Bc, map);
-            else hipLaunchKernelGGL((k_outer_resid<false, false, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
+            else hipLaunchKernelGGL((k_outer_resid<false, false, PCVv, TR, TU>), dim3(g), dim3(256), 0, st, L64, BF(),
                                     lbsF, outer_chunk(), f, u, r64, rc, part, (const TU*)nullptr, (const int*)nullptr,
-                                    (double*)nullptr, Bc, map));
+                                    (double*)nullptr, Bc, map)));
     }
     if (nrm) {
       hipLaunchKernelGGL(k_norm_final, dim3(BF()), dim3(256), 0, st, part, (int)g, BF(), nrm, e ? act : nullptr);
@@ -1036,6 +1141,17 @@ struct Engine final : EngineBase {
     LAUNCH_OK();
     std::swap(r0, e0);
     for (int b = 0; b < F; ++b) hcur[b] = hnew[b];
+    if (pl.nv) {
+      // per-column operators: slot s uses the operator of the column it holds (padding: column 0)
+      int* hv = hfrom;   // the repack sources were uploaded above; reuse after a sync
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int c = 0; c < Bn; ++c) hv[c] = 0;
+      for (int b = 0; b < F; ++b)
+        if (hnew[b] >= 0) hv[hnew[b]] = b;
+      HIP_TRY(hipMemcpyAsync(vmapd, hv, Bn * sizeof(int), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      set_vmap(vmapd);
+    }
     compacted = true;
     set_width(Bn);
     return MG_OK;
@@ -1044,7 +1160,14 @@ struct Engine final : EngineBase {
     if (!compacted) return;
     compacted = false;
     hcur.clear();
+    if (pl.nv) set_vmap(nullptr);
     set_width(BF());
+  }
+  // the vector-to-operator column map of every level's sweeps (and the coarse tail's copies)
+  void set_vmap(const int* vm) {
+    for (auto& x : d) x.L.vmap = vm;
+    for (auto& t : tails)
+      for (int q = 0; q < t.nl; ++q) t.lv[q].L.vmap = vm;
   }
 
   mg_status residual(const double* f, const double* u, double* r, double* nrm, hipStream_t st) override {
@@ -1330,6 +1453,7 @@ struct Engine final : EngineBase {
   // A Z_m = V_{m+1} H_m holds to FP64 rounding whatever C does.
   mg_status fgmres(const double* f, double* x, const mg_krylov_options* o, void* work, size_t wbytes,
                    mg_rhs_info* info, hipStream_t st) override {
+    if (pl.nv) return fail(MG_ERR_UNSUPPORTED, "FGMRES with per-column operators is not built");
     const int m = o->restart, Bn = B(), n0 = pl.lv[0].n;
     const long n0B = (long)n0 * Bn;
     Kr k;
@@ -1499,7 +1623,7 @@ struct Engine final : EngineBase {
       MG_TRY(smooth(l, f, D.ut, uz, D.S[j], st));
       uz = 0;
     }
-    ROWS_LAUNCH_F(D, l == 0, k_resid, (C, TU, TU), D.L, B(), lbs, f, (const TU*)D.ut, uz,
+    ROWS_LAUNCH_F(D, l == 0, k_resid, (false, C, TU, TU), D.L, B(), lbs, f, (const TU*)D.ut, uz,
                        0, D.Rv);
     LAUNCH_OK();
     const TU* ec = ck.u[l + 1];
@@ -1679,6 +1803,25 @@ mg_status mg_set_params(mg_ctx* c, const double* v, void* stream) {
   g_err.clear();
   if (!c || !v) return fail(MG_ERR_INVALID_ARG, "null argument");
   return c->e->set_params(v, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_load_column(mg_ctx* c, int32_t b, const double* const* values, void* stream) {
+  g_err.clear();
+  if (!c) return fail(MG_ERR_INVALID_ARG, "null context");
+  return c->e->load_column(b, values, static_cast<hipStream_t>(stream));
+}
+
+mg_status mg_set_solver_options(mg_ctx* c, int32_t max_outer, int32_t check_every, double rtol,
+                                double diverge_factor) {
+  g_err.clear();
+  if (!c) return fail(MG_ERR_INVALID_ARG, "null context");
+  if (max_outer < 1 || check_every < 1 || !(rtol >= 0.0))
+    return fail(MG_ERR_INVALID_ARG, "max_outer and check_every must be >= 1, rtol >= 0");
+  c->e->pl.max_outer = max_outer;
+  c->e->pl.check_every = check_every;
+  c->e->pl.rtol = rtol;
+  c->e->pl.divf = diverge_factor;
+  return MG_OK;
 }
 
 mg_status mg_vcycle(mg_ctx* c, const void* f, void* u, void* ckpt, void* stream) {

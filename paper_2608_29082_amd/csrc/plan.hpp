@@ -76,6 +76,8 @@ struct HLevel {
   std::vector<double> invdeg;   // row scale of the aggregation operator
   std::vector<double> gval;     // edge weights in the graph's slots (weighted / symmetric aggregation)
   bool sym_graph = false, sym_A = false;
+  // per-column operators (HostPlan::nv > 0): off-diagonal values [w][ld][nv] and diagonal [ld][nv]
+  std::vector<double> offv, diagv;
 };
 
 // fn(r0, r1) over a split of [0, n) into contiguous ranges, one host thread
@@ -344,7 +346,43 @@ struct HostPlan {
   std::vector<double> Acoarse;   // dense n_J x n_J row-major
   std::vector<double> params;   // power-series coefficients (converted from the caller's basis)
   bool sym_all = true;
+  int nv = 0;                    // columns with their own operator values (0: shared)
+  std::vector<double> AcoarseV;  // nv > 0: [nv][n_J][n_J], each column's dense coarsest operator
+  // nv > 0: the CSR pattern of every A_l (rowptr, col), kept to place a new column's values
+  std::vector<std::vector<int32_t>> prow, pcol;
 };
+
+// One column's operator on the ELL layout of level L (built from the same
+// pattern): off[k * ld + i] the k-th off-diagonal entry of row i (CSR order,
+// padding 0), dg[i] the diagonal (rows [n, ld): 1).  The values must be finite
+// with nonzero off-diagonal entries and diagonal, so the column's graph is the
+// pattern's.
+mg_status column_arrays(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b) {
+  const int n = A->nrows, ld = L.off.ld, w = L.off.w;
+  std::fill(off, off + (size_t)w * ld, 0.0);
+  std::fill(dg, dg + ld, 1.0);
+  for (int i = 0; i < n; ++i) {
+    int k = 0;
+    bool has_diag = false;
+    for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+      const double x = v[p];
+      if (!std::isfinite(x) || x == 0.0)
+        return fail(MG_ERR_SHAPE, "column " + std::to_string(b) + " of A[" + std::to_string(l) +
+                                      "]: zero or non-finite value on the pattern at row " + std::to_string(i));
+      if (A->col[p] == i) {
+        dg[i] = x;
+        has_diag = true;
+      } else {
+        if (k >= w) return fail(MG_ERR_SHAPE, "column values do not fit the pattern's width");
+        off[(size_t)k * ld + i] = x;
+        ++k;
+      }
+    }
+    if (!has_diag)
+      return fail(MG_ERR_SHAPE, "A[" + std::to_string(l) + "]: no diagonal entry at row " + std::to_string(i));
+  }
+  return MG_OK;
+}
 
 // Coefficients of the Chebyshev polynomials, T_k(t) = sum_m t[k][m] t^m, k, m <= 8.
 ChebTab cheb_table() {
@@ -416,6 +454,16 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
         return fail(MG_ERR_SHAPE, "R[" + std::to_string(l) + "] must be n_{l+1} x n_l");
     }
   }
+  if (h->ncolumn_values != 0) {
+    if (h->ncolumn_values != o->nrhs || !h->column_values)
+      return fail(MG_ERR_INVALID_ARG, "ncolumn_values must be 0 or nrhs, with column_values");
+    if (p->aggregation != MG_AGG_MEAN)
+      return fail(MG_ERR_UNSUPPORTED, "per-column operators support the mean aggregation only");
+    if (o->flags & MG_FLAG_BACKWARD) return fail(MG_ERR_UNSUPPORTED, "per-column operators have no reverse sweep");
+    for (int q = 0; q < J * o->nrhs; ++q)
+      if (!h->column_values[q]) return fail(MG_ERR_INVALID_ARG, "null column_values entry");
+    pl.nv = o->nrhs;
+  }
   if (J > 32) return fail(MG_ERR_UNSUPPORTED, "at most 32 levels");
   if (h->A[J - 1].nrows > 4096) return fail(MG_ERR_UNSUPPORTED, "coarsest level larger than 4096 unknowns");
   if (p->values == nullptr) return fail(MG_ERR_INVALID_ARG, "params.values is null");
@@ -426,7 +474,25 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
   to_power_series(pl.params, J, p->KB, p->KR, p->KP, p->basis);
   pl.lv.resize(J);
   for (int l = 0; l < J; ++l) {
-    if (full) {
+    if (full && pl.nv) {
+      // the pattern with column 0's values, then every column's arrays on its slots
+      mg_csr a0 = h->A[l];
+      a0.val = h->column_values[(size_t)l * pl.nv];
+      HLevel& L = pl.lv[l];
+      MG_TRY(build_level(&a0, h->G ? &h->G[l] : nullptr, L, l, p->aggregation, false));
+      const int w = L.off.w, ld = L.off.ld, nv = pl.nv;
+      L.offv.assign((size_t)w * ld * nv, 0.0);
+      L.diagv.assign((size_t)ld * nv, 1.0);
+      std::vector<double> off((size_t)w * ld), dg(ld);
+      for (int b = 0; b < nv; ++b) {
+        MG_TRY(column_arrays(&h->A[l], h->column_values[(size_t)l * nv + b], L, off.data(), dg.data(), l, b));
+        for (size_t q = 0; q < off.size(); ++q) L.offv[q * nv + b] = off[q];
+        for (int i = 0; i < ld; ++i) L.diagv[(size_t)i * nv + b] = dg[i];
+      }
+      pl.sym_all = false;
+      pl.prow.emplace_back(h->A[l].rowptr, h->A[l].rowptr + h->A[l].nrows + 1);
+      pl.pcol.emplace_back(h->A[l].col, h->A[l].col + h->A[l].nnz);
+    } else if (full) {
       MG_TRY(build_level(&h->A[l], h->G ? &h->G[l] : nullptr, pl.lv[l], l, p->aggregation,
                          (o->flags & MG_FLAG_BACKWARD) != 0));
       pl.sym_all = pl.sym_all && pl.lv[l].sym_A && pl.lv[l].sym_graph;
@@ -488,8 +554,18 @@ mg_status build_plan(const mg_hierarchy* h, const mg_params* p, const mg_options
     const mg_csr* Ac = &h->A[J - 1];
     const int n = Ac->nrows;
     pl.Acoarse.assign((size_t)n * n, 0.0);
+    const double* av = pl.nv ? h->column_values[(size_t)(J - 1) * pl.nv] : Ac->val;
     for (int i = 0; i < n; ++i)
-      for (int q = Ac->rowptr[i]; q < Ac->rowptr[i + 1]; ++q) pl.Acoarse[(size_t)i * n + Ac->col[q]] = Ac->val[q];
+      for (int q = Ac->rowptr[i]; q < Ac->rowptr[i + 1]; ++q) pl.Acoarse[(size_t)i * n + Ac->col[q]] = av[q];
+    if (pl.nv) {
+      pl.AcoarseV.assign((size_t)pl.nv * n * n, 0.0);
+      for (int b = 0; b < pl.nv; ++b) {
+        const double* cv = h->column_values[(size_t)(J - 1) * pl.nv + b];
+        double* Ab = &pl.AcoarseV[(size_t)b * n * n];
+        for (int i = 0; i < n; ++i)
+          for (int q = Ac->rowptr[i]; q < Ac->rowptr[i + 1]; ++q) Ab[(size_t)i * n + Ac->col[q]] = cv[q];
+      }
+    }
   }
   return MG_OK;
 }
