@@ -50,6 +50,7 @@ class Result:
     t_done: float
     footprint: int
     u: np.ndarray | None = None
+    fallback: bool = False      # solved with the classical parameters after the learned cycle diverged
 
     @property
     def latency(self) -> float:
@@ -201,11 +202,13 @@ class Server:
                     run = (lambda: ctx.fgmres(f, u, restart=self.restart, max_iter=self.max_outer, rtol=self.rtol,
                                               work=work)) if self.solver == "fgmres" else (lambda: ctx.solve(f, u))
                     info = run()
+                    fell = False
                     if info.status[0] != 0 and self.theta is not None:
                         # learned parameters failed on this request: classical cycle
                         ctx.set_params(self.PR.identity(ctx.J, self.K, self.K, self.K))
                         u.zero_()
                         info = run()
+                        fell = True
                         with lock:
                             self.fallbacks += 1
                     u_host = u.cpu().numpy() if self.keep else None
@@ -217,7 +220,7 @@ class Server:
                 with lock:
                     results.append(Result(req.rid, req.side, req.f.shape[0], int(info.iters[0]),
                                           float(info.relres[0]), int(info.status[0]), t_arr, t_adm, t_start,
-                                          t_done, fp, u_host))
+                                          t_done, fp, u_host, fell))
 
         setups = [threading.Thread(target=setup_worker, daemon=True) for _ in range(self.setup_threads)]
         solvers = [threading.Thread(target=solve_worker, daemon=True) for _ in range(self.slots)]
@@ -241,6 +244,292 @@ class Server:
         wall = now()
         done = [r for r in results if r is not None]
         return done, errors, wall
+
+
+def pattern_key(hier) -> str:
+    """Key of a native hierarchy's level patterns (row pointers and columns of
+    every A_l): requests with equal keys can share a batch context."""
+    import hashlib
+    hs = hashlib.sha1()
+    for l in range(hier.nlevels):
+        m = hier.view.A[l]
+        hs.update(np.ctypeslib.as_array(m.rowptr, shape=(m.nrows + 1,)).tobytes())
+        hs.update(np.ctypeslib.as_array(m.col, shape=(max(int(m.nnz), 1),))[: int(m.nnz)].tobytes())
+    return f"{hier.sizes[0]}:{hs.hexdigest()[:16]}"
+
+
+class BatchServer:
+    """Continuous batching of solve requests (stationary refinement solver).
+
+    Requests whose hierarchies have the same level patterns (in practice: the
+    same grid side) share one batch context of `capacity` column slots with
+    per-column operators (mg_hierarchy.ncolumn_values): each request brings its
+    own coefficient field's operators into its slot (mg_load_column), its right-
+    hand side into column b of f and a zero start into column b of u.  A group
+    worker (one thread and HIP stream per batch, so batches of different sides
+    overlap on the GPU) runs rounds of at most `cycles_per_round` refinement
+    cycles (mg_solve); between rounds it takes finished requests out and puts
+    waiting ones into the free slots, so a request that arrives while others
+    run starts at the next round boundary.  The iteration u <- u + LMG(A, f - A u, 0)
+    depends only on the current iterate, so a request's iterates, cycle count
+    and result are the same whatever the rounds and whatever the other columns
+    hold (columns are independent; empty slots carry f = 0 and are skipped by
+    the solver's column compaction).  Each batch's device footprint (workspace,
+    tile lists excluded, plus f and u) is acquired from the HBM budget before its
+    context is set up and released when the batch retires.  A request whose
+    learned cycle diverges is solved again on its own with the classical
+    parameters (counted in `fallbacks`)."""
+
+    def __init__(self, theta=None, J_src=None, K=3, precision="fp32", capacity=32, cycles_per_round=8,
+                 setup_threads=4, hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False,
+                 device="cuda:0", fail_setup=None, diverge_factor=1e6):
+        import torch
+        from . import binding as Bd
+        from . import params as PR
+        self.torch, self.Bd, self.PR = torch, Bd, PR
+        self.theta, self.J_src, self.K = theta, J_src, K
+        self.precision, self.capacity = precision, capacity
+        self.diverge_factor = diverge_factor
+        self.cycles_per_round, self.setup_threads = cycles_per_round, setup_threads
+        self.budget = _Budget(hbm_budget)
+        self.rtol, self.max_outer, self.keep = rtol, max_outer, keep_solution
+        self.device = torch.device(device)
+        self.peak_used = 0
+        self.fallbacks = 0
+        self.batches = 0
+        self.fail_setup = fail_setup
+        self._single = Server(theta, J_src, K, precision, slots=1, setup_threads=1, hbm_budget=hbm_budget, rtol=rtol,
+                              max_outer=max_outer, keep_solution=keep_solution, device=device)
+
+    def _params(self, J, side):
+        return self._single._params(J, side)
+
+    def _footprint(self, hier, params) -> int:
+        import ctypes as Cc
+        Bd, K, cap = self.Bd, self.K, self.capacity
+        lib = Bd.load_library()
+        p = np.ascontiguousarray(params)
+        pr = Bd._Params(K, K, K, 2, 2, p.ctypes.data_as(Cc.POINTER(Cc.c_double)))
+        o = Bd._Options(Bd.PRECISIONS[self.precision], cap, self.max_outer, 2, self.rtol, 1e6, 0)
+        hh = Bd._Hier()
+        Cc.memmove(Cc.byref(hh), Cc.byref(hier.view), Cc.sizeof(Bd._Hier))
+        vals = (Cc.POINTER(Cc.c_double) * (hier.nlevels * cap))()
+        for l in range(hier.nlevels):
+            for b in range(cap):
+                vals[l * cap + b] = hier.view.A[l].val
+        hh.ncolumn_values = cap
+        hh.column_values = vals
+        ws, ck = Cc.c_size_t(), Cc.c_size_t()
+        Bd._check(lib.mg_workspace_bytes(Cc.byref(hh), Cc.byref(pr), Cc.byref(o), Cc.byref(ws), Cc.byref(ck)),
+                  "mg_workspace_bytes")
+        return int(ws.value) + 2 * hier.sizes[0] * cap * 8
+
+    def run(self, requests, open_loop=True):
+        """Serve `requests` (sorted by arrival).  open_loop: each request enters
+        at its arrival time; otherwise all are queued at t = 0 (saturation)."""
+        torch, Bd = self.torch, self.Bd
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        incoming: queue.Queue = queue.Queue()
+        results, errors = [], []
+        lock = threading.Lock()
+        groups = {}          # pattern key -> group record
+        workers = []
+        setups_done = threading.Event()
+        # built hierarchies wait on the host until a slot takes them: at most 2 * capacity per side
+        side_slots = {}
+
+        def side_sem(side):
+            with lock:
+                if side not in side_slots:
+                    side_slots[side] = threading.Semaphore(2 * self.capacity)
+                return side_slots[side]
+
+        class Group:
+            def __init__(self, key):
+                self.key = key
+                self.q: queue.Queue = queue.Queue()
+
+        def admit(item):
+            """Put a set-up request into its batch group, creating the group (and its worker) on first use."""
+            key = item[3]
+            with lock:
+                g = groups.get(key)
+                if g is None:
+                    g = groups[key] = Group(key)
+                    th = threading.Thread(target=group_worker, args=(g,), daemon=True)
+                    workers.append(th)
+                    th.start()
+            g.q.put(item)
+
+        def setup_worker():
+            while True:
+                it = incoming.get()
+                if it is None:
+                    return
+                req, t_arr = it
+                hier = None
+                sem = side_sem(req.side)
+                sem.acquire()
+                try:
+                    hier = Bd.SquareHierarchy(req.side, req.blocks)
+                    if self.fail_setup is not None and self.fail_setup(req):
+                        raise RuntimeError(f"setup of request {req.rid} failed (injected)")
+                    admit((req, t_arr, hier, pattern_key(hier)))
+                except Exception as e:  # report and keep serving
+                    if hier is not None:
+                        hier.close()
+                    sem.release()
+                    with lock:
+                        errors.append((req.rid, repr(e)))
+
+        def finish(req, t_arr, t_adm, t_start, iters, relres, status, fp, u_host, fell=False):
+            with lock:
+                results.append(Result(req.rid, req.side, req.f.shape[0], iters, relres, status, t_arr, t_adm, t_start,
+                                      now(), fp, u_host, fell))
+
+        def fallback(req, t_arr, t_adm, t_start, iters, fp):
+            # the learned cycle diverged on this request: the classical cycle on its own
+            res, errs, _ = self._single.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
+            with lock:
+                self.fallbacks += 1
+            if res:
+                r = res[0]
+                finish(req, t_arr, t_adm, t_start, r.iters, r.relres, r.status, fp, r.u, True)
+            else:
+                with lock:
+                    errors.append((req.rid, "fallback failed: " + repr(errs[:1])))
+
+        def group_worker(g):
+            stream = torch.cuda.Stream(device=self.device)
+            cap = self.capacity
+            ctx = None
+            fp = 0
+            slots = [None] * cap      # (req, t_arr, t_adm, t_start, iters so far)
+            pending = []
+            try:
+                with torch.cuda.stream(stream):
+                    first = g.q.get()
+                    pending.append(first)
+                    req0, _, hier0, _ = first
+                    params = self._params(hier0.nlevels, req0.side)
+                    fp = self._footprint(hier0, params)
+                    self.budget.acquire(fp)
+                    with lock:
+                        self.peak_used = max(self.peak_used, self.budget.used)
+                        self.batches += 1
+                    ctx = Bd.Context(None, None, params, self.K, self.K, self.K, precision=self.precision, nrhs=cap,
+                                     max_outer=self.cycles_per_round, check_every=2, rtol=self.rtol, stream=stream,
+                                     device=self.device, native=hier0, columns=[hier0] * cap)
+                    n = hier0.sizes[0]
+                    f = torch.zeros((n, cap), dtype=torch.float64, device=self.device)
+                    u = torch.zeros_like(f)
+                    while True:
+                        # fill free slots with waiting requests of this group
+                        while True:
+                            free = [b for b in range(cap) if slots[b] is None]
+                            if not free:
+                                break
+                            if not pending:
+                                try:
+                                    pending.append(g.q.get_nowait())
+                                except queue.Empty:
+                                    break
+                            req, t_arr, hier, _ = pending.pop(0)
+                            b = free[0]
+                            try:
+                                ctx.load_column(b, hier)
+                            finally:
+                                hier.close()
+                                side_sem(req.side).release()
+                            f[:, b] = torch.as_tensor(req.f[:, 0], device=self.device)
+                            u[:, b] = 0.0
+                            slots[b] = [req, t_arr, now(), None, 0]
+                        busy = [b for b in range(cap) if slots[b] is not None]
+                        if not busy:
+                            if setups_done.is_set() and g.q.empty():
+                                break
+                            try:
+                                pending.append(g.q.get(timeout=0.05))
+                            except queue.Empty:
+                                pass
+                            continue
+                        t_round = now()
+                        for b in busy:
+                            if slots[b][3] is None:
+                                slots[b][3] = t_round
+                        info = ctx.solve(f, u)
+                        for b in busy:
+                            req, t_arr, t_adm, t_start, it = slots[b]
+                            it += int(info.iters[b])
+                            st = int(info.status[b])
+                            # divergence as the per-request solver sees it: the residual against its
+                            # start (u = 0, so ||f||), not against the start of this round
+                            if st != 0 and not (float(info.relres[b]) <= self.diverge_factor):
+                                st = 6
+                            done = st == 0 or st == 6 or it >= self.max_outer
+                            if not done:
+                                slots[b][4] = it
+                                continue
+                            slots[b] = None
+                            if st == 6 and self.theta is not None:
+                                f[:, b] = 0.0
+                                u[:, b] = 0.0
+                                fallback(req, t_arr, t_adm, t_start, it, fp)
+                                continue
+                            u_host = u[:, b].cpu().numpy()[:, None] if self.keep else None
+                            stream.synchronize()
+                            finish(req, t_arr, t_adm, t_start, it, float(info.relres[b]), 0 if st == 0 else
+                                   (6 if st == 6 else 5), fp, u_host)
+                            f[:, b] = 0.0
+                            u[:, b] = 0.0
+                    stream.synchronize()
+            except Exception as e:
+                # the batch failed: report every request it held or would have taken
+                left = [sl[0] for sl in slots if sl is not None]
+                waiting = list(pending)
+                while True:
+                    try:
+                        waiting.append(g.q.get_nowait())
+                    except queue.Empty:
+                        break
+                for rq, _, hh, _ in waiting:   # built hierarchies never loaded: free them
+                    hh.close()
+                    side_sem(rq.side).release()
+                left += [it[0] for it in waiting]
+                with lock:
+                    errors.append(("group " + g.key, repr(e)))
+                    for rq in left:
+                        errors.append((rq.rid, "batch failed"))
+            finally:
+                if ctx is not None:
+                    ctx.close()
+                if fp:
+                    self.budget.release(fp)
+
+        setups = [threading.Thread(target=setup_worker, daemon=True) for _ in range(self.setup_threads)]
+        for t in setups:
+            t.start()
+        for req in requests:
+            if open_loop:
+                delay = req.arrival - now()
+                if delay > 0:
+                    time.sleep(delay)
+            incoming.put((req, req.arrival if open_loop else 0.0))
+        for _ in setups:
+            incoming.put(None)
+        for t in setups:
+            t.join()
+        setups_done.set()
+        while True:
+            with lock:
+                ws = list(workers)
+            if all(not w.is_alive() for w in ws):
+                break
+            for w in ws:
+                w.join(timeout=0.1)
+        wall = now()
+        return results, errors, wall
 
 
 def krylov_bytes_bound(n: int, B: int, m: int) -> int:

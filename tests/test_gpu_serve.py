@@ -98,3 +98,74 @@ def test_failed_setup_returns_its_budget():
     assert sorted(r.rid for r in res2) == [1, 3, 4]
     assert all(r.status == 0 for r in res2)
     assert srv.budget.used == 0
+
+
+def _batch_server(**kw):
+    from paper_2608_29082_amd import params as PR
+    from paper_2608_29082_amd import serve as S
+    theta = {}
+    for side in (65, 129, 257):
+        f = PR.default_file(f"serving-{side}", 3)
+        if f:
+            th, meta = PR.load(f)
+            theta[side] = (th, meta["J"])
+    return S.BatchServer(theta, None, keep_solution=True, **kw)
+
+
+def test_batched_stream_converges_and_is_invariant():
+    """Continuous batching: 40 requests of three sides (more than the 16 column
+    slots per side, so slots are refilled between rounds) all reach 1e-8 in
+    FP64 on the host; a request served alone (alone in its batch) and in the
+    stream gives the same cycle count and the same bits; the batches overlap."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(40, 0.0, seed=8, sides=(65, 129, 257))
+    srv = _batch_server(capacity=16, cycles_per_round=6)
+    res, errs, wall = srv.run(reqs, open_loop=False)
+    assert not errs and len(res) == len(reqs), errs[:3]
+    byid = {r.rid: r for r in res}
+    for q in reqs:
+        r = byid[q.rid]
+        assert r.status == 0 and _relres(q, r.u) <= 1e-8, (q.side, r.relres)
+    print(f"batched: {len(res)} requests in {wall:.2f} s, {srv.batches} batches, fallbacks {srv.fallbacks}",
+          flush=True)
+    for q in reqs[:5]:
+        alone, e2, _ = _batch_server(capacity=16, cycles_per_round=5).run([q], open_loop=False)
+        assert not e2 and alone[0].iters == byid[q.rid].iters
+        assert np.array_equal(alone[0].u, byid[q.rid].u)
+
+
+def test_batched_matches_per_request_solver():
+    """The batched loop and the per-request loop solve the same requests to
+    1e-8 with the same cycle counts up to one cycle at the threshold (different
+    launch configurations round differently) and nearly the same iterates."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(12, 0.0, seed=9, sides=(65, 129))
+    rb, eb, _ = _batch_server(capacity=16).run(reqs, open_loop=False)
+    rs, es, _ = _server(slots=3, setup_threads=3).run(reqs, open_loop=False)
+    assert not eb and not es
+    b, s = {r.rid: r for r in rb}, {r.rid: r for r in rs}
+    for q in reqs:
+        # both loops fall back to the classical cycle for the same requests
+        assert b[q.rid].fallback == s[q.rid].fallback
+        assert abs(b[q.rid].iters - s[q.rid].iters) <= 1
+        d = np.abs(b[q.rid].u - s[q.rid].u).max() / np.abs(s[q.rid].u).max()
+        assert d <= 1e-6, d
+
+
+def test_batched_budget_and_failed_setup():
+    """A failed setup is reported and the rest served; with a budget of one
+    batch, batches of different sides run one after the other and the budget
+    comes back to zero."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(10, 0.0, seed=10, sides=(65, 129))
+    probe = _batch_server(capacity=16)
+    hier = __import__("paper_2608_29082_amd.binding", fromlist=["x"]).SquareHierarchy(129, reqs[0].blocks)
+    params = probe._params(hier.nlevels, 129)
+    big = probe._footprint(hier, params)
+    hier.close()
+    srv = _batch_server(capacity=16, hbm_budget=big, fail_setup=lambda q: q.rid == 4)
+    res, errs, _ = srv.run(reqs, open_loop=False)
+    assert [r for r, _ in errs] == [4]
+    assert sorted(r.rid for r in res) == [k for k in range(10) if k != 4]
+    assert all(r.status == 0 for r in res)
+    assert srv.peak_used <= big and srv.budget.used == 0
