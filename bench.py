@@ -63,9 +63,16 @@ def parse():
     ap.add_argument("--no-helmholtz", action="store_true", help="skip the complex Helmholtz section")
     ap.add_argument("--helmholtz-only", action="store_true",
                     help="run only the complex Helmholtz section (no CPU leg) and print its JSON")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-worker", type=int, default=-1, help=argparse.SUPPRESS)
     ap.add_argument("--serving-requests", type=int, default=60,
-                    help="requests per serving run (closed loop, then open loop at 0.5x and 0.8x its rate); 0 skips")
+                    help="requests per run of the per-request serving loop (closed loop, 0.5x its rate, FGMRES); "
+                         "0 skips")
+    ap.add_argument("--batched-requests", type=int, default=1000,
+                    help="requests per run of the continuous-batching loop (closed loop, then open loop at 0.5x "
+                         "and 0.8x its rate); 0 skips")
+    ap.add_argument("--batch-capacity", type=int, default=32, help="column slots per batch of the batched loop")
+    ap.add_argument("--cycles-per-round", type=int, default=8, help="refinement cycles per round of the batched loop")
     return ap.parse_args()
 
 
@@ -81,6 +88,9 @@ def workload(name, K):
 
 def main():
     args = parse()
+    if args.cpu_worker >= 0:
+        cpu_worker(args.cpu_worker, args.cpu_seconds, args.K)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
@@ -223,11 +233,15 @@ def main():
     elif not args.no_krylov:
         out["krylov"] = krylov(args, {"learned_" + args.precision: ctx}, f, w, h, B)
 
+    if not args.no_ablation and args.workload == "diffusion-513":
+        out["cycle_cost"] = cycle_cost(args, h, params, f, B, stream)
+        out["held_out_fields"] = held_out(args, params, stream)
+
     if not args.no_variants:
         out["conv_variants"] = conv_variants(args, h, f, B, stream)
         out["darcy"] = darcy(args)
 
-    if args.serving_requests > 0:
+    if args.serving_requests > 0 or args.batched_requests > 0:
         out["serving"] = serving(args)
 
     if not args.no_helmholtz:
@@ -393,12 +407,17 @@ def level0_kernels(ctx, f, steps=3):
 
 
 def serving(args):
-    """Request loop over the serving stream (sides 65..1025, log10 a ~ U(-2, 2)
-    on 16 x 16 blocks, f ~ N(0, 1), per-size trained FP32 parameters, FP64
-    refinement to 1e-8): closed loop to find the saturated rate T, then Poisson
-    arrivals at 0.5 T and 0.8 T; then the same with flexible GMRES(30) around
-    the learned cycle (closed loop and 0.5 T).  Latency = done - arrival, setup
-    included."""
+    """Request loops over the serving stream (sides uniform over 65..1025, log10 a
+    ~ U(-2, 2) on 16 x 16 blocks per request, f ~ N(0, 1), per-size trained FP32
+    parameters, FP64 refinement to 1e-8).  Latency = done - arrival, setup
+    (the request's hierarchy) included.
+      * batched: continuous batching (serve.BatchServer, per-column operators,
+        capacity columns per grid, slots refilled between rounds): closed loop
+        over --batched-requests requests for the saturated rate T, then Poisson
+        arrivals at 0.5 T and 0.8 T;
+      * per_request: one context per request (serve.Server, B = 1) on
+        --serving-requests requests, closed loop and 0.5 T, and flexible
+        GMRES(30) around the learned cycle (closed loop)."""
     from paper_2608_29082_amd import params as PR
     from paper_2608_29082_amd import serve as S
     theta = {}
@@ -407,27 +426,52 @@ def serving(args):
         if f:
             th, meta = PR.load(f)
             theta[side] = (th, meta["J"])
-    runs = {}
-    reqs = S.make_stream(args.serving_requests, 0.0, seed=11)
-    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8).run(reqs, open_loop=False)
-    runs["closed_loop"] = S.summarize(res, wall)
-    T = runs["closed_loop"]["solves_per_s"]
-    for frac in (0.5, 0.8):
-        reqs = S.make_stream(args.serving_requests, frac * T, seed=12)
-        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8).run(reqs, open_loop=True)
-        runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T)
-    # the same streams with flexible GMRES around the learned cycle (Sec. 4.2)
-    reqs = S.make_stream(args.serving_requests, 0.0, seed=11)
-    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, solver="fgmres").run(reqs, open_loop=False)
-    runs["fgmres_closed_loop"] = S.summarize(res, wall)
-    Tf = runs["fgmres_closed_loop"]["solves_per_s"]
-    reqs = S.make_stream(args.serving_requests, 0.5 * Tf, seed=12)
-    res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, solver="fgmres").run(reqs, open_loop=True)
-    runs["fgmres_open_loop_0.5T"] = dict(S.summarize(res, wall), qps=0.5 * Tf)
-    for r in runs.values():
-        r.pop("by_side", None)
-    print(f"# serving: {json.dumps(runs)}", file=sys.stderr, flush=True)
-    return {"requests_per_run": args.serving_requests, "sides": [65, 129, 257, 513, 1025], **runs}
+    out = {"sides": [65, 129, 257, 513, 1025]}
+    budget = 96 << 30
+    if args.batched_requests > 0:
+        nb = args.batched_requests
+        runs = {}
+
+        def bsrv():
+            return S.BatchServer(theta, None, capacity=args.batch_capacity, cycles_per_round=args.cycles_per_round,
+                                 setup_threads=16, hbm_budget=budget, progress=True)
+        srv = bsrv()
+        res, errs, wall = srv.run(S.make_stream(nb, 0.0, seed=11), open_loop=False)
+        runs["closed_loop"] = dict(S.summarize(res, wall), errors=len(errs), batches=srv.batches,
+                                   fallbacks=srv.fallbacks)
+        print(f"# batched closed loop: {runs['closed_loop']['solves_per_s']:.1f} solves/s over {nb} requests",
+              file=sys.stderr, flush=True)
+        T = runs["closed_loop"]["solves_per_s"]
+        for frac in (0.5, 0.8):
+            srv = bsrv()
+            res, errs, wall = srv.run(S.make_stream(nb, frac * T, seed=12), open_loop=True)
+            runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T, errors=len(errs),
+                                              fallbacks=srv.fallbacks)
+            print(f"# batched open loop {frac} T: p50 {runs[f'open_loop_{frac}T']['p50_ms']:.1f} ms, "
+                  f"p99 {runs[f'open_loop_{frac}T']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out["batched"] = dict(requests_per_run=nb, capacity=args.batch_capacity,
+                              cycles_per_round=args.cycles_per_round, **runs)
+    if args.serving_requests > 0:
+        n1 = args.serving_requests
+        runs = {}
+        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, hbm_budget=budget).run(
+            S.make_stream(n1, 0.0, seed=11), open_loop=False)
+        runs["closed_loop"] = S.summarize(res, wall)
+        T = runs["closed_loop"]["solves_per_s"]
+        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, hbm_budget=budget).run(
+            S.make_stream(n1, 0.5 * T, seed=12), open_loop=True)
+        runs["open_loop_0.5T"] = dict(S.summarize(res, wall), qps=0.5 * T)
+        # flexible GMRES around the learned cycle (Sec. 4.2)
+        res, errs, wall = S.Server(theta, None, slots=4, setup_threads=8, solver="fgmres", hbm_budget=budget).run(
+            S.make_stream(n1, 0.0, seed=11), open_loop=False)
+        runs["fgmres_closed_loop"] = S.summarize(res, wall)
+        out["per_request"] = dict(requests_per_run=n1, **runs)
+    for grp in ("batched", "per_request"):
+        for r in out.get(grp, {}).values():
+            if isinstance(r, dict):
+                r.pop("by_side", None)
+    print(f"# serving: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 def helmholtz(args):
@@ -655,6 +699,69 @@ def unbatched(args, h, params, f, stream, cols=4):
     return out
 
 
+def cycle_cost(args, h, params, f, B, stream):
+    """Where the time goes (paper Sec. 4.2: a learnable cycle costs about 1.5 classical
+    ones; Sec. 3: graph convolutions are expensive on large problems): ms per FP32
+    refinement step (one V(2,2) cycle on all levels, FP64 residual and update) on
+    the benchmark hierarchy and right-hand sides, learned K = 3 cycle against the
+    classical K = 0 cycle (identity parameters), both FP32, the fused convolution
+    and the coarse tail in both; beside the per-hop byte model's ratio of vector
+    passes on a level, 2 nu 3 (K + 1) + (3 K + 1.25) + (3 K + 2.25) against 6 nu + 4.5."""
+    import torch
+    from mginputs import configs as C
+    from paper_2608_29082_amd import binding as Bd
+    J = h.nlevels
+    out = {}
+    for name, K, prm in (("learned_K3", args.K, params), ("classical_K0", 0, C.identity_params(J, 0, 0, 0))):
+        ctx = Bd.Context(h.A, h.P, prm, K, K, K, precision="fp32", nrhs=B, stream=stream)
+        u = torch.zeros_like(f)
+        for _ in range(3):
+            ctx.refine_step(f, u, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 30
+        for _ in range(steps):
+            ctx.refine_step(f, u, u)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_cycle": 1e3 * (time.perf_counter() - t0) / steps}
+        ctx.close()
+    nu, K = 2, args.K
+    out["ratio_learned_over_classical"] = out["learned_K3"]["ms_per_cycle"] / out["classical_K0"]["ms_per_cycle"]
+    out["per_hop_model_ratio"] = (2 * nu * 3 * (K + 1) + (3 * K + 1.25) + (3 * K + 2.25)) / (6 * nu + 4.5)
+    out["paper_ratio"] = 1.5
+    print(f"# cycle cost: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def held_out(args, params, stream, seeds=(10, 11)):
+    """The shipped parameters were trained on coefficient fields 0..4 of the
+    workload's law; solves/s and cycle counts on fields they never saw (same law,
+    right-hand sides of the same distribution), beside the benchmark's field."""
+    import torch
+    from mginputs import configs as C
+    from paper_2608_29082_amd import binding as Bd
+    out = {}
+    for sd in seeds:
+        w2 = C.diffusion_513(seed=sd, B=64)
+        h2 = w2.hier
+        ctx = Bd.Context(h2.A, h2.P, params, args.K, args.K, args.K, precision=args.precision, nrhs=64,
+                         max_outer=args.max_outer, check_every=args.check_every, stream=stream)
+        f2 = torch.tensor(w2.f, dtype=torch.float64, device="cuda:0")
+        u2 = torch.zeros_like(f2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.solve(f2, u2)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rr = np.linalg.norm(w2.f - h2.A[0] @ u2.cpu().numpy(), axis=0) / np.linalg.norm(w2.f, axis=0)
+        out[f"field_{sd}"] = {"value": 64 / dt if info.code == 0 else 0.0, "unit": "solves/s",
+                              "iters_max": int(info.iters.max()), "iters_mean": float(info.iters.mean()),
+                              "relres_max_fp64_host": float(rr.max()), "converged": bool(info.code == 0)}
+        ctx.close()
+    print(f"# held-out fields: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline_helmholtz():
     """The CPU complex128 oracle's FGMRES(40)-FMG solve of one column (the
     training source) of the Helmholtz workload, identity parameters."""
@@ -676,36 +783,82 @@ def cpu_baseline_helmholtz():
             "kind": "oracle", "sample": f"one column (the training source), FGMRES(40)-FMG, {wall:.1f}s wall"}
 
 
-def cpu_baseline(w, params, args, cycles_per_solve):
-    """The CPU FP64 oracle on a bounded sample of the same workload."""
+def cpu_worker(col: int, seconds: float, K: int):
+    """One oracle process (single-threaded BLAS): cycles of the learned V-cycle with the
+    solver's per-cycle FP64 residual on column `col` of the benchmark workload for
+    `seconds`; prints its count as one JSON line."""
     import resource
+    from mginputs import configs as C
     from oracle import lmg as O
+    from paper_2608_29082_amd import params as PR
+    w = C.diffusion_513(B=64)
     h = w.hier
     J = h.nlevels
+    theta, meta = PR.load(PR.default_file("diffusion-513", K))
+    prm = O.unpack(PR.map_levels(theta, meta["J"], J, K, K, K), J, K, K, K)
     lv = O.make_levels(h.A, h.P, h.R)
-    prm = O.unpack(params, J, args.K, args.K, args.K)
-    cols = 2
-    f = w.f[:, :cols]
+    f = w.f[:, col:col + 1]
     A = h.A[0]
     u = np.zeros_like(f)
     ru0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     cycles = 0
-    while True:
-        np.linalg.norm(f - A @ u, axis=0)          # the solver's per-cycle FP64 residual check
+    while time.perf_counter() - t0 < seconds:
+        np.linalg.norm(f - A @ u, axis=0)
         u = O.lmg(lv, prm, 0, f, u)
         cycles += 1
-        if time.perf_counter() - t0 >= args.cpu_seconds:
-            break
     wall = time.perf_counter() - t0
     ru1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
-    per_cycle_per_col = wall / (cycles * cols)
-    return {"value": 1.0 / (per_cycle_per_col * cycles_per_solve), "unit": "solves/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"{cycles} oracle cycles (with the per-cycle FP64 residual) on {cols} of the {w.B} right-hand "
-                      f"sides, {wall:.1f}s wall; solves/s = 1 / (seconds per cycle per column x "
-                      f"{cycles_per_solve:.0f} cycles per solve, the GPU run's mean count)"}
+    print(json.dumps({"cycles": cycles, "wall": wall, "cpu": cpu}), flush=True)
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(w, params, args, cycles_per_solve):
+    """The CPU FP64 oracle on a bounded sample of the same workload, in the two modes
+    of a CPU baseline: one process on one core (single-threaded BLAS), and N
+    independent processes (one right-hand side each) over the host's cores (N =
+    min(cpu_count, 16)).  Each process runs oracle cycles for --cpu-seconds after
+    building its hierarchy (not timed); solves/s = columns x cycles / (seconds x
+    the GPU run's mean cycle count per solve)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    n_host = os.cpu_count() or 1
+    modes = {}
+    for name, nproc in (("single_process", 1), ("all_cores", max(1, min(n_host, 16)))):
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(c),
+                                   "--cpu-seconds", str(args.cpu_seconds), "--K", str(args.K)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env, text=True)
+                 for c in range(nproc)]
+        runs = []
+        for p in procs:
+            outp, _ = p.communicate(timeout=600)
+            runs.append(json.loads(outp.strip().splitlines()[-1]))
+        rate = sum(r["cycles"] / r["wall"] for r in runs)   # column-cycles per second over all processes
+        modes[name] = {"value": rate / cycles_per_solve, "unit": "solves/s", "cores": nproc,
+                       "cycles": [r["cycles"] for r in runs],
+                       "cpu_over_wall": [round(r["cpu"] / r["wall"], 2) for r in runs]}
+        print(f"# cpu baseline {name}: {modes[name]['value']:.4f} solves/s on {nproc} processes",
+              file=sys.stderr, flush=True)
+    allc = modes["all_cores"]
+    return {"value": allc["value"], "unit": "solves/s", "cores": allc["cores"], "kind": "oracle",
+            "sample": f"{allc['cores']} single-threaded oracle processes, one right-hand side each, "
+                      f"{args.cpu_seconds:.0f} s of V-cycles with the per-cycle FP64 residual after the setup; "
+                      f"solves/s = column-cycles per second / {cycles_per_solve:.0f} (the GPU run's mean cycles "
+                      f"per solve)",
+            "single_process": modes["single_process"], "host": host_cpu()}
 
 
 if __name__ == "__main__":

@@ -369,7 +369,7 @@ mg_status mg_timing_read(mg_ctx* ctx, int64_t* launches, double* total_ms, doubl
  * (blocks[bj * nb + bi] > 0 covers [bi/nb, (bi+1)/nb) x [bj/nb, (bj+1)/nb)),
  * P = nested linear interpolation, R = P^T and Galerkin coarse operators
  * A_{l+1} = P^T A_l P (paper Sec. 2.2) symmetrised with off-diagonal
- * round-off residue (|a_ij| <= 1e-14 sqrt(|a_ii a_jj|)) removed; coarsening
+ * round-off residue (|a_ij| <= 1e-11 sqrt(|a_ii a_jj|)) removed; coarsening
  * stops at a coarsest x coarsest interior.  Returns MG_ERR_SHAPE when side
  * does not coarsen to that size.  The object owns its arrays. */
 typedef struct mg_host_hierarchy mg_host_hierarchy;

@@ -8,8 +8,13 @@ operators are either rediscretised on the coarse mesh or Galerkin products
 A_{l+1} = R_l A_l P_l.  Level 0 is the finest (the paper's level 1).
 
 Galerkin products are symmetrised and off-diagonal entries that are round-off
-residue of cancellation (|a_ij| <= 1e-14 sqrt(|a_ii a_jj|)) are removed, so the
-stored pattern of A_l is its graph {(i, j): A_ij != 0} (Sec. 2.1).
+residue of cancellation (|a_ij| <= 1e-11 sqrt(|a_ii a_jj|)) are removed, so the
+stored pattern of A_l is its graph {(i, j): A_ij != 0} (Sec. 2.1).  Couplings
+that are exactly zero (the diagonal direction inside a block of constant
+coefficient) leave a residue that grows with every product, to ~1e-13 of the
+diagonal on the coarsest levels; couplings that are not zero stay above ~1e-4
+of it, so the threshold separates the two and the pattern depends on the grid
+and the block geometry only, not on the coefficient values.
 """
 from __future__ import annotations
 
@@ -20,7 +25,7 @@ import scipy.sparse as sp
 
 from . import fem
 
-DROP_TOL = 1e-14
+DROP_TOL = 1e-11
 
 
 @dataclass

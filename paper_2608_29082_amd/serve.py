@@ -20,6 +20,7 @@ its own context, stream and buffers, and every kernel is deterministic).
 from __future__ import annotations
 
 import queue
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -282,7 +283,7 @@ class BatchServer:
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", capacity=32, cycles_per_round=8,
                  setup_threads=4, hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False,
-                 device="cuda:0", fail_setup=None, diverge_factor=1e6):
+                 device="cuda:0", fail_setup=None, diverge_factor=1e6, progress=False):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -290,6 +291,8 @@ class BatchServer:
         self.theta, self.J_src, self.K = theta, J_src, K
         self.precision, self.capacity = precision, capacity
         self.diverge_factor = diverge_factor
+        self.idle_s = 0.25          # an idle batch retires after this long without requests
+        self.progress = progress    # a line on stderr every ~10 s while batches run
         self.cycles_per_round, self.setup_threads = cycles_per_round, setup_threads
         self.budget = _Budget(hbm_budget)
         self.rtol, self.max_outer, self.keep = rtol, max_outer, keep_solution
@@ -298,11 +301,13 @@ class BatchServer:
         self.fallbacks = 0
         self.batches = 0
         self.fail_setup = fail_setup
-        self._single = Server(theta, J_src, K, precision, slots=1, setup_threads=1, hbm_budget=hbm_budget, rtol=rtol,
-                              max_outer=max_outer, keep_solution=keep_solution, device=device)
+        self._learned = Server(theta, J_src, K, precision, slots=1, setup_threads=1, hbm_budget=hbm_budget,
+                               rtol=rtol, max_outer=max_outer, keep_solution=keep_solution, device=device)
+        self._fallback_args = dict(K=K, precision=precision, slots=1, setup_threads=1, hbm_budget=hbm_budget,
+                                   rtol=rtol, max_outer=max_outer, keep_solution=keep_solution, device=device)
 
     def _params(self, J, side):
-        return self._single._params(J, side)
+        return self._learned._params(J, side)
 
     def _footprint(self, hier, params) -> int:
         import ctypes as Cc
@@ -349,18 +354,30 @@ class BatchServer:
             def __init__(self, key):
                 self.key = key
                 self.q: queue.Queue = queue.Queue()
+                self.alive = True
 
         def admit(item):
-            """Put a set-up request into its batch group, creating the group (and its worker) on first use."""
+            """Put a set-up request into its batch group, creating the group (and its worker) when the
+            grid has none or its batch has retired."""
             key = item[3]
             with lock:
                 g = groups.get(key)
-                if g is None:
+                if g is None or not g.alive:
                     g = groups[key] = Group(key)
                     th = threading.Thread(target=group_worker, args=(g,), daemon=True)
                     workers.append(th)
                     th.start()
-            g.q.put(item)
+                g.q.put(item)
+
+        def retire(g) -> bool:
+            """An idle batch retires (freeing its context and budget) unless work arrived meanwhile."""
+            with lock:
+                if not g.q.empty():
+                    return False
+                g.alive = False
+                if groups.get(g.key) is g:
+                    del groups[g.key]
+                return True
 
         def setup_worker():
             while True:
@@ -388,17 +405,35 @@ class BatchServer:
                 results.append(Result(req.rid, req.side, req.f.shape[0], iters, relres, status, t_arr, t_adm, t_start,
                                       now(), fp, u_host, fell))
 
+        # the learned cycle diverged on a request: the classical cycle solves it on its own, in a
+        # fallback worker, so that the batch it left keeps running
+        fallback_q: queue.Queue = queue.Queue()
+        fallback_threads = []
+
+        def fallback_worker():
+            classical = Server(None, None, **self._fallback_args)   # identity parameters: the classical cycle
+            while True:
+                job = fallback_q.get()
+                if job is None:
+                    return
+                req, t_arr, t_adm, t_start, fp = job
+                res, errs, _ = classical.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
+                if res:
+                    r = res[0]
+                    finish(req, t_arr, t_adm, t_start, r.iters, r.relres, r.status, fp, r.u, True)
+                else:
+                    with lock:
+                        errors.append((req.rid, "fallback failed: " + repr(errs[:1])))
+
         def fallback(req, t_arr, t_adm, t_start, iters, fp):
-            # the learned cycle diverged on this request: the classical cycle on its own
-            res, errs, _ = self._single.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
             with lock:
                 self.fallbacks += 1
-            if res:
-                r = res[0]
-                finish(req, t_arr, t_adm, t_start, r.iters, r.relres, r.status, fp, r.u, True)
-            else:
-                with lock:
-                    errors.append((req.rid, "fallback failed: " + repr(errs[:1])))
+                if not fallback_threads:
+                    for _ in range(2):
+                        th = threading.Thread(target=fallback_worker, daemon=True)
+                        fallback_threads.append(th)
+                        th.start()
+            fallback_q.put((req, t_arr, t_adm, t_start, fp))
 
         def group_worker(g):
             stream = torch.cuda.Stream(device=self.device)
@@ -447,12 +482,13 @@ class BatchServer:
                             slots[b] = [req, t_arr, now(), None, 0]
                         busy = [b for b in range(cap) if slots[b] is not None]
                         if not busy:
-                            if setups_done.is_set() and g.q.empty():
-                                break
+                            # idle: wait a little for more requests of this grid, else retire (so
+                            # that a batch never holds budget another grid's batch waits for)
                             try:
-                                pending.append(g.q.get(timeout=0.05))
+                                pending.append(g.q.get(timeout=0.02 if setups_done.is_set() else self.idle_s))
                             except queue.Empty:
-                                pass
+                                if retire(g):
+                                    break
                             continue
                         t_round = now()
                         for b in busy:
@@ -518,8 +554,15 @@ class BatchServer:
             incoming.put((req, req.arrival if open_loop else 0.0))
         for _ in setups:
             incoming.put(None)
+        last = now()
         for t in setups:
-            t.join()
+            while t.is_alive():
+                t.join(timeout=0.5)
+                if self.progress and now() - last > 10.0:
+                    last = now()
+                    with lock:
+                        print(f"# batched serving: {len(results)} done, {len(errors)} errors, {now():.0f} s",
+                              file=sys.stderr, flush=True)
         setups_done.set()
         while True:
             with lock:
@@ -528,6 +571,23 @@ class BatchServer:
                 break
             for w in ws:
                 w.join(timeout=0.1)
+            if self.progress and now() - last > 10.0:
+                last = now()
+                with lock:
+                    print(f"# batched serving: {len(results)} done, {len(errors)} errors, {now():.0f} s",
+                          file=sys.stderr, flush=True)
+        # every batch has retired, so no fallback can be added any more
+        with lock:
+            fts = list(fallback_threads)
+        for _ in fts:
+            fallback_q.put(None)
+        for th in fts:
+            while th.is_alive():
+                th.join(timeout=0.5)
+                if self.progress and now() - last > 10.0:
+                    last = now()
+                    print(f"# batched serving: {len(results)} done, fallbacks running, {now():.0f} s",
+                          file=sys.stderr, flush=True)
         wall = now()
         return results, errors, wall
 

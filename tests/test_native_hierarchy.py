@@ -40,3 +40,22 @@ def test_native_builder_rejects_bad_sizes():
         Bd.SquareHierarchy(34, np.ones((4, 4)))
     with pytest.raises(Bd.MGError):
         Bd.SquareHierarchy(33, -np.ones((4, 4)))
+
+
+@pytest.mark.parametrize("side,count", [(65, 6), (257, 4), (513, 3)])
+def test_same_side_requests_share_one_pattern(side, count):
+    """Every level's pattern depends on the grid and the block geometry, not on
+    the coefficient values: the rounding residue of exactly cancelling Galerkin
+    couplings is removed on every level, so requests of one side can share a
+    batch (per-column operators on one pattern)."""
+    Bd = _lib()
+    pats = []
+    for k in range(count):
+        _, blocks = C.serving_request(k, 21, sides=(side,))
+        h = Bd.SquareHierarchy(side, blocks)
+        A, _ = h.to_scipy()
+        h.close()
+        pats.append([(a.indptr.copy(), a.indices.copy()) for a in A])
+    for p in pats[1:]:
+        for (r0, c0), (r1, c1) in zip(pats[0], p):
+            assert np.array_equal(r0, r1) and np.array_equal(c0, c1)
