@@ -72,6 +72,8 @@ def parse():
                     help="requests per run of the continuous-batching loop (closed loop, then open loop at 0.5x "
                          "and 0.8x its rate); 0 skips")
     ap.add_argument("--batch-capacity", type=int, default=32, help="column slots per batch of the batched loop")
+    ap.add_argument("--serving-compare", type=int, default=100,
+                    help="requests of the learned-vs-plain-FP64 batched comparison (0: skip)")
     ap.add_argument("--cycles-per-round", type=int, default=8, help="refinement cycles per round of the batched loop")
     return ap.parse_args()
 
@@ -414,7 +416,9 @@ def serving(args):
       * batched: continuous batching (serve.BatchServer, per-column operators,
         capacity columns per grid, slots refilled between rounds): closed loop
         over --batched-requests requests for the saturated rate T, then Poisson
-        arrivals at 0.5 T and 0.8 T;
+        arrivals at 0.5 T and 0.8 T; then the first --serving-compare requests
+        of the stream batched with the learned FP32 cycle and with the plain
+        FP64 classical V-cycle (closed loops, same accuracy);
       * per_request: one context per request (serve.Server, B = 1) on
         --serving-requests requests, closed loop and 0.5 T, and flexible
         GMRES(30) around the learned cycle (closed loop)."""
@@ -449,6 +453,24 @@ def serving(args):
                                               fallbacks=srv.fallbacks)
             print(f"# batched open loop {frac} T: p50 {runs[f'open_loop_{frac}T']['p50_ms']:.1f} ms, "
                   f"p99 {runs[f'open_loop_{frac}T']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        if args.serving_compare > 0:
+            # the same first requests, batched, with the plain FP64 GPU V-cycle (classical components)
+            nc = args.serving_compare
+            cmp = {}
+            for name, th, prec in (("learned_fp32", theta, "fp32"), ("plain_fp64_classical", None, "fp64")):
+                srv = S.BatchServer(th, None, precision=prec, capacity=args.batch_capacity,
+                                    cycles_per_round=args.cycles_per_round, setup_threads=16, hbm_budget=budget,
+                                    progress=True)
+                res, errs, wall = srv.run(S.make_stream(nc, 0.0, seed=11), open_loop=False)
+                sm = S.summarize(res, wall)
+                by_side = sm.pop("by_side")
+                cmp[name] = dict(sm, errors=len(errs), fallbacks=srv.fallbacks,
+                                 mean_cycles_by_side={k: v["mean_iters"] for k, v in by_side.items()})
+                print(f"# batched {name} on {nc} requests: {cmp[name]['solves_per_s']:.1f} solves/s",
+                      file=sys.stderr, flush=True)
+            a, b = cmp["learned_fp32"]["solves_per_s"], cmp["plain_fp64_classical"]["solves_per_s"]
+            cmp["speedup"] = a / b if b > 0 else None
+            runs[f"closed_loop_first_{nc}"] = cmp
         out["batched"] = dict(requests_per_run=nb, capacity=args.batch_capacity,
                               cycles_per_round=args.cycles_per_round, **runs)
     if args.serving_requests > 0:
@@ -733,7 +755,7 @@ def cycle_cost(args, h, params, f, B, stream):
     return out
 
 
-def held_out(args, params, stream, seeds=(10, 11)):
+def held_out(args, params, stream, seeds=(10, 11, 12, 13, 14)):
     """The shipped parameters were trained on coefficient fields 0..4 of the
     workload's law; solves/s and cycle counts on fields they never saw (same law,
     right-hand sides of the same distribution), beside the benchmark's field."""

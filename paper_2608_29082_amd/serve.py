@@ -51,7 +51,8 @@ class Result:
     t_done: float
     footprint: int
     u: np.ndarray | None = None
-    fallback: bool = False      # solved with the classical parameters after the learned cycle diverged
+    fallback: bool = False      # left the learned stationary iteration (diverged or stalled); solved by
+                                # FGMRES around the learned cycle, or around the classical one
 
     @property
     def latency(self) -> float:
@@ -81,12 +82,20 @@ class Server:
     """theta: flat parameters trained on a J_src-level hierarchy (mapped to each
     request's level count by params.map_levels, levels matched by mesh size),
     a dict {side: (theta, J)} of parameters per grid size, or None for the
-    identity (classical) parameters.  A request whose learned cycle diverges
-    is solved again with the classical parameters (counted in `fallbacks`)."""
+    identity (classical) parameters.
+
+    A request whose learned stationary iteration diverges (the library's
+    divergence test), or has not brought its residual below ||f|| after
+    `stall_cycles` cycles, is solved again from zero by flexible GMRES(restart)
+    preconditioned with the same learned cycle (a Krylov method converges where
+    the stationary iteration of a few bad modes does not), and if that fails
+    too, around the classical cycle; counted in `fallbacks`, its iteration
+    count is then the FGMRES one.  With solver="fgmres" a failed learned FGMRES
+    solve is repeated around the classical cycle."""
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", slots=4, setup_threads=4,
                  hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0",
-                 solver="refine", restart=30, fail_setup=None):
+                 solver="refine", restart=30, fail_setup=None, stall_cycles=64, fallback_iters=2000):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -101,6 +110,7 @@ class Server:
         if solver not in ("refine", "fgmres"):
             raise ValueError("solver must be 'refine' or 'fgmres'")
         self.solver, self.restart = solver, restart
+        self.stall_cycles, self.fallback_iters = stall_cycles, fallback_iters
         # fail_setup(request) -> bool: make that request's setup fail after admission (tests of the
         # error path: the budget it took must come back)
         self.fail_setup = fail_setup
@@ -115,6 +125,61 @@ class Server:
             th, Js = self.theta[side]
             return self.PR.map_levels(th, Js, J, K, K, K)
         return self.PR.map_levels(self.theta, self.J_src, J, K, K, K, shift=self.J_src - J)
+
+    def _stationary(self, ctx, f, u):
+        """The refinement solver from u = 0; with learned parameters, first
+        `stall_cycles` cycles, then (if the residual is below ||f|| and the
+        request not done) the rest of the cycle budget.  The iteration depends
+        only on the current iterate, so the split changes no bit."""
+        stall = self.stall_cycles if self.theta is not None else 0
+        if not stall or stall >= self.max_outer:
+            return ctx.solve(f, u)
+        ctx.set_solver_options(max_outer=stall)
+        info = ctx.solve(f, u)
+        ctx.set_solver_options(max_outer=self.max_outer)
+        if info.status[0] != 5 or not float(info.relres[0]) <= 1.0:
+            return info
+        ctx.set_solver_options(max_outer=self.max_outer - int(info.iters[0]))
+        rest = ctx.solve(f, u)
+        ctx.set_solver_options(max_outer=self.max_outer)
+        return self.Bd.SolveInfo(info.iters + rest.iters, rest.status, rest.relres, rest.code)
+
+    def _krylov(self, ctx, f, u, work):
+        """FGMRES(restart) from zero around the context's cycle, then (learned
+        parameters failing) around the classical cycle.  Returns (info, fell)."""
+        torch = self.torch
+        kb, owned = 0, work is None
+        if owned:   # the stationary solver's contexts carry no Krylov workspace: take one for this solve
+            kb = ctx.fgmres_workspace_bytes(self.restart)
+            self.budget.acquire(kb)
+            work = torch.empty(kb, dtype=torch.uint8, device=self.device)
+        try:
+            iters = self.fallback_iters if owned else self.max_outer
+            run = lambda: ctx.fgmres(f, u, restart=self.restart, max_iter=iters, rtol=self.rtol, work=work)
+            u.zero_()
+            info = run()
+            fell = owned            # reached from a failed stationary solve
+            if info.status[0] != 0 and self.theta is not None:
+                ctx.set_params(self.PR.identity(ctx.J, self.K, self.K, self.K))
+                u.zero_()
+                info = run()
+                fell = True
+            return info, fell
+        finally:
+            if owned:
+                torch.cuda.current_stream(self.device).synchronize()
+                del work
+                self.budget.release(kb)
+
+    def _solve_one(self, ctx, f, u, work):
+        """One request on its context: (SolveInfo, fell back)."""
+        if self.solver == "fgmres":
+            return self._krylov(ctx, f, u, work)
+        info = self._stationary(ctx, f, u)
+        if info.status[0] == 0 or self.theta is None:
+            return info, False
+        info, _ = self._krylov(ctx, f, u, None)
+        return info, True
 
     def _footprint(self, hier, params, n) -> int:
         import ctypes as Cc
@@ -200,16 +265,8 @@ class Server:
                 ctx.stream = stream
                 with torch.cuda.stream(stream):
                     u = torch.zeros_like(f)
-                    run = (lambda: ctx.fgmres(f, u, restart=self.restart, max_iter=self.max_outer, rtol=self.rtol,
-                                              work=work)) if self.solver == "fgmres" else (lambda: ctx.solve(f, u))
-                    info = run()
-                    fell = False
-                    if info.status[0] != 0 and self.theta is not None:
-                        # learned parameters failed on this request: classical cycle
-                        ctx.set_params(self.PR.identity(ctx.J, self.K, self.K, self.K))
-                        u.zero_()
-                        info = run()
-                        fell = True
+                    info, fell = self._solve_one(ctx, f, u, work)
+                    if fell:
                         with lock:
                             self.fallbacks += 1
                     u_host = u.cpu().numpy() if self.keep else None
@@ -278,12 +335,14 @@ class BatchServer:
     the solver's column compaction).  Each batch's device footprint (workspace,
     tile lists excluded, plus f and u) is acquired from the HBM budget before its
     context is set up and released when the batch retires.  A request whose
-    learned cycle diverges is solved again on its own with the classical
-    parameters (counted in `fallbacks`)."""
+    learned cycle diverges, or stalls (Server's test), leaves the batch and is
+    solved on its own by FGMRES around the learned cycle, then around the
+    classical one (counted in `fallbacks`)."""
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", capacity=32, cycles_per_round=8,
                  setup_threads=4, hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False,
-                 device="cuda:0", fail_setup=None, diverge_factor=1e6, progress=False):
+                 device="cuda:0", fail_setup=None, diverge_factor=1e6, progress=False, stall_cycles=64,
+                 fallback_iters=2000):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -291,6 +350,7 @@ class BatchServer:
         self.theta, self.J_src, self.K = theta, J_src, K
         self.precision, self.capacity = precision, capacity
         self.diverge_factor = diverge_factor
+        self.stall_cycles, self.fallback_iters = stall_cycles, fallback_iters
         self.idle_s = 0.25          # an idle batch retires after this long without requests
         self.progress = progress    # a line on stderr every ~10 s while batches run
         self.cycles_per_round, self.setup_threads = cycles_per_round, setup_threads
@@ -303,8 +363,11 @@ class BatchServer:
         self.fail_setup = fail_setup
         self._learned = Server(theta, J_src, K, precision, slots=1, setup_threads=1, hbm_budget=hbm_budget,
                                rtol=rtol, max_outer=max_outer, keep_solution=keep_solution, device=device)
+        # the fallback of a request that left the batch: FGMRES around the learned cycle, then around
+        # the classical one (the same chain as Server's after its stationary solve failed)
         self._fallback_args = dict(K=K, precision=precision, slots=1, setup_threads=1, hbm_budget=hbm_budget,
-                                   rtol=rtol, max_outer=max_outer, keep_solution=keep_solution, device=device)
+                                   rtol=rtol, max_outer=fallback_iters, keep_solution=keep_solution,
+                                   device=device, solver="fgmres")
 
     def _params(self, J, side):
         return self._learned._params(J, side)
@@ -411,13 +474,13 @@ class BatchServer:
         fallback_threads = []
 
         def fallback_worker():
-            classical = Server(None, None, **self._fallback_args)   # identity parameters: the classical cycle
+            krylov = Server(self.theta, self.J_src, **self._fallback_args)
             while True:
                 job = fallback_q.get()
                 if job is None:
                     return
                 req, t_arr, t_adm, t_start, fp = job
-                res, errs, _ = classical.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
+                res, errs, _ = krylov.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
                 if res:
                     r = res[0]
                     finish(req, t_arr, t_adm, t_start, r.iters, r.relres, r.status, fp, r.u, True)
@@ -502,6 +565,11 @@ class BatchServer:
                             # divergence as the per-request solver sees it: the residual against its
                             # start (u = 0, so ||f||), not against the start of this round
                             if st != 0 and not (float(info.relres[b]) <= self.diverge_factor):
+                                st = 6
+                            # stalled: still no residual below ||f|| at the first round end past
+                            # stall_cycles (Server's test after its first stall_cycles cycles)
+                            if (st != 0 and self.theta is not None and self.stall_cycles
+                                    and slots[b][4] < self.stall_cycles <= it and not float(info.relres[b]) <= 1.0):
                                 st = 6
                             done = st == 0 or st == 6 or it >= self.max_outer
                             if not done:

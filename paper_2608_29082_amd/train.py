@@ -12,7 +12,9 @@ after 10 unrolled refinement steps (cycle precision as chosen, FP64 iterate
 and residual), minimised with Rprop from the identity initialisation
 (Sec. 3.1; Sec. 3.4; learning rate 0.01, at most 100 epochs, Sec. 4).
 --fields N trains on N coefficient fields at once (the right-hand sides are
-split between them).  --init starts Rprop from a saved parameter file.  Held-out right-hand sides, on the training fields and
+split between them), seeds --field-seed .. --field-seed + N - 1.  --init starts
+Rprop from a saved parameter file.  The result is the parameter set of the
+lowest loss seen (--keep-last: the last iterate).  Held-out right-hand sides, on the training fields and
 on held-out fields, are then solved to 1e-8 with the trained and with the
 identity parameters, and the cycle counts are reported.
 
@@ -80,6 +82,8 @@ def main(argv=None):
     ap.add_argument("--field-seed", type=int, default=0, help="seed of the first training field")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--init", default=None, help="start from this parameter file (.npy) instead of the identity")
+    ap.add_argument("--keep-last", action="store_true",
+                    help="keep the last Rprop iterate instead of the parameters of the lowest loss seen")
     ap.add_argument("--out", default=None)
     ap.add_argument("--eval-B", type=int, default=8)
     ap.add_argument("--eval-fields", type=int, default=2)
@@ -131,6 +135,7 @@ def main(argv=None):
     phi = torch.tensor(var.initial(start), dtype=torch.float64, requires_grad=True)
     opt = torch.optim.Rprop([phi], lr=args.lr, etas=(0.5, 1.2), step_sizes=(1e-6, 50.0))
     losses = []
+    best_loss, best_phi, best_step = float("inf"), None, -1
     t0 = time.time()
     for it in range(args.steps):
         opt.zero_grad()
@@ -138,13 +143,18 @@ def main(argv=None):
         L = sum(AG.unrolled_loss(c, theta, f, args.cycles, u0=u0) for c, f, u0 in zip(ctxs, fs, u0s)) / len(ctxs)
         L.backward()
         losses.append(L.item())
+        # the parameters of the lowest loss seen are the result (a Rprop run can leave a good
+        # region late in training; the loss of an unrolled divergent cycle grows without bound)
+        if np.isfinite(losses[-1]) and losses[-1] < best_loss:
+            best_loss, best_phi, best_step = losses[-1], phi.detach().clone(), it
         if it % 10 == 0:
             print(f"# step {it} loss {losses[-1]:.4e} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
         if losses[-1] <= 1e-6 * losses[0]:
             break
         opt.step()
     train_s = time.time() - t0
-    theta_np = var.expand(phi.detach().numpy().copy())
+    final_phi = best_phi if (best_phi is not None and not args.keep_last) else phi.detach()
+    theta_np = var.expand(final_phi.numpy().copy())
     for c in ctxs:
         c.close()
 
@@ -173,7 +183,8 @@ def main(argv=None):
             evals.append({"field": name, "identity": cycles(h, theta0, f_eval), "trained": cycles(h, theta_np, f_eval)})
             print(f"# eval {evals[-1]}", file=sys.stderr, flush=True)
     out = {"workload": args.workload, "variant": args.variant, "K": K, "fields": args.fields, "steps": len(losses),
-           "loss0": losses[0], "loss_final": losses[-1], "train_seconds": train_s, "eval": evals}
+           "loss0": losses[0], "loss_final": losses[-1], "loss_best": best_loss, "best_step": best_step,
+           "train_seconds": train_s, "eval": evals}
     if args.out:
         if darcy:
             desc = (f"Darcy cell-centred, {n_cells}x{n_cells} cells, 1e-6 inclusion on [0.4,0.6]^2, piecewise "
@@ -187,7 +198,8 @@ def main(argv=None):
             "trained_on": desc, "J": J, "KB": K, "KR": K, "KP": K, "nu": [nu, nu], "precision": args.precision,
             "variant": args.variant, "optimizer": f"Rprop lr={args.lr}", "steps": len(losses),
             "init": os.path.basename(args.init) if args.init else "identity",
-            "loss0": losses[0], "loss_final": losses[-1], "eval": evals})
+            "loss0": losses[0], "loss_final": losses[-1], "loss_best": best_loss, "best_step": best_step,
+            "kept": "last" if args.keep_last else "lowest loss", "eval": evals})
     print(json.dumps(out), flush=True)
 
 

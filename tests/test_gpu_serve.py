@@ -145,7 +145,7 @@ def test_batched_matches_per_request_solver():
     assert not eb and not es
     b, s = {r.rid: r for r in rb}, {r.rid: r for r in rs}
     for q in reqs:
-        # both loops fall back to the classical cycle for the same requests
+        # both loops leave the learned stationary iteration for the same requests
         assert b[q.rid].fallback == s[q.rid].fallback
         assert abs(b[q.rid].iters - s[q.rid].iters) <= 1
         d = np.abs(b[q.rid].u - s[q.rid].u).max() / np.abs(s[q.rid].u).max()
@@ -169,3 +169,43 @@ def test_batched_budget_and_failed_setup():
     assert sorted(r.rid for r in res) == [k for k in range(10) if k != 4]
     assert all(r.status == 0 for r in res)
     assert srv.peak_used <= big and srv.budget.used == 0
+
+
+def _overshooting(sides):
+    """Identity parameters with eta = 4 on every level: the damped Jacobi
+    smoother overshoots and the stationary iteration diverges."""
+    from paper_2608_29082_amd import params as PR
+    from paper_2608_29082_amd import binding as Bd
+    theta = {}
+    for side in sides:
+        h = Bd.SquareHierarchy(side, np.zeros((16, 16)))
+        J = h.nlevels
+        h.close()
+        p = PR.identity(J, 3, 3, 3).reshape(J - 1, -1)
+        p[:, 1] = 4.0
+        theta[side] = (p.ravel(), J)
+    return theta
+
+
+def test_fallback_chain_same_in_both_loops():
+    """Requests whose learned stationary iteration diverges leave it (the
+    divergence test or the stall test after 64 cycles) and are solved by FGMRES
+    around the same cycle, else around the classical one: every request
+    reaches 1e-8, is marked as a fallback, and the per-request and batched
+    loops give the same FGMRES iteration counts and the same bits."""
+    from paper_2608_29082_amd import serve as S
+    reqs = S.make_stream(6, 0.0, seed=11, sides=(65, 129))
+    theta = _overshooting((65, 129))
+    rs, es, _ = S.Server(theta, None, keep_solution=True, slots=2, setup_threads=2).run(reqs, open_loop=False)
+    bsrv = S.BatchServer(theta, None, keep_solution=True, capacity=16)
+    rb, eb, _ = bsrv.run(reqs, open_loop=False)
+    assert not es and not eb, (es[:2], eb[:2])
+    s, b = {r.rid: r for r in rs}, {r.rid: r for r in rb}
+    assert bsrv.fallbacks == len(reqs)
+    for q in reqs:
+        assert s[q.rid].fallback and b[q.rid].fallback
+        assert s[q.rid].status == 0 and b[q.rid].status == 0
+        assert _relres(q, s[q.rid].u[:, 0]) <= 1e-8 and _relres(q, b[q.rid].u[:, 0]) <= 1e-8
+        assert s[q.rid].iters == b[q.rid].iters
+        assert np.array_equal(s[q.rid].u, b[q.rid].u)
+    print("fallback FGMRES iterations:", sorted((q.side, s[q.rid].iters) for q in reqs), flush=True)
