@@ -14,6 +14,7 @@
 #include <atomic>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -221,11 +222,23 @@ Csr restriction(int side_f) {
 // couplings reaches ~1e-13 on the coarsest levels; genuine couplings stay above ~1e-4).
 Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
   const int nc = R.nrows;
-  // pass 1: the sorted column pattern and values of every row of R A P
-  std::vector<std::vector<int>> pc(nc);
-  std::vector<std::vector<double>> pv(nc);
+  // pass 1: the sorted column pattern and values of every row of R A P; each thread keeps its
+  // rows in flat buffers of its own, gathered afterwards into one CSR T
+  struct Chunk {
+    int r0 = 0, r1 = 0;
+    std::vector<int> col;
+    std::vector<double> val;
+  };
+  std::vector<int> cnt(nc, 0);
+  std::vector<Chunk> chunks;
+  std::mutex mu;
   par_rows(nc, [&](int r0, int r1) {
     RowAcc ap(P.ncols), ai(P.ncols);
+    Chunk ch;
+    ch.r0 = r0;
+    ch.r1 = r1;
+    ch.col.reserve((size_t)(r1 - r0) * 8);
+    ch.val.reserve((size_t)(r1 - r0) * 8);
     int tag = 0;
     for (int I = r0; I < r1; ++I) {
       for (int p = R.rowptr[I]; p < R.rowptr[I + 1]; ++p) {
@@ -241,43 +254,58 @@ Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
         ++tag;
       }
       std::sort(ap.cols.begin(), ap.cols.end());
-      pc[I] = ap.cols;
-      pv[I].resize(ap.cols.size());
-      for (size_t k = 0; k < ap.cols.size(); ++k) pv[I][k] = ap.acc[ap.cols[k]];
+      cnt[I] = (int)ap.cols.size();
+      for (int J : ap.cols) {
+        ch.col.push_back(J);
+        ch.val.push_back(ap.acc[J]);
+      }
       ap.cols.clear();
     }
+    std::lock_guard<std::mutex> lk(mu);
+    chunks.push_back(std::move(ch));
   });
+  Csr T = alloc_csr(nc, nc, cnt);
+  for (const Chunk& ch : chunks) {
+    std::copy(ch.col.begin(), ch.col.end(), T.col.data() + T.rowptr[ch.r0]);
+    std::copy(ch.val.begin(), ch.val.end(), T.val.data() + T.rowptr[ch.r0]);
+  }
+  std::vector<Chunk>().swap(chunks);
   // pass 2: symmetrise by merging each row with the matching column
   // (value of (J, I) looked up in row J, whose pattern contains I by symmetry
   // of the pattern), then drop residue
   std::vector<double> d(nc, 0.0);
-  for (int I = 0; I < nc; ++I)
-    for (size_t k = 0; k < pc[I].size(); ++k)
-      if (pc[I][k] == I) d[I] = std::fabs(pv[I][k]);
+  par_rows(nc, [&](int r0, int r1) {
+    for (int I = r0; I < r1; ++I)
+      for (int k = T.rowptr[I]; k < T.rowptr[I + 1]; ++k)
+        if (T.col[k] == I) d[I] = std::fabs(T.val[k]);
+  });
   auto at = [&](int r, int c) {
-    const auto it = std::lower_bound(pc[r].begin(), pc[r].end(), c);
-    return (it != pc[r].end() && *it == c) ? pv[r][it - pc[r].begin()] : 0.0;
+    const int* b = T.col.data() + T.rowptr[r];
+    const int* e = T.col.data() + T.rowptr[r + 1];
+    const int* it = std::lower_bound(b, e, c);
+    return (it != e && *it == c) ? T.val[it - T.col.data()] : 0.0;
   };
-  std::vector<int> cnt(nc, 0);
-  std::vector<std::vector<double>> sv(nc);
+  Buf<double> sv;
+  sv.resize(T.col.size());
   par_rows(nc, [&](int r0, int r1) {
     for (int I = r0; I < r1; ++I) {
-      sv[I].resize(pc[I].size());
-      for (size_t k = 0; k < pc[I].size(); ++k) {
-        const int J = pc[I][k];
-        double v = 0.5 * (pv[I][k] + at(J, I));
+      int c = 0;
+      for (int k = T.rowptr[I]; k < T.rowptr[I + 1]; ++k) {
+        const int J = T.col[k];
+        double v = 0.5 * (T.val[k] + at(J, I));
         if (J != I && std::fabs(v) <= 1e-11 * std::sqrt(d[I] * d[J])) v = 0.0;
-        sv[I][k] = v;
-        cnt[I] += v != 0.0;
+        sv[k] = v;
+        c += v != 0.0;
       }
+      cnt[I] = c;
     }
   });
   Csr o = alloc_csr(nc, nc, cnt);
   par_rows(nc, [&](int r0, int r1) {
     for (int I = r0; I < r1; ++I) {
       int p = o.rowptr[I];
-      for (size_t k = 0; k < pc[I].size(); ++k)
-        if (sv[I][k] != 0.0) { o.col[p] = pc[I][k]; o.val[p] = sv[I][k]; ++p; }
+      for (int k = T.rowptr[I]; k < T.rowptr[I + 1]; ++k)
+        if (sv[k] != 0.0) { o.col[p] = T.col[k]; o.val[p] = sv[k]; ++p; }
     }
   });
   return o;

@@ -351,6 +351,7 @@ class BatchServer:
         self.precision, self.capacity = precision, capacity
         self.diverge_factor = diverge_factor
         self.stall_cycles, self.fallback_iters = stall_cycles, fallback_iters
+        self.fallback_workers = 8   # each rebuilds its request's hierarchy on the host, then runs FGMRES
         self.idle_s = 0.25          # an idle batch retires after this long without requests
         self.progress = progress    # a line on stderr every ~10 s while batches run
         self.cycles_per_round, self.setup_threads = cycles_per_round, setup_threads
@@ -492,7 +493,7 @@ class BatchServer:
             with lock:
                 self.fallbacks += 1
                 if not fallback_threads:
-                    for _ in range(2):
+                    for _ in range(self.fallback_workers):
                         th = threading.Thread(target=fallback_worker, daemon=True)
                         fallback_threads.append(th)
                         th.start()

@@ -178,7 +178,7 @@ def _overshooting(sides):
     from paper_2608_29082_amd import binding as Bd
     theta = {}
     for side in sides:
-        h = Bd.SquareHierarchy(side, np.zeros((16, 16)))
+        h = Bd.SquareHierarchy(side, np.ones((16, 16)))
         J = h.nlevels
         h.close()
         p = PR.identity(J, 3, 3, 3).reshape(J - 1, -1)
