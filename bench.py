@@ -237,7 +237,10 @@ def main():
 
     if not args.no_ablation and args.workload == "diffusion-513":
         out["cycle_cost"] = cycle_cost(args, h, params, f, B, stream)
-        out["held_out_fields"] = held_out(args, params, stream)
+        seeds = (tuple(s for s in meta.get("held_out_seeds", (10, 11, 12, 13, 14)) if s != 0)
+                 if pfile and pfile != "identity" else ())
+        if seeds:
+            out["held_out_fields"] = held_out(args, params, stream, seeds)
 
     if not args.no_variants:
         out["conv_variants"] = conv_variants(args, h, f, B, stream)
@@ -755,10 +758,11 @@ def cycle_cost(args, h, params, f, B, stream):
     return out
 
 
-def held_out(args, params, stream, seeds=(10, 11, 12, 13, 14)):
-    """The shipped parameters were trained on coefficient fields 0..4 of the
-    workload's law; solves/s and cycle counts on fields they never saw (same law,
-    right-hand sides of the same distribution), beside the benchmark's field."""
+def held_out(args, params, stream, seeds):
+    """Solves/s and cycle counts on coefficient fields of the workload's law
+    that the parameters never saw in training (the parameter file's
+    `held_out_seeds`; same solver, right-hand sides of the same distribution),
+    beside the benchmark's own field."""
     import torch
     from mginputs import configs as C
     from paper_2608_29082_amd import binding as Bd

@@ -78,6 +78,29 @@ class _Budget:
             self.cv.notify_all()
 
 
+class Progress:
+    """Stop test of the learned stationary iteration, applied by both request
+    loops at the end of every round of cycles (a request's own cycle count
+    `it`): the request leaves the learned iteration when the solver reports
+    divergence or its residual exceeds `diverge_factor` ||f||, when after
+    `stall_cycles` cycles its residual is still not below ||f||, or when its
+    best residual has not improved for `window` cycles (a slowly diverging or
+    stagnating iteration)."""
+
+    def __init__(self, diverge_factor=1e6, stall_cycles=64, window=128):
+        self.diverge_factor, self.stall_cycles, self.window = diverge_factor, stall_cycles, window
+        self.best, self.best_it = float("inf"), 0
+
+    def failed(self, it: int, relres: float, status: int) -> bool:
+        if status == 6 or not relres <= self.diverge_factor:
+            return True
+        if relres < self.best:
+            self.best, self.best_it = relres, it
+        if self.stall_cycles and it >= self.stall_cycles and not relres < 1.0:
+            return True
+        return bool(self.window) and it - self.best_it >= self.window
+
+
 class Server:
     """theta: flat parameters trained on a J_src-level hierarchy (mapped to each
     request's level count by params.map_levels, levels matched by mesh size),
@@ -95,7 +118,8 @@ class Server:
 
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", slots=4, setup_threads=4,
                  hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0",
-                 solver="refine", restart=30, fail_setup=None, stall_cycles=64, fallback_iters=2000):
+                 solver="refine", restart=30, fail_setup=None, stall_cycles=64, stall_window=128,
+                 round_cycles=8, diverge_factor=1e6, fallback_iters=2000):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -111,6 +135,7 @@ class Server:
             raise ValueError("solver must be 'refine' or 'fgmres'")
         self.solver, self.restart = solver, restart
         self.stall_cycles, self.fallback_iters = stall_cycles, fallback_iters
+        self.stall_window, self.round_cycles, self.diverge_factor = stall_window, round_cycles, diverge_factor
         # fail_setup(request) -> bool: make that request's setup fail after admission (tests of the
         # error path: the budget it took must come back)
         self.fail_setup = fail_setup
@@ -127,22 +152,27 @@ class Server:
         return self.PR.map_levels(self.theta, self.J_src, J, K, K, K, shift=self.J_src - J)
 
     def _stationary(self, ctx, f, u):
-        """The refinement solver from u = 0; with learned parameters, first
-        `stall_cycles` cycles, then (if the residual is below ||f|| and the
-        request not done) the rest of the cycle budget.  The iteration depends
-        only on the current iterate, so the split changes no bit."""
-        stall = self.stall_cycles if self.theta is not None else 0
-        if not stall or stall >= self.max_outer:
+        """The refinement solver from u = 0.  With learned parameters it runs in
+        rounds of `round_cycles` cycles with the Progress test after each (the
+        batched loop's rounds and test, so both loops take the same decisions);
+        the iteration depends only on the current iterate, so the rounds change
+        no bit.  With the classical parameters it is one solve."""
+        if self.theta is None:
             return ctx.solve(f, u)
-        ctx.set_solver_options(max_outer=stall)
-        info = ctx.solve(f, u)
+        prog = Progress(self.diverge_factor, self.stall_cycles, self.stall_window)
+        total, st, rr = 0, 5, float("nan")
+        while total < self.max_outer:
+            ctx.set_solver_options(max_outer=min(self.round_cycles, self.max_outer - total))
+            info = ctx.solve(f, u)
+            total += int(info.iters[0])
+            st, rr = int(info.status[0]), float(info.relres[0])
+            if st == 0:
+                break
+            if prog.failed(total, rr, st):
+                st = 6
+                break
         ctx.set_solver_options(max_outer=self.max_outer)
-        if info.status[0] != 5 or not float(info.relres[0]) <= 1.0:
-            return info
-        ctx.set_solver_options(max_outer=self.max_outer - int(info.iters[0]))
-        rest = ctx.solve(f, u)
-        ctx.set_solver_options(max_outer=self.max_outer)
-        return self.Bd.SolveInfo(info.iters + rest.iters, rest.status, rest.relres, rest.code)
+        return self.Bd.SolveInfo(np.array([total]), np.array([st]), np.array([rr]), st)
 
     def _krylov(self, ctx, f, u, work):
         """FGMRES(restart) from zero around the context's cycle, then (learned
@@ -342,7 +372,7 @@ class BatchServer:
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", capacity=32, cycles_per_round=8,
                  setup_threads=4, hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False,
                  device="cuda:0", fail_setup=None, diverge_factor=1e6, progress=False, stall_cycles=64,
-                 fallback_iters=2000):
+                 stall_window=128, fallback_iters=2000):
         import torch
         from . import binding as Bd
         from . import params as PR
@@ -351,6 +381,7 @@ class BatchServer:
         self.precision, self.capacity = precision, capacity
         self.diverge_factor = diverge_factor
         self.stall_cycles, self.fallback_iters = stall_cycles, fallback_iters
+        self.stall_window = stall_window
         self.fallback_workers = 8   # each rebuilds its request's hierarchy on the host, then runs FGMRES
         self.idle_s = 0.25          # an idle batch retires after this long without requests
         self.progress = progress    # a line on stderr every ~10 s while batches run
@@ -543,7 +574,8 @@ class BatchServer:
                                 side_sem(req.side).release()
                             f[:, b] = torch.as_tensor(req.f[:, 0], device=self.device)
                             u[:, b] = 0.0
-                            slots[b] = [req, t_arr, now(), None, 0]
+                            slots[b] = [req, t_arr, now(), None, 0,
+                                        Progress(self.diverge_factor, self.stall_cycles, self.stall_window)]
                         busy = [b for b in range(cap) if slots[b] is not None]
                         if not busy:
                             # idle: wait a little for more requests of this grid, else retire (so
@@ -560,17 +592,15 @@ class BatchServer:
                                 slots[b][3] = t_round
                         info = ctx.solve(f, u)
                         for b in busy:
-                            req, t_arr, t_adm, t_start, it = slots[b]
+                            req, t_arr, t_adm, t_start, it, prog = slots[b]
                             it += int(info.iters[b])
                             st = int(info.status[b])
-                            # divergence as the per-request solver sees it: the residual against its
-                            # start (u = 0, so ||f||), not against the start of this round
-                            if st != 0 and not (float(info.relres[b]) <= self.diverge_factor):
-                                st = 6
-                            # stalled: still no residual below ||f|| at the first round end past
-                            # stall_cycles (Server's test after its first stall_cycles cycles)
-                            if (st != 0 and self.theta is not None and self.stall_cycles
-                                    and slots[b][4] < self.stall_cycles <= it and not float(info.relres[b]) <= 1.0):
+                            rr = float(info.relres[b])
+                            # relres is against the request's start (u = 0, so ||f||), not this round's;
+                            # learned parameters: the Progress test (Server's, at the same cycle counts
+                            # when the rounds have the same length); classical: divergence only
+                            if st != 0 and (prog.failed(it, rr, st) if self.theta is not None
+                                            else not rr <= self.diverge_factor):
                                 st = 6
                             done = st == 0 or st == 6 or it >= self.max_outer
                             if not done:
