@@ -68,9 +68,11 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="requests per run of the per-request serving loop (closed loop, 0.5x its rate, FGMRES); "
                          "0 skips")
-    ap.add_argument("--batched-requests", type=int, default=1000,
-                    help="requests per run of the continuous-batching loop (closed loop, then open loop at 0.5x "
-                         "and 0.8x its rate); 0 skips")
+    ap.add_argument("--batched-requests", type=int, default=10000,
+                    help="requests of the continuous-batching loop's closed-loop run (its rate T sets the "
+                         "open-loop arrival rates); 0 skips")
+    ap.add_argument("--open-requests", type=int, default=1000,
+                    help="requests of each open-loop run of the batched loop (0.5 T, 0.8 T, 1.2 T)")
     ap.add_argument("--batch-capacity", type=int, default=32, help="column slots per batch of the batched loop")
     ap.add_argument("--serving-compare", type=int, default=100,
                     help="requests of the learned-vs-plain-FP64 batched comparison (0: skip)")
@@ -419,7 +421,7 @@ def serving(args):
       * batched: continuous batching (serve.BatchServer, per-column operators,
         capacity columns per grid, slots refilled between rounds): closed loop
         over --batched-requests requests for the saturated rate T, then Poisson
-        arrivals at 0.5 T and 0.8 T; then the first --serving-compare requests
+        arrivals at 0.5 T, 0.8 T and 1.2 T (overload) over --open-requests; then the first --serving-compare requests
         of the stream batched with the learned FP32 cycle and with the plain
         FP64 classical V-cycle (closed loops, same accuracy);
       * per_request: one context per request (serve.Server, B = 1) on
@@ -449,9 +451,10 @@ def serving(args):
         print(f"# batched closed loop: {runs['closed_loop']['solves_per_s']:.1f} solves/s over {nb} requests",
               file=sys.stderr, flush=True)
         T = runs["closed_loop"]["solves_per_s"]
-        for frac in (0.5, 0.8):
+        no = min(nb, args.open_requests)
+        for frac in (0.5, 0.8, 1.2):
             srv = bsrv()
-            res, errs, wall = srv.run(S.make_stream(nb, frac * T, seed=12), open_loop=True)
+            res, errs, wall = srv.run(S.make_stream(no, frac * T, seed=12), open_loop=True)
             runs[f"open_loop_{frac}T"] = dict(S.summarize(res, wall), qps=frac * T, errors=len(errs),
                                               fallbacks=srv.fallbacks)
             print(f"# batched open loop {frac} T: p50 {runs[f'open_loop_{frac}T']['p50_ms']:.1f} ms, "
@@ -474,7 +477,8 @@ def serving(args):
             a, b = cmp["learned_fp32"]["solves_per_s"], cmp["plain_fp64_classical"]["solves_per_s"]
             cmp["speedup"] = a / b if b > 0 else None
             runs[f"closed_loop_first_{nc}"] = cmp
-        out["batched"] = dict(requests_per_run=nb, capacity=args.batch_capacity,
+        out["batched"] = dict(requests_closed_loop=nb, requests_open_loop=min(nb, args.open_requests),
+                              capacity=args.batch_capacity,
                               cycles_per_round=args.cycles_per_round, **runs)
     if args.serving_requests > 0:
         n1 = args.serving_requests

@@ -33,8 +33,22 @@ class Request:
     rid: int
     side: int
     blocks: np.ndarray          # (16, 16) coefficient per block
-    f: np.ndarray               # (n, 1) right-hand side
+    f_data: np.ndarray | None = None   # (n, 1) right-hand side, or None: drawn from the stream seed when used
     arrival: float = 0.0        # seconds from the start of the stream
+    seed: int = 0               # stream seed of a drawn right-hand side
+
+    @property
+    def n(self) -> int:
+        return (self.side - 2) ** 2
+
+    @property
+    def f(self) -> np.ndarray:
+        """The right-hand side (drawn again at each use when not stored, so a long
+        stream does not hold every request's vector in host memory)."""
+        if self.f_data is not None:
+            return self.f_data
+        from mginputs import configs as C
+        return C.serving_rhs(self.rid, self.n, self.seed)
 
 
 @dataclass
@@ -306,7 +320,7 @@ class Server:
                 del ctx, f, u, work
                 self.budget.release(fp)
                 with lock:
-                    results.append(Result(req.rid, req.side, req.f.shape[0], int(info.iters[0]),
+                    results.append(Result(req.rid, req.side, req.n, int(info.iters[0]),
                                           float(info.relres[0]), int(info.status[0]), t_arr, t_adm, t_start,
                                           t_done, fp, u_host, fell))
 
@@ -497,7 +511,7 @@ class BatchServer:
 
         def finish(req, t_arr, t_adm, t_start, iters, relres, status, fp, u_host, fell=False):
             with lock:
-                results.append(Result(req.rid, req.side, req.f.shape[0], iters, relres, status, t_arr, t_adm, t_start,
+                results.append(Result(req.rid, req.side, req.n, iters, relres, status, t_arr, t_adm, t_start,
                                       now(), fp, u_host, fell))
 
         # the learned cycle diverged on a request: the classical cycle solves it on its own, in a
@@ -512,7 +526,8 @@ class BatchServer:
                 if job is None:
                     return
                 req, t_arr, t_adm, t_start, fp = job
-                res, errs, _ = krylov.run([Request(req.rid, req.side, req.blocks, req.f)], open_loop=False)
+                res, errs, _ = krylov.run([Request(req.rid, req.side, req.blocks, req.f_data, 0.0, req.seed)],
+                                          open_loop=False)
                 if res:
                     r = res[0]
                     finish(req, t_arr, t_adm, t_start, r.iters, r.relres, r.status, fp, r.u, True)
@@ -729,8 +744,7 @@ def make_stream(count, qps, seed=0, sides=None):
     reqs = []
     for k in range(count):
         side, blocks = C.serving_request(k, seed, sides)
-        n = (side - 2) ** 2
-        reqs.append(Request(k, side, blocks, C.serving_rhs(k, n, seed), float(arr[k])))
+        reqs.append(Request(k, side, blocks, None, float(arr[k]), seed))
     return reqs
 
 
