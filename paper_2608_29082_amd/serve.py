@@ -133,14 +133,14 @@ class Server:
     def __init__(self, theta=None, J_src=None, K=3, precision="fp32", slots=4, setup_threads=4,
                  hbm_budget=16 << 30, rtol=1e-8, max_outer=20000, keep_solution=False, device="cuda:0",
                  solver="refine", restart=30, fail_setup=None, stall_cycles=64, stall_window=128,
-                 round_cycles=8, diverge_factor=1e6, fallback_iters=2000):
+                 round_cycles=8, diverge_factor=1e6, fallback_iters=2000, budget=None):
         import torch
         from . import binding as Bd
         from . import params as PR
         self.torch, self.Bd, self.PR = torch, Bd, PR
         self.theta, self.J_src, self.K = theta, J_src, K
         self.precision, self.slots, self.setup_threads = precision, slots, setup_threads
-        self.budget = _Budget(hbm_budget)
+        self.budget = budget if budget is not None else _Budget(hbm_budget)   # shareable between loops
         self.rtol, self.max_outer, self.keep = rtol, max_outer, keep_solution
         self.device = torch.device(device)
         self.peak_used = 0
@@ -192,10 +192,11 @@ class Server:
         """FGMRES(restart) from zero around the context's cycle, then (learned
         parameters failing) around the classical cycle.  Returns (info, fell)."""
         torch = self.torch
-        kb, owned = 0, work is None
-        if owned:   # the stationary solver's contexts carry no Krylov workspace: take one for this solve
+        owned = work is None
+        if owned:   # a stationary solver's context: its fallback workspace was counted at admission
             kb = ctx.fgmres_workspace_bytes(self.restart)
-            self.budget.acquire(kb)
+            if kb > krylov_bytes_bound(ctx.n[0], 1, self.restart):
+                raise RuntimeError("Krylov workspace exceeds its admission bound")
             work = torch.empty(kb, dtype=torch.uint8, device=self.device)
         try:
             iters = self.fallback_iters if owned else self.max_outer
@@ -213,7 +214,6 @@ class Server:
             if owned:
                 torch.cuda.current_stream(self.device).synchronize()
                 del work
-                self.budget.release(kb)
 
     def _solve_one(self, ctx, f, u, work):
         """One request on its context: (SolveInfo, fell back)."""
@@ -235,7 +235,10 @@ class Server:
         ws, ck = Cc.c_size_t(), Cc.c_size_t()
         Bd._check(lib.mg_workspace_bytes(Cc.byref(hier.view), Cc.byref(pr), Cc.byref(o), Cc.byref(ws),
                                          Cc.byref(ck)), "mg_workspace_bytes")
-        return int(ws.value) + 2 * n * 8 + (krylov_bytes_bound(n, 1, self.restart) if self.solver == "fgmres" else 0)
+        # a Krylov workspace: the FGMRES solver's, or the fallback's of a learned stationary solver
+        # (counted at admission, so that a fallback never waits for budget that admitted requests hold)
+        krylov = self.solver == "fgmres" or self.theta is not None
+        return int(ws.value) + 2 * n * 8 + (krylov_bytes_bound(n, 1, self.restart) if krylov else 0)
 
     def run(self, requests, open_loop=True):
         """Serve `requests` (sorted by arrival).  open_loop: each request enters
@@ -520,7 +523,7 @@ class BatchServer:
         fallback_threads = []
 
         def fallback_worker():
-            krylov = Server(self.theta, self.J_src, **self._fallback_args)
+            krylov = Server(self.theta, self.J_src, budget=self.budget, **self._fallback_args)
             while True:
                 job = fallback_q.get()
                 if job is None:
