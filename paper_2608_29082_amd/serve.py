@@ -16,6 +16,15 @@ A request is (side, coefficient blocks, right-hand side).  The loop:
 Requests that arrive while others run are admitted as budget and slots free
 up; a request's result does not depend on what else is in flight (each has
 its own context, stream and buffers, and every kernel is deterministic).
+
+BatchServer is the continuous-batching form: requests of one grid size share
+a context of column slots, each column with its own operator values
+(per-column operators, mg_load_column), advanced in rounds of refinement
+cycles with free slots refilled between rounds.  In both loops a request whose
+learned stationary iteration fails the Progress test (divergence, no residual
+below ||f|| after 64 cycles, no new best residual for 128 cycles) is solved by
+flexible GMRES around the same learned cycle, and if that fails too, around
+the classical cycle.
 """
 from __future__ import annotations
 
@@ -310,14 +319,23 @@ class Server:
                 req, ctx, f, fp, t_arr, t_adm, work = job
                 t_start = now()
                 ctx.stream = stream
-                with torch.cuda.stream(stream):
-                    u = torch.zeros_like(f)
-                    info, fell = self._solve_one(ctx, f, u, work)
-                    if fell:
-                        with lock:
-                            self.fallbacks += 1
-                    u_host = u.cpu().numpy() if self.keep else None
-                stream.synchronize()
+                try:
+                    with torch.cuda.stream(stream):
+                        u = torch.zeros_like(f)
+                        info, fell = self._solve_one(ctx, f, u, work)
+                        if fell:
+                            with lock:
+                                self.fallbacks += 1
+                        u_host = u.cpu().numpy() if self.keep else None
+                    stream.synchronize()
+                except Exception as e:  # report the request, free what it holds and keep serving
+                    ctx.close()
+                    del ctx, f, work
+                    self.budget.release(fp)
+                    with lock:
+                        errors.append((req.rid, repr(e)))
+                        results.append(None)
+                    continue
                 t_done = now()
                 ctx.close()
                 del ctx, f, u, work
