@@ -14,7 +14,6 @@
 // Arnoldi sweep would cost more than the sweep.  The outer FGMRES runs in
 // FP64 with multi-block reductions in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
-#include <rocprim/warp/warp_reduce.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -236,21 +235,26 @@ __global__ __launch_bounds__(256) void k_hz_copy(size_t cnt, const cx<T>* __rest
 }
 
 // ------------------------------------------------------------------ GMRES smoothing step
+// Sum over the 64 lanes of a wavefront, left in every lane: a butterfly of
+// lane exchanges (each step adds the value of the lane whose index differs in
+// one bit; the same pairing order in every lane, so the sum is deterministic).
+__device__ __forceinline__ double hz_wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // Block-wide sums of the first cnt of N doubles (and of the last one when
-// last is set), broadcast to every work-item: wavefront reductions (rocPRIM's,
-// DPP lane moves on this target), then
-// work-item k adds the waves' totals of value k in wave order (a fixed order:
-// deterministic).  lds: N x 16 doubles, tot: N.
+// last is set), broadcast to every work-item: wavefront sums (hz_wave_sum),
+// then work-item k adds the waves' totals of value k in wave order (a fixed
+// order: deterministic).  lds: N x 16 doubles, tot: N.
 template <int N>
 __device__ __forceinline__ void hz_block_sum(double (&a)[N], int cnt, double* lds, double* tot, bool last = false) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (k < cnt || (last && k == N - 1)) {
-      using WR = rocprim::warp_reduce<double, 64>;
-      __shared__ typename WR::storage_type wst[16];
-      double x;
-      WR().reduce(a[k], x, wst[wv], rocprim::plus<double>());
+      const double x = hz_wave_sum(a[k]);
       if (ln == 0) lds[k * 16 + wv] = x;
     }
   }
