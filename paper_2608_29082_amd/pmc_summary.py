@@ -3,9 +3,13 @@
     python -m paper_2608_29082_amd.pmc_summary stats  STATS_CSV [--top N]
     python -m paper_2608_29082_amd.pmc_summary traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV
            [--copy-mib 256] [--kernel NAME] [--json OUT] [--workload TEXT]
+    python -m paper_2608_29082_amd.pmc_summary counters CSV [CSV ...] --kernel NAME [--kernel NAME ...]
 
 `stats` prints a markdown table (calls, total ms, average us, share) from a
 `--kernel-trace --stats` run's `*_kernel_stats.csv`.
+
+`counters` prints, for each named kernel, the mean per dispatch of every
+counter in the given `--pmc` passes (one table row per counter).
 
 `traffic` reads two counter passes (`--pmc FETCH_SIZE`, then `--pmc
 WRITE_SIZE`; KiB per dispatch) of the same program and the same passes of a
@@ -24,7 +28,6 @@ import csv
 import hashlib
 import json
 import os
-import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,12 +123,33 @@ def traffic(fetch: str, write: str, copy_fetch: str, copy_write: str, mib: int =
     return "\n".join(table), cal, {k: (rd, wr) for k, n, fk, wk, rd, wr in rows}, (ff, fw)
 
 
+def counters_table(paths, kernels) -> str:
+    """Mean per dispatch of every counter in the CSV files, for each kernel."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in paths:
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in kernels for c in vals.get(k, {})})
+    out = ["| counter | " + " | ".join(f"`{k}`" for k in kernels) + " |",
+           "|---|" + "---:|" * len(kernels)]
+    for c in names:
+        out.append(f"| {c} | " + " | ".join(f"{mean(vals[k][c]):.4g}" if vals[k].get(c) else "" for k in kernels)
+                   + " |")
+    out.append("| dispatches | " + " | ".join(str(max((len(v) for v in vals[k].values()), default=0))
+                                                for k in kernels) + " |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=25)
+    cs = sub.add_parser("counters")
+    cs.add_argument("csv", nargs="+")
+    cs.add_argument("--kernel", action="append", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
@@ -139,6 +163,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv, a.top))
+        return
+    if a.cmd == "counters":
+        print(counters_table(a.csv, a.kernel))
         return
     table, cal, per, (ff, fw) = traffic(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib)
     print(cal)
