@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "chebtab.hpp"
 
 namespace mgl {
@@ -492,8 +494,9 @@ struct TileCoef {
 };
 // LDS layout of one workgroup, in float4 units
 struct TileLds {
-  int y0, y1;               // hop buffers (x occupies [0, y0))
-  int col;                  // local columns (uint16) of the rows at distance <= K - 1
+  int xs;                   // input rows
+  int y0, y1;               // hop buffers (each of the three preceded by a row of zeros)
+  int col;                  // local columns + 1 (uint16, 0: padding) of the rows at distance <= K - 1
   int idg;                  // their row scales (float)
 };
 
@@ -516,13 +519,15 @@ __device__ __forceinline__ void st4v(bf16_t* p, const float (&v)[4]) {
   *reinterpret_cast<uint2*>(p) = t;
 }
 
-// s += sum over the graph slots of local row r of [w] y_j; columns from LDS,
-// y in LDS, weights (WG) from the tile's slot array in global memory.  A
-// padding slot holds the row's own index and adds +0, as in the per-hop sweep;
-// weighted terms are rounded before they are added (no fused multiply-add).
+// s += sum over the graph slots of a local row of [w] y_j; columns (local
+// index + 1) from LDS, y in LDS with y0 pointing at the row of zeros before
+// the buffer, weights (WG) from the tile's slot array in global memory.  A
+// padding slot (0) reads that zero row and adds +0, as the per-hop sweep adds
+// +0 for it (same sums, same order, no selection); weighted terms are rounded
+// before they are added (no fused multiply-add).
 template <bool WG>
-__device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const float* __restrict__ gw, int r,
-                                            const float4* y, int q, float (&s)[4]) {
+__device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const float* __restrict__ gw,
+                                            const float4* y0, int q, float (&s)[4]) {
 #pragma clang fp contract(off)
   for (int k = 0; k < wg; k += 4) {
     const ushort4 jj = *reinterpret_cast<const ushort4*>(lc + k);
@@ -534,12 +539,12 @@ __device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const fl
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float4 t = y[j[e] * kTileQ + q];
+      const float4 t = y0[j[e] * kTileQ + q];
       float v[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if constexpr (WG) v[c] *= ew[e];
-        s[c] += (j[e] != r) ? v[c] : 0.f;
+        s[c] += v[c];
       }
     }
   }
@@ -580,7 +585,13 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
   const int q = threadIdx.x % kTileQ;
   const int p0 = threadIdx.x / kTileQ;
   const int KM = T.KM, wg = T.wg;
-  float4* S = conv_smem;
+  float4* S = conv_smem + lo.xs;
+  // the rows of zeros before the three buffers (never written again; the
+  // first barrier below orders them before any read)
+  for (int z = threadIdx.x; z < 3 * kTileQ; z += blockDim.x) {
+    const int base = z < kTileQ ? lo.xs : (z < 2 * kTileQ ? lo.y0 : lo.y1);
+    conv_smem[base - kTileQ + z % kTileQ] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   uint2* LC2 = reinterpret_cast<uint2*>(conv_smem + lo.col);
   const uint16_t* LC = reinterpret_cast<const uint16_t*>(conv_smem + lo.col);
   float* LI = reinterpret_cast<float*>(conv_smem + lo.idg);
@@ -666,28 +677,32 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
     const int* cn = T.cnt + (size_t)h.t * (KM + 1);
     const float* gw = WG ? T.lgw + h.m0 : nullptr;
     // hops 1 .. K-1 on the nodes at distance <= K - hop; the first applies c_K, the
-    // others continue Horner's rule with factor 1 (hop_value, a == 1 exactly)
-    const float4* yin = S;
-    for (int hp = 1; hp < K; ++hp) {
+    // others continue Horner's rule with factor 1 (hop_value1, a == 1 exactly).
+    // yin points at the row of zeros before the hop's input buffer.
+    const float4* yin = S - kTileQ;
+    auto hop_pass = [&](auto scaled, int hp) {
       const int rows = cn[K - hp];
-      const float a = hp == 1 ? cf.c[K] : 1.f;
-      const bool scaled = hp == 1;
       const float cc = cf.c[K - hp];
       float4* yo = conv_smem + ((hp & 1) ? lo.y0 : lo.y1);
       for (int r = p0; r < rows; r += kTileNp) {
         float s[4] = {0.f, 0.f, 0.f, 0.f};
-        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, r, yin, q, s);
+        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, yin, q, s);
         const float idg = LI[r];
         const float4 xv = S[r * kTileQ + q];
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
         float o[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[c] = scaled ? hop_value(a, idg, s[c], cc, xs[c]) : hop_value1(idg, s[c], cc, xs[c]);
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (decltype(scaled)::value) o[c] = hop_value(cf.c[K], idg, s[c], cc, xs[c]);
+          else o[c] = hop_value1(idg, s[c], cc, xs[c]);
+        }
         yo[r * kTileQ + q] = make_float4(o[0], o[1], o[2], o[3]);
       }
       __syncthreads();
-      yin = yo;
-    }
+      yin = yo - kTileQ;
+    };
+    hop_pass(std::true_type{}, 1);
+    for (int hp = 2; hp < K; ++hp) hop_pass(std::false_type{}, hp);
     // last hop on the own nodes, fused with the output update (factor 1: K >= 2)
     const float c0 = cf.c[0];
     const int col = h.g * kTileCols + q * 4;
@@ -696,7 +711,7 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
       const int r = p0 + e * kTileNp;
       if (r < h.own) {
         float s[4] = {0.f, 0.f, 0.f, 0.f};
-        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, r, yin, q, s);
+        tile_gather<WG>(wg, LC + r * wg, WG ? gw + (size_t)r * wg : nullptr, yin, q, s);
         const float idg = LI[r];
         const float4 xv = S[r * kTileQ + q];
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};

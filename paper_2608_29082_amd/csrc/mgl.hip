@@ -748,7 +748,7 @@ struct Engine final : EngineBase {
       td.lgw = wgt() ? static_cast<const float*>(put(lgw[l].data(), lgw[l].size() * sizeof(float))) : nullptr;
       for (int K = 2; K <= t.KM; ++K) {
         const TileLayout y = tile_layout(t, K, kTileCols);
-        d[l].tlo[K] = TileLds{y.y0, y.y1, y.col, y.idg};
+        d[l].tlo[K] = TileLds{y.xs, y.y0, y.y1, y.col, y.idg};
         d[l].tlds[K] = tile_lds_bytes(t, K, kTileCols);
         maxlds = std::max(maxlds, d[l].tlds[K]);
       }

@@ -10,7 +10,8 @@
 // the convolution over the tile need nothing outside the list: hop h is
 // computed on the nodes at distance <= K - h, whose neighbours are all at
 // distance <= K - h + 1.  The graph columns of the listed nodes at distance
-// <= KM - 1 are stored as local (list) indices.
+// <= KM - 1 are stored as local (list) indices plus one; 0 marks a padding
+// slot, which the kernel reads from a row of zeros kept before each buffer.
 #pragma once
 #include <algorithm>
 #include <cstdint>
@@ -27,24 +28,26 @@ struct TilePlan {
   std::vector<int> node;         // global node ids, own nodes first, then by distance
   std::vector<int> cnt;          // ntiles x (KM + 1): nodes at distance <= d from the own nodes
   std::vector<int> goff;         // ntiles + 1: start of each tile's local columns in `lcol`
-  std::vector<uint16_t> lcol;    // rows at distance <= KM - 1, wg local columns per row (own index: padding)
+  std::vector<uint16_t> lcol;    // rows at distance <= KM - 1, wg local columns + 1 per row (0: padding)
   std::vector<int> maxcnt;       // KM + 1: maxima of cnt over the tiles
 };
 
 // LDS layout of one workgroup for a convolution of K >= 2 hops over `cols`
-// columns, in 16-byte units: the input on the nodes at distance <= K at 0,
-// hop buffers at y0 (distance <= K - 1) and y1 (distance <= K - 2), the
+// columns, in 16-byte units: the input on the nodes at distance <= K at xs,
+// hop buffers at y0 (distance <= K - 1) and y1 (distance <= K - 2), each of
+// the three preceded by one row of zeros (what a padding slot reads), the
 // local graph columns (uint16) and row scales (float) of the rows at
 // distance <= K - 1 at col and idg; `end` is the total.
 struct TileLayout {
-  int y0 = 0, y1 = 0, col = 0, idg = 0, end = 0;
+  int xs = 0, y0 = 0, y1 = 0, col = 0, idg = 0, end = 0;
 };
 inline TileLayout tile_layout(const TilePlan& tp, int K, int cols) {
   TileLayout t;
   if (K < 2 || K > tp.KM) return t;
   const int m = tp.maxcnt[K - 1], u = cols / 4;
-  t.y0 = u * tp.maxcnt[K];
-  t.y1 = t.y0 + u * m;
+  t.xs = u;
+  t.y0 = t.xs + u * tp.maxcnt[K] + u;
+  t.y1 = t.y0 + u * m + u;
   t.col = t.y1 + (K >= 3 ? u * tp.maxcnt[K - 2] : 0);
   t.idg = t.col + (m * tp.wg * 2 + 15) / 16;
   t.end = t.idg + (m * 4 + 15) / 16;
@@ -199,7 +202,7 @@ inline bool build_tiles(int n, int ld, int wg, const int* col, int KM, int h, in
         a = e;
         c[d] = (int)L.size();
       }
-      if (L.size() > 65535) { bad[tid] = 1; continue; }
+      if (L.size() > 65534) { bad[tid] = 1; continue; }
       const int rows = c[KM - 1];
       std::vector<uint16_t>& lc = lcols[t];
       lc.resize((size_t)rows * wg);
@@ -207,7 +210,7 @@ inline bool build_tiles(int n, int ld, int wg, const int* col, int KM, int h, in
         const int g = L[r];
         for (int k = 0; k < wg; ++k) {
           const int j = adj[(size_t)g * wg + k];
-          lc[(size_t)r * wg + k] = (uint16_t)(j == g ? r : loc[j]);
+          lc[(size_t)r * wg + k] = (uint16_t)(j == g ? 0 : loc[j] + 1);
         }
       }
     }
@@ -237,8 +240,9 @@ inline bool build_tiles(int n, int ld, int wg, const int* col, int KM, int h, in
 }
 
 // Checks the invariants the kernel relies on: every node is the own node of
-// exactly one tile, and each stored local column of a row at distance d
-// points at that neighbour, listed at distance <= d + 1.
+// exactly one tile, each stored local column of a row at distance d points
+// (minus one) at that neighbour, listed at distance <= d + 1, and padding
+// slots hold 0.
 inline bool check_tiles(int n, int ld, const int* col, const TilePlan& tp) {
   std::vector<int> owner(n, -1);
   const int KM = tp.KM;
@@ -266,9 +270,9 @@ inline bool check_tiles(int n, int ld, const int* col, const TilePlan& tp) {
         for (int r = d ? c[d - 1] : 0; r < c[d]; ++r)
           for (int k = 0; k < tp.wg; ++k) {
             const int j = col[(size_t)k * ld + L[r]];
-            const int q = lc[(size_t)r * tp.wg + k];
-            if (j == L[r]) { if (q != r) bad[tid] = 1; continue; }
-            if (q >= c[d + 1] || L[q] != j || q == r) bad[tid] = 1;
+            const int q = lc[(size_t)r * tp.wg + k] - 1;
+            if (j == L[r]) { if (q != -1) bad[tid] = 1; continue; }
+            if (q < 0 || q >= c[d + 1] || L[q] != j || q == r) bad[tid] = 1;
           }
     }
   });

@@ -72,9 +72,11 @@ int main(int argc, char** argv) {
         for (int r = 0; r < rows; ++r) {
           double s = 0.0;
           for (int q = 0; q < tp.wg; ++q) {
-            const int j = lc[(size_t)r * tp.wg + q];
-            if (j >= cn[K - h + 1]) { std::printf("local-column-out-of-range\n"); return 1; }
-            if (j != r) s += (*yin)[j];
+            const int e = lc[(size_t)r * tp.wg + q];   // local column + 1, 0: padding
+            if (e == 0) continue;
+            const int j = e - 1;
+            if (j >= cn[K - h + 1] || j == r) { std::printf("local-column-out-of-range\n"); return 1; }
+            s += (*yin)[j];
           }
           Yn[r] = aa * (idg[nd[r]] * s) + c[K - h] * S[r];
         }
