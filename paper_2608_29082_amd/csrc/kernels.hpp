@@ -485,7 +485,8 @@ struct TileDev {
   const int* node;          // per tile: own nodes, then by distance
   const int* cnt;           // ntiles x (KM + 1): nodes at distance <= d
   const int* goff;          // ntiles + 1; goff / wg indexes the per-row arrays below
-  const uint16_t* lcol;     // local graph columns of the rows at distance <= KM - 1 (padding: own index)
+  const uint16_t* lcol;     // local graph columns of the rows at distance <= KM - 1: (index + 1) x the
+                            // LDS row size in bytes (0: padding, the row of zeros)
   const float* lidg;        // row scale of the aggregation (invdeg) of those rows
   const float* lgw;         // edge weights in their slots (weighted / symmetric aggregation), or null
 };
@@ -496,7 +497,7 @@ struct TileCoef {
 struct TileLds {
   int xs;                   // input rows
   int y0, y1;               // hop buffers (each of the three preceded by a row of zeros)
-  int col;                  // local columns + 1 (uint16, 0: padding) of the rows at distance <= K - 1
+  int col;                  // local columns of the rows at distance <= K - 1 as byte offsets (uint16)
   int idg;                  // their row scales (float)
 };
 
@@ -519,16 +520,17 @@ __device__ __forceinline__ void st4v(bf16_t* p, const float (&v)[4]) {
   *reinterpret_cast<uint2*>(p) = t;
 }
 
-// s += sum over the graph slots of a local row of [w] y_j; columns (local
-// index + 1) from LDS, y in LDS with y0 pointing at the row of zeros before
-// the buffer, weights (WG) from the tile's slot array in global memory.  A
-// padding slot (0) reads that zero row and adds +0, as the per-hop sweep adds
-// +0 for it (same sums, same order, no selection); weighted terms are rounded
-// before they are added (no fused multiply-add).
+// s += sum over the graph slots of a local row of [w] y_j; columns from LDS as
+// byte offsets ((local index + 1) x row size) from y0, the row of zeros before
+// the LDS buffer, weights (WG) from the tile's slot array in global memory.  A
+// padding slot (offset 0) reads that zero row and adds +0, as the per-hop sweep
+// adds +0 for it (same sums, same order, no selection); weighted terms are
+// rounded before they are added (no fused multiply-add).
 template <bool WG>
 __device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const float* __restrict__ gw,
                                             const float4* y0, int q, float (&s)[4]) {
 #pragma clang fp contract(off)
+  const char* yb = reinterpret_cast<const char*>(y0 + q);
   for (int k = 0; k < wg; k += 4) {
     const ushort4 jj = *reinterpret_cast<const ushort4*>(lc + k);
     const int j[4] = {jj.x, jj.y, jj.z, jj.w};
@@ -539,7 +541,7 @@ __device__ __forceinline__ void tile_gather(int wg, const uint16_t* lc, const fl
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float4 t = y0[j[e] * kTileQ + q];
+      const float4 t = *reinterpret_cast<const float4*>(yb + j[e]);
       float v[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {

@@ -692,6 +692,7 @@ struct Engine final : EngineBase {
     };
     std::vector<TilePlan> tp(pl.J);
     std::vector<std::vector<float>> lidg(pl.J), lgw(pl.J);
+    std::vector<std::vector<uint16_t>> lcb(pl.J);
     size_t bytes = 0;
     auto a256 = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
     for (int l = 0; l < pl.J; ++l) {
@@ -743,7 +744,12 @@ struct Engine final : EngineBase {
       td.goff = static_cast<const int*>(put(t.goff.data(), t.goff.size() * sizeof(int)));
       td.node = static_cast<const int*>(put(t.node.data(), t.node.size() * sizeof(int)));
       td.cnt = static_cast<const int*>(put(t.cnt.data(), t.cnt.size() * sizeof(int)));
-      td.lcol = static_cast<const uint16_t*>(put(t.lcol.data(), t.lcol.size() * sizeof(uint16_t)));
+      // local columns as byte offsets from the buffer's row of zeros (one LDS row: kTileCols floats);
+      // at most kTileRows * kTileNp listed rows (fits above), so they fit 16 bits
+      static_assert((kTileRows * kTileNp + 1) * kTileCols * sizeof(float) <= 65535, "16-bit LDS offsets");
+      lcb[l].resize(t.lcol.size());
+      for (size_t k = 0; k < t.lcol.size(); ++k) lcb[l][k] = (uint16_t)(t.lcol[k] * (kTileCols * sizeof(float)));
+      td.lcol = static_cast<const uint16_t*>(put(lcb[l].data(), lcb[l].size() * sizeof(uint16_t)));
       td.lidg = static_cast<const float*>(put(lidg[l].data(), lidg[l].size() * sizeof(float)));
       td.lgw = wgt() ? static_cast<const float*>(put(lgw[l].data(), lgw[l].size() * sizeof(float))) : nullptr;
       for (int K = 2; K <= t.KM; ++K) {
