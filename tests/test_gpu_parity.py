@@ -47,7 +47,7 @@ def test_fp64_cycle_matches_oracle(case, K):
         assert err <= TOL["fp64"]
 
 
-@pytest.mark.parametrize("B", [2, 32, 64, 100])
+@pytest.mark.parametrize("B", [2, 32, 64, 100, 256])
 def test_fp64_cycle_batch_widths(B):
     hier = dict(small_cases())["blocks65"]
     err, got, _ = _cycle_case(hier, 3, B, seed=B)

@@ -243,3 +243,36 @@ def test_fused_conv_equals_hop_chain_bench_hierarchy(B):
     assert all(c == 6 for c in per_level) and n_off == 0
     assert d1.max() == 0.0 and d2.max() == 0.0
     on.close(); off.close()
+
+
+@pytest.mark.parametrize("agg", ["mean", "weighted"])
+def test_fused_conv_equals_hop_chain_widest_batch(agg):
+    """The widest batch the library takes (B = 256: sixteen column groups per
+    tile, 64 lanes per row in the sweeps) on the 129 x 129 hierarchy: the fused
+    convolution equals the per-hop sweeps bit for bit, and the cycle is within
+    the FP32 tolerance of the FP64 oracle on sampled columns."""
+    import torch
+    name, hier = CASES[0]
+    J = hier.nlevels
+    B, K = 256, (3, 3, 3)
+    flat = C.random_params(J, *K, seed=103, spread=0.2)
+    g = C.rng(6, 23, 0)
+    f = g.standard_normal((hier.sizes[0], B))
+    u = g.standard_normal((hier.sizes[0], B))
+    on, off = _pair(hier, flat, K, B, "fp32", aggregation=agg)
+    outs = []
+    for ctx in (on, off):
+        ud = to_dev(u, torch.float32)
+        ctx.vcycle(to_dev(f, torch.float32), ud)
+        outs.append(to_np(ud))
+    n_on = _conv_launches(on, to_dev(f, torch.float32), to_dev(u, torch.float32))
+    d = float(np.abs(outs[0] - outs[1]).max())
+    cols = [0, 17, 100, 255]
+    lv = O.make_levels(hier.A, hier.P, hier.R, aggregation=agg)
+    want = O.lmg(lv, O.unpack(flat, J, *K, 2, 2), 0, f[:, cols], u[:, cols])
+    err = elem_rel(outs[0][:, cols], want)
+    print(f"{name} {agg} B=256: fused launches {n_on}, max diff to hop chain {d:.1e}, rel to oracle {err:.2e}",
+          flush=True)
+    assert n_on > 0 and d == 0.0
+    assert err <= TOL["fp32"]
+    on.close(); off.close()
