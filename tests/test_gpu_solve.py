@@ -43,7 +43,16 @@ def test_mixed_precision_reaches_1e8(precision):
     assert np.all(relres <= 1e-8)
     ref = O.solve(oracle_levels(w.hier), oracle_params(w.params, w.hier.nlevels, 3), w.f[:, :2], rtol=1e-12)
     err = np.linalg.norm(u[:, :2] - ref.u, axis=0) / np.linalg.norm(ref.u, axis=0)
-    print("forward error vs FP64 oracle solution", err, flush=True)
+    # a posteriori bound for the SPD operator: ||u - u*|| <= ||A^{-1}||_2 ||f - A u|| = ||r|| / lambda_min,
+    # plus the reference's own residual (rtol 1e-12) the same way
+    from scipy.sparse.linalg import eigsh
+    A = w.hier.A[0].tocsc()
+    lam_min = float(eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0])
+    r_gpu = np.linalg.norm(w.f[:, :2] - A @ u[:, :2], axis=0)
+    r_ref = np.linalg.norm(w.f[:, :2] - A @ ref.u, axis=0)
+    bound = (r_gpu + r_ref) / lam_min / np.linalg.norm(ref.u, axis=0)
+    print("forward error vs FP64 oracle solution", err, "bound", bound, flush=True)
+    assert np.all(err <= bound * (1 + 1e-6)) and np.all(bound < 1e-3)
 
 
 def test_mixed_lshape_reaches_1e8():
