@@ -520,6 +520,15 @@ __device__ __forceinline__ void st4v(bf16_t* p, const float (&v)[4]) {
   *reinterpret_cast<uint2*>(p) = t;
 }
 
+// A read of memory that no kernel of the launch writes (the tile metadata),
+// through the constant address space: wave-uniform addresses become scalar
+// loads, which are waited on apart from the vector loads in flight (those
+// complete in order, so any wait on a vector load would also wait for every
+// prefetch issued before it).
+__device__ __forceinline__ int ld_const(const int* p) {
+  return *(const __attribute__((address_space(4))) int*)p;
+}
+
 // s += sum over the graph slots of a local row of [w] y_j; columns from LDS as
 // byte offsets ((local index + 1) x row size) from y0, the row of zeros before
 // the LDS buffer, weights (WG) from the tile's slot array in global memory.  A
@@ -603,11 +612,11 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
     h.t = i / T.ngroups;
     h.g = i - h.t * T.ngroups;
     const int* cn = T.cnt + (size_t)h.t * (KM + 1);
-    h.cK = cn[K];
-    h.rows1 = cn[K - 1];
-    h.own = cn[0];
-    h.base = T.toff[h.t];
-    h.m0 = T.goff[h.t];
+    h.cK = ld_const(cn + K);
+    h.rows1 = ld_const(cn + K - 1);
+    h.own = ld_const(cn);
+    h.base = ld_const(T.toff + h.t);
+    h.m0 = ld_const(T.goff + h.t);
 #pragma unroll
     for (int e = 0; e < kTileRows; ++e) h.nd[e] = T.node[h.base + min(p0 + e * kTileNp, h.cK - 1)];
   };
@@ -683,7 +692,7 @@ __global__ __launch_bounds__(kTileThreads) void k_conv_tile(TileDev T, int B, in
     // yin points at the row of zeros before the hop's input buffer.
     const float4* yin = S - kTileQ;
     auto hop_pass = [&](auto scaled, int hp) {
-      const int rows = cn[K - hp];
+      const int rows = ld_const(cn + K - hp);
       const float cc = cf.c[K - hp];
       float4* yo = conv_smem + ((hp & 1) ? lo.y0 : lo.y1);
       for (int r = p0; r < rows; r += kTileNp) {
