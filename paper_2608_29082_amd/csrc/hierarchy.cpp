@@ -10,27 +10,58 @@
 // |a_ij| <= 1e-11 sqrt(|a_ii a_jj|) removed so that the stored pattern is the
 // matrix graph {(i, j): A_ij != 0} (Sec. 2.1).  Used for per-request setup
 // when serving; it builds inputs of the V-cycle, not the V-cycle itself.
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "mgl.h"
 
 namespace {
 
+// Host memory of the builders: blocks of 2 MiB and more are 2 MiB aligned
+// and marked for transparent huge pages, so that first touching them costs a
+// few hundred page faults instead of a few hundred thousand (on a grid of a
+// million unknowns the faults of 4 KiB pages took about a third of a build).
+struct HostFree {
+  void operator()(void* q) const { std::free(q); }
+};
+inline void* host_alloc(size_t bytes) {
+  constexpr size_t kHuge = size_t(2) << 20;
+  bytes = std::max<size_t>(bytes, 1);
+  if (bytes < kHuge) {
+    void* q = std::malloc(bytes);
+    if (!q) throw std::bad_alloc();
+    return q;
+  }
+  const size_t len = (bytes + kHuge - 1) / kHuge * kHuge;
+  void* q = std::aligned_alloc(kHuge, len);
+  if (!q) throw std::bad_alloc();
+  madvise(q, len, MADV_HUGEPAGE);   // advice only: without huge pages nothing changes
+  return q;
+}
+
 // Array whose elements start uninitialised (filled in parallel by the
 // builders, so the pages are first touched by the threads that write them).
 template <class T>
 struct Buf {
-  std::unique_ptr<T[]> p;
+  static_assert(std::is_trivial<T>::value, "Buf holds trivial element types");
+  std::unique_ptr<T[], HostFree> p;
   size_t n = 0;
   void resize(size_t m) {
-    p.reset(new T[std::max<size_t>(m, 1)]);
+    p.reset(static_cast<T*>(host_alloc(std::max<size_t>(m, 1) * sizeof(T))));
     n = m;
   }
   T& operator[](size_t i) { return p[i]; }
@@ -55,11 +86,13 @@ inline int unk(int side, int i, int j) {
   return (j - 1) * m + (i - 1);
 }
 
-// Rows assembled from (row, col, val) triplets with a dense per-row accumulator.
+// Rows assembled from (row, col, val) triplets with a dense per-row accumulator
+// (an entry's value is set when its mark first shows the row, so the values
+// need no initialisation).
 struct RowAcc {
-  std::vector<double> acc;
+  Buf<double> acc;
   std::vector<int> mark, cols;
-  explicit RowAcc(int n) : acc(n, 0.0), mark(n, -1) {}
+  explicit RowAcc(int n) : mark(n, -1) { acc.resize(n); }
   void add(int row, int c, double v) {
     if (mark[c] != row) {
       mark[c] = row;
@@ -70,7 +103,60 @@ struct RowAcc {
   }
 };
 
-// fn(r0, r1) over a split of [0, n) into at most 8 contiguous ranges, one thread each.
+// Worker threads of the builders, started on first use and kept for the life
+// of the process (a build makes a few dozen parallel loops; starting threads
+// for each took longer than the loops on grids below ~10^5 unknowns).
+class Workers {
+ public:
+  explicit Workers(int n) {
+    for (int i = 0; i < n; ++i) th_.emplace_back([this] { run(); });
+  }
+  ~Workers() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void submit(std::function<void()> f) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.push_back(std::move(f));
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  void run() {
+    for (;;) {
+      std::function<void()> f;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+        if (q_.empty()) return;   // stop_ and nothing left
+        f = std::move(q_.front());
+        q_.pop_front();
+      }
+      f();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::function<void()>> q_;
+  std::vector<std::thread> th_;
+  bool stop_ = false;
+};
+
+inline int host_threads() { return (int)std::max(1u, std::thread::hardware_concurrency()); }
+inline Workers& workers() {
+  static Workers w(std::min(host_threads(), 8) - 1);
+  return w;
+}
+
+// fn(r0, r1) over a split of [0, n) into at most 8 contiguous ranges of at
+// least about `grain` rows: the calling thread takes the first, the workers the
+// others.
 // Calls of this library building setup data at the same time (serving runs
 // several); their per-row loops share the host's threads between them.
 std::atomic<int> g_active_calls{0};
@@ -80,15 +166,25 @@ struct ActiveCall {
 };
 
 template <class F>
-void par_rows(int n, F&& fn) {
-  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int share = std::max(1, hw / std::max(1, g_active_calls.load()));
-  const int nt = std::max(1, std::min({share, 8, n / 8192 + 1}));
-  std::vector<std::thread> th;
+void par_rows(int n, F&& fn, int grain = 8192) {
+  const int share = std::max(1, host_threads() / std::max(1, g_active_calls.load()));
+  const int nt = std::max(1, std::min({share, 8, n / grain + 1}));
+  if (nt == 1) {
+    fn(0, n);
+    return;
+  }
+  std::mutex m;
+  std::condition_variable done;
+  int left = nt - 1;
   for (int t = 1; t < nt; ++t)
-    th.emplace_back([&, t] { fn((int)((long long)n * t / nt), (int)((long long)n * (t + 1) / nt)); });
+    workers().submit([&, t] {
+      fn((int)((long long)n * t / nt), (int)((long long)n * (t + 1) / nt));
+      std::lock_guard<std::mutex> g(m);
+      if (--left == 0) done.notify_one();
+    });
   fn(0, (int)((long long)n / nt));
-  for (auto& x : th) x.join();
+  std::unique_lock<std::mutex> lk(m);
+  done.wait(lk, [&] { return left == 0; });
 }
 
 // CSR with known row lengths: rowptr from the counts, arrays sized once.
@@ -114,7 +210,9 @@ Csr assemble(int side, int nb, const double* blocks) {
   // coefficient of the block containing each triangle's centroid
   // (ci + 2/3, cj + 1/3) (lower-right) and (ci + 1/3, cj + 2/3) (upper-left),
   // exactly in integers
-  std::vector<double> lr((size_t)cells * cells), ul((size_t)cells * cells);
+  Buf<double> lr, ul;
+  lr.resize((size_t)cells * cells);
+  ul.resize((size_t)cells * cells);
   auto blk = [&](int c3, int d3) {   // coordinates times 3*cells
     int bi = (int)((long long)c3 * nb / (3LL * cells));
     int bj = (int)((long long)d3 * nb / (3LL * cells));
@@ -221,6 +319,7 @@ Csr restriction(int side_f) {
 // |a_IJ| <= 1e-11 sqrt(|a_II a_JJ|) and exact zeros removed (residue of exactly cancelling
 // couplings reaches ~1e-13 on the coarsest levels; genuine couplings stay above ~1e-4).
 Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
+  constexpr int kGalerkinGrain = 512;   // rows of R A P per thread at least (~1 us each)
   const int nc = R.nrows;
   // pass 1: the sorted column pattern and values of every row of R A P; each thread keeps its
   // rows in flat buffers of its own, gathered afterwards into one CSR T
@@ -263,7 +362,7 @@ Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
     }
     std::lock_guard<std::mutex> lk(mu);
     chunks.push_back(std::move(ch));
-  });
+  }, kGalerkinGrain);
   Csr T = alloc_csr(nc, nc, cnt);
   for (const Chunk& ch : chunks) {
     std::copy(ch.col.begin(), ch.col.end(), T.col.data() + T.rowptr[ch.r0]);
@@ -299,7 +398,7 @@ Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
       }
       cnt[I] = c;
     }
-  });
+  }, kGalerkinGrain);
   Csr o = alloc_csr(nc, nc, cnt);
   par_rows(nc, [&](int r0, int r1) {
     for (int I = r0; I < r1; ++I) {

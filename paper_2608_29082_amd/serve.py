@@ -371,13 +371,19 @@ class Server:
 
 def pattern_key(hier) -> str:
     """Key of a native hierarchy's level patterns (row pointers and columns of
-    every A_l): requests with equal keys can share a batch context."""
-    import hashlib
-    hs = hashlib.sha1()
+    every A_l): requests with equal keys can share a batch context.  The arrays
+    are hashed in place (xxh3-128, or SHA-1 where xxhash is not installed)."""
+    try:
+        import xxhash
+        hs = xxhash.xxh3_128()
+    except ImportError:
+        import hashlib
+        hs = hashlib.sha1()
     for l in range(hier.nlevels):
         m = hier.view.A[l]
-        hs.update(np.ctypeslib.as_array(m.rowptr, shape=(m.nrows + 1,)).tobytes())
-        hs.update(np.ctypeslib.as_array(m.col, shape=(max(int(m.nnz), 1),))[: int(m.nnz)].tobytes())
+        hs.update(np.ctypeslib.as_array(m.rowptr, shape=(m.nrows + 1,)))
+        if m.nnz > 0:
+            hs.update(np.ctypeslib.as_array(m.col, shape=(int(m.nnz),)))
     return f"{hier.sizes[0]}:{hs.hexdigest()[:16]}"
 
 

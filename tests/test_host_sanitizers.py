@@ -10,7 +10,10 @@ Two drivers built with the host compiler and -fsanitize=address,undefined
     refused with MG_ERR_SHAPE before any out-of-bounds read;
   * tests/native/tiles_check.cpp: the fused convolution's tiling
     (csrc/tiles.hpp: 16-bit local columns, per-item metadata) on grid levels,
-    an unstructured mesh and random graphs."""
+    an unstructured mesh and random graphs.
+A third, tests/native/concurrent_build.cpp, runs under the thread sanitizer:
+four threads build hierarchies at once through the builder's shared worker
+threads, and each result must equal the same build done alone."""
 import os
 import shutil
 import subprocess
@@ -29,12 +32,12 @@ SAN = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
 
 
-def _build(tmp_path_factory, name, srcs):
+def _build(tmp_path_factory, name, srcs, flags=SAN):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
     exe = tmp_path_factory.mktemp(name) / name
-    subprocess.run([cxx, *SAN, "-std=c++17", "-pthread", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    subprocess.run([cxx, *flags, "-std=c++17", "-pthread", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                     *srcs, "-o", str(exe)], check=True)
     return str(exe)
 
@@ -81,3 +84,14 @@ def test_tiles_under_sanitizers(tiles_driver, tmp_path):
     A = H.square_hierarchy(33).A[0]
     _run_tiles(tiles_driver, _ell(sp.block_diag([A, A]).tocsr(), str(tmp_path)), 3, 8)
     _run_tiles(tiles_driver, _ell(_random_graph(2000, 2, 1), str(tmp_path)), 2, 8)
+
+
+def test_concurrent_builds_under_thread_sanitizer(tmp_path_factory):
+    exe = _build(tmp_path_factory, "concurrent_build",
+                 [os.path.join(HERE, "native", "concurrent_build.cpp"), os.path.join(CSRC, "hierarchy.cpp")],
+                 flags=["-O1", "-g", "-fsanitize=thread", "-fno-omit-frame-pointer"])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=600,
+                         env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ThreadSanitizer" not in out.stderr, out.stderr
+    assert out.stdout.split() == ["ok", "0"], out.stdout
