@@ -187,7 +187,8 @@ mg_status mg_set_params(mg_ctx* ctx, const double* values, void* stream);
  * other columns are not touched.  Synchronises `stream`; must not overlap a
  * solve on the context.  MG_ERR_STATE for a context with shared operators,
  * MG_ERR_SHAPE (context unchanged) for values off the rules or a singular
- * coarsest operator. */
+ * coarsest operator.  The first call allocates a pinned host buffer for one
+ * column's arrays of every level, kept by the context until mg_destroy. */
 mg_status mg_load_column(mg_ctx* ctx, int32_t b, const double* const* values, void* stream);
 
 /* Change mg_solve's options after setup (same meaning and limits as the

@@ -254,6 +254,8 @@ struct Engine final : EngineBase {
   int* cmap = nullptr;              // device [nrhs]
   int* vmapd = nullptr;             // per-column operators: device [nrhs], operator column of each slot
   double* colstage = nullptr;       // per-column operators: one column's level arrays (mg_load_column)
+  double* colhost = nullptr;        // pinned host: all level arrays of one column (mg_load_column)
+  size_t colhost_n = 0;             // its size in doubles
   int* cfrom = nullptr;             // device [nrhs]: old slot of each new slot (repack)
   int* hmap = nullptr;              // pinned host [3 nrhs]: flags, new map, repack sources
   std::vector<int> hcur;            // host copy of cmap
@@ -267,6 +269,7 @@ struct Engine final : EngineBase {
     if (tile_mem) (void)hipFree(tile_mem);
     if (hcount) (void)hipHostFree(hcount);
     if (hmap) (void)hipHostFree(hmap);
+    if (colhost) (void)hipHostFree(colhost);
   }
 
   bool bwd() const { return (pl.flags & MG_FLAG_BACKWARD) != 0; }
@@ -846,19 +849,29 @@ struct Engine final : EngineBase {
     for (int l = 0; l < pl.J; ++l)
       if (!vals[l]) return fail(MG_ERR_INVALID_ARG, "null values of level " + std::to_string(l));
     const int J = pl.J;
-    // validate every level first, so a refused column leaves the context unchanged
-    std::vector<std::vector<double>> hs(J);
-    for (int l = 0; l < J; ++l) {
-      const HLevel& H = pl.lv[l];
-      const int w = H.off.w, ld = H.off.ld;
-      mg_csr pat{H.n, H.n, (int64_t)pl.pcol[l].size(), pl.prow[l].data(), pl.pcol[l].data(), nullptr};
-      hs[l].assign((size_t)(w + 1) * ld, 0.0);
-      MG_TRY(column_arrays(&pat, vals[l], H, hs[l].data(), hs[l].data() + (size_t)w * ld, l, b));
+    // every level's arrays into one pinned host buffer (kept for the next
+    // call: no page faults, and the copies run at the host link's DMA rate),
+    // validated first, so a refused column leaves the context unchanged
+    std::vector<size_t> at(J + 1, 0);
+    for (int l = 0; l < J; ++l) at[l + 1] = at[l] + (size_t)(pl.lv[l].off.w + 1) * pl.lv[l].off.ld;
+    if (colhost_n < at[J]) {
+      if (colhost) HIP_TRY(hipHostFree(colhost));
+      colhost = nullptr;
+      colhost_n = 0;
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&colhost), at[J] * sizeof(double), hipHostMallocDefault));
+      colhost_n = at[J];
     }
     for (int l = 0; l < J; ++l) {
       const HLevel& H = pl.lv[l];
       const int w = H.off.w, ld = H.off.ld;
-      HIP_TRY(hipMemcpyAsync(colstage, hs[l].data(), hs[l].size() * sizeof(double), hipMemcpyHostToDevice, st));
+      mg_csr pat{H.n, H.n, (int64_t)pl.pcol[l].size(), pl.prow[l].data(), pl.pcol[l].data(), nullptr};
+      MG_TRY(column_arrays(&pat, vals[l], H, colhost + at[l], colhost + at[l] + (size_t)w * ld, l, b));
+    }
+    for (int l = 0; l < J; ++l) {
+      const HLevel& H = pl.lv[l];
+      const int w = H.off.w, ld = H.off.ld;
+      HIP_TRY(hipMemcpyAsync(colstage, colhost + at[l], (at[l + 1] - at[l]) * sizeof(double), hipMemcpyHostToDevice,
+                             st));
       const bool f64 = l == 0 && !std::is_same<C, double>::value;
       const long cnt = std::max<long>((long)w * ld, ld);
       hipLaunchKernelGGL((k_put_column<C>), dim3(nblocks(cnt)), dim3(256), 0, st, w, ld, H.n, pl.nv, b,

@@ -528,7 +528,9 @@ class BatchServer:
                     hier = Bd.SquareHierarchy(req.side, req.blocks)
                     if self.fail_setup is not None and self.fail_setup(req):
                         raise RuntimeError(f"setup of request {req.rid} failed (injected)")
-                    admit((req, t_arr, hier, pattern_key(hier)))
+                    # the right-hand side is drawn here, in parallel, not in the batch's thread
+                    fv = torch.from_numpy(np.ascontiguousarray(req.f[:, 0], dtype=np.float64)).pin_memory()
+                    admit((req, t_arr, hier, pattern_key(hier), fv))
                 except Exception as e:  # report and keep serving
                     if hier is not None:
                         hier.close()
@@ -583,7 +585,7 @@ class BatchServer:
                 with torch.cuda.stream(stream):
                     first = g.q.get()
                     pending.append(first)
-                    req0, _, hier0, _ = first
+                    req0, _, hier0 = first[:3]
                     params = self._params(hier0.nlevels, req0.side)
                     fp = self._footprint(hier0, params)
                     self.budget.acquire(fp)
@@ -607,14 +609,14 @@ class BatchServer:
                                     pending.append(g.q.get_nowait())
                                 except queue.Empty:
                                     break
-                            req, t_arr, hier, _ = pending.pop(0)
+                            req, t_arr, hier, _, fv = pending.pop(0)
                             b = free[0]
                             try:
                                 ctx.load_column(b, hier)
                             finally:
                                 hier.close()
                                 side_sem(req.side).release()
-                            f[:, b] = torch.as_tensor(req.f[:, 0], device=self.device)
+                            f[:, b].copy_(fv, non_blocking=True)
                             u[:, b] = 0.0
                             slots[b] = [req, t_arr, now(), None, 0,
                                         Progress(self.diverge_factor, self.stall_cycles, self.stall_window)]
@@ -670,7 +672,7 @@ class BatchServer:
                         waiting.append(g.q.get_nowait())
                     except queue.Empty:
                         break
-                for rq, _, hh, _ in waiting:   # built hierarchies never loaded: free them
+                for rq, _, hh, *_ in waiting:   # built hierarchies never loaded: free them
                     hh.close()
                     side_sem(rq.side).release()
                 left += [it[0] for it in waiting]
