@@ -9,9 +9,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -357,31 +359,69 @@ struct HostPlan {
 // padding 0), dg[i] the diagonal (rows [n, ld): 1).  The values must be finite
 // with nonzero off-diagonal entries and diagonal, so the column's graph is the
 // pattern's.
-mg_status column_arrays(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b) {
-  const int n = A->nrows, ld = L.off.ld, w = L.off.w;
-  std::fill(off, off + (size_t)w * ld, 0.0);
-  std::fill(dg, dg + ld, 1.0);
-  for (int i = 0; i < n; ++i) {
+// Rows [r0, r1) of column_arrays: on a value off the rules, the failing row
+// (INT_MAX when the row count of the message does not apply) and the message.
+mg_status column_rows(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b,
+                      int r0, int r1, int& row, std::string& msg) {
+  const int ld = L.off.ld, w = L.off.w;
+  for (int k = 0; k < w; ++k) std::fill(off + (size_t)k * ld + r0, off + (size_t)k * ld + r1, 0.0);
+  for (int i = r0; i < r1; ++i) {
     int k = 0;
     bool has_diag = false;
     for (int p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
       const double x = v[p];
-      if (!std::isfinite(x) || x == 0.0)
-        return fail(MG_ERR_SHAPE, "column " + std::to_string(b) + " of A[" + std::to_string(l) +
-                                      "]: zero or non-finite value on the pattern at row " + std::to_string(i));
+      if (!std::isfinite(x) || x == 0.0) {
+        row = i;
+        msg = "column " + std::to_string(b) + " of A[" + std::to_string(l) +
+              "]: zero or non-finite value on the pattern at row " + std::to_string(i);
+        return MG_ERR_SHAPE;
+      }
       if (A->col[p] == i) {
         dg[i] = x;
         has_diag = true;
       } else {
-        if (k >= w) return fail(MG_ERR_SHAPE, "column values do not fit the pattern's width");
+        if (k >= w) {
+          row = i;
+          msg = "column values do not fit the pattern's width";
+          return MG_ERR_SHAPE;
+        }
         off[(size_t)k * ld + i] = x;
         ++k;
       }
     }
-    if (!has_diag)
-      return fail(MG_ERR_SHAPE, "A[" + std::to_string(l) + "]: no diagonal entry at row " + std::to_string(i));
+    if (!has_diag) {
+      row = i;
+      msg = "A[" + std::to_string(l) + "]: no diagonal entry at row " + std::to_string(i);
+      return MG_ERR_SHAPE;
+    }
   }
   return MG_OK;
+}
+
+mg_status column_arrays(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b) {
+  const int n = A->nrows, ld = L.off.ld, w = L.off.w;
+  // rows [n, ld) of the padded layout
+  for (int k = 0; k < w; ++k) std::fill(off + (size_t)k * ld + n, off + (size_t)(k + 1) * ld, 0.0);
+  std::fill(dg + n, dg + ld, 1.0);
+  // rows in parallel; the reported error is the one of the first failing row,
+  // as a pass in row order would report it
+  std::mutex mu;
+  int first = INT_MAX;
+  mg_status st = MG_OK;
+  std::string msg;
+  par_rows(n, [&](int r0, int r1) {
+    int row = INT_MAX;
+    std::string m;
+    const mg_status s = column_rows(A, v, L, off, dg, l, b, r0, r1, row, m);
+    if (s == MG_OK) return;
+    std::lock_guard<std::mutex> g(mu);
+    if (st == MG_OK || row < first) {
+      first = row;
+      st = s;
+      msg = m;
+    }
+  });
+  return st == MG_OK ? MG_OK : fail(st, msg);
 }
 
 // Coefficients of the Chebyshev polynomials, T_k(t) = sum_m t[k][m] t^m, k, m <= 8.

@@ -9,8 +9,10 @@
 // feeds malformed copies of the hierarchy to the validation and prints one
 // line per case:  <case> <status>.  Exit status 0 unless a case returns a
 // status other than the expected one.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <random>
 #include <vector>
 
@@ -118,6 +120,38 @@ int main(int argc, char** argv) {
     std::vector<double> vl = {1.0, 1.0};
     mg_csr m{2, 2, 2, rp.data(), cl.data(), vl.data()};
     expect("rowptr-overrun-sorted", check_csr(&m, "A", 0), MG_ERR_SHAPE);
+  }
+  {
+    // one column's operator arrays (per-column operators, converted by row
+    // ranges in parallel): equal to the plan's own ELL arrays; with bad values
+    // in two rows, far apart, the error names the first of them, as a pass in
+    // row order would
+    HostPlan pl;
+    expect("plan-columns", plan_of(h, 0, pl), MG_OK);
+    const HLevel& L0 = pl.lv[0];
+    const int w = L0.off.w, ld = L0.off.ld;
+    std::vector<double> off((size_t)w * ld, -1.0), dg(ld, -1.0);
+    expect("column", column_arrays(&h.A[0], h.A[0].val, L0, off.data(), dg.data(), 0, 0), MG_OK);
+    for (size_t k = 0; k < off.size(); ++k)
+      if (off[k] != L0.off.val[k]) {
+        std::printf("  column arrays differ from the plan's at slot %zu\n", k);
+        ++g_bad;
+        break;
+      }
+    for (int i = 0; i < ld; ++i)
+      if (dg[i] != (i < n0 ? L0.diag[i] : 1.0)) {
+        std::printf("  column diagonal differs from the plan's at row %d\n", i);
+        ++g_bad;
+        break;
+      }
+    std::vector<double> bad(h.A[0].val, h.A[0].val + h.A[0].nnz);
+    const int ra = n0 / 2 + 3, rb = n0 - 5;
+    bad[h.A[0].rowptr[rb]] = 0.0;
+    bad[h.A[0].rowptr[ra] + 1] = std::nan("");
+    expect("column-bad-values", column_arrays(&h.A[0], bad.data(), L0, off.data(), dg.data(), 0, 7), MG_ERR_SHAPE);
+    const std::string want = "column 7 of A[0]: zero or non-finite value on the pattern at row " + std::to_string(ra);
+    std::printf("column-bad-message %s\n", g_err.c_str());
+    if (g_err != want) ++g_bad;
   }
   mg_host_hierarchy_free(hh);
   // sides that do not coarsen to the coarsest size are refused
