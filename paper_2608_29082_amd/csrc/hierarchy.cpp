@@ -213,13 +213,10 @@ Csr assemble(int side, int nb, const double* blocks) {
   Buf<double> lr, ul;
   lr.resize((size_t)cells * cells);
   ul.resize((size_t)cells * cells);
-  auto blk = [&](int c3, int d3) {   // coordinates times 3*cells
-    int bi = (int)((long long)c3 * nb / (3LL * cells));
-    int bj = (int)((long long)d3 * nb / (3LL * cells));
-    bi = std::min(bi, nb - 1);
-    bj = std::min(bj, nb - 1);
-    return blocks[(size_t)bj * nb + bi];
-  };
+  // block index of each coordinate times 3*cells (one division per coordinate, not per triangle)
+  std::vector<int> bix((size_t)3 * cells);
+  for (int c3 = 0; c3 < 3 * cells; ++c3) bix[c3] = std::min((int)((long long)c3 * nb / (3LL * cells)), nb - 1);
+  auto blk = [&](int c3, int d3) { return blocks[(size_t)bix[d3] * nb + bix[c3]]; };
   par_rows(cells, [&](int j0, int j1) {
     for (int cj = j0; cj < j1; ++cj)
       for (int ci = 0; ci < cells; ++ci) {
@@ -231,15 +228,12 @@ Csr assemble(int side, int nb, const double* blocks) {
   auto U = [&](int ci, int cj) { return ul[(size_t)cj * cells + ci]; };
   std::vector<int> cnt(n);
   par_rows(n, [&](int r0, int r1) {
-    for (int r = r0; r < r1; ++r) {
-      const int i = r % m + 1, j = r / m + 1;
+    for (int r = r0, i = r0 % m + 1, j = r0 / m + 1; r < r1; ++r, i = i == m ? (++j, 1) : i + 1)
       cnt[r] = 1 + (i > 1) + (j > 1) + (i < m) + (j < m);
-    }
   });
   Csr A = alloc_csr(n, n, cnt);
   par_rows(n, [&](int r0, int r1) {
-    for (int r = r0; r < r1; ++r) {
-      const int i = r % m + 1, j = r / m + 1;
+    for (int r = r0, i = r0 % m + 1, j = r0 / m + 1; r < r1; ++r, i = i == m ? (++j, 1) : i + 1) {
       const double a1 = L(i, j), a2 = U(i, j), b1 = L(i - 1, j), c1 = L(i - 1, j - 1), c2 = U(i - 1, j - 1),
                    d2 = U(i, j - 1);
       const double diag = 0.5 * a1 + 0.5 * a2 + b1 + 0.5 * c1 + 0.5 * c2 + d2;
@@ -261,24 +255,24 @@ Csr assemble(int side, int nb, const double* blocks) {
 Csr prolongation(int side_f) {
   const int side_c = (side_f + 1) / 2, mf = side_f - 2;
   const int nf = mf * mf, nc = (side_c - 2) * (side_c - 2);
-  auto ends = [&](int r, int& c1, int& c2) {
-    const int i = r % mf + 1, j = r / mf + 1;
+  // fine row r is grid point (i, j), walked along the rows without divisions
+  auto ends = [&](int i, int j, int& c1, int& c2) {
     c1 = unk(side_c, i / 2, j / 2);
     c2 = unk(side_c, (i + 1) / 2, (j + 1) / 2);
   };
   std::vector<int> cnt(nf);
   par_rows(nf, [&](int r0, int r1) {
-    for (int r = r0; r < r1; ++r) {
+    for (int r = r0, i = r0 % mf + 1, j = r0 / mf + 1; r < r1; ++r, i = i == mf ? (++j, 1) : i + 1) {
       int c1, c2;
-      ends(r, c1, c2);
+      ends(i, j, c1, c2);
       cnt[r] = c1 == c2 ? (c1 >= 0) : (c1 >= 0) + (c2 >= 0);
     }
   });
   Csr P = alloc_csr(nf, nc, cnt);
   par_rows(nf, [&](int r0, int r1) {
-    for (int r = r0; r < r1; ++r) {
+    for (int r = r0, i = r0 % mf + 1, j = r0 / mf + 1; r < r1; ++r, i = i == mf ? (++j, 1) : i + 1) {
       int c1, c2, p = P.rowptr[r];
-      ends(r, c1, c2);
+      ends(i, j, c1, c2);
       if (c1 == c2) {
         if (c1 >= 0) { P.col[p] = c1; P.val[p] = 1.0; }
         continue;
@@ -318,7 +312,28 @@ Csr restriction(int side_f) {
 // 0.5 (A_c + A_c^T), with off-diagonal round-off residue
 // |a_IJ| <= 1e-11 sqrt(|a_II a_JJ|) and exact zeros removed (residue of exactly cancelling
 // couplings reaches ~1e-13 on the coarsest levels; genuine couplings stay above ~1e-4).
-Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
+// Coarse columns of a row of R A P on the structured grids lie within two
+// grid steps of the row's own node; Window maps the column offset J - I (the
+// coarse grid has mc interior nodes per line, mc >= 5) to one of the 5 x 5
+// positions, numbered so that increasing position is increasing J.
+struct Window {
+  static constexpr int kSide = 5, kHalf = 2, kSize = kSide * kSide;
+  int mc = 0, base = 0;
+  std::vector<int> pos;   // offset + base -> position, or -1
+  explicit Window(int mc_) : mc(mc_), base(kHalf * mc_ + kHalf), pos((size_t)2 * base + 1, -1) {
+    for (int dj = -kHalf; dj <= kHalf; ++dj)
+      for (int di = -kHalf; di <= kHalf; ++di) pos[(size_t)(dj * mc + di + base)] = (dj + kHalf) * kSide + di + kHalf;
+  }
+  int at(int off) const {
+    const int k = off + base;
+    return k < 0 || k >= (int)pos.size() ? -1 : pos[(size_t)k];
+  }
+  int offset(int w) const { return (w / kSide - kHalf) * mc + (w % kSide - kHalf); }
+};
+
+// Galerkin product; mc: interior nodes per line of the coarse grid (the
+// window accumulation for mc >= 5, else the general one)
+Csr galerkin(const Csr& A, const Csr& P, const Csr& R, int mc) {
   constexpr int kGalerkinGrain = 512;   // rows of R A P per thread at least (~1 us each)
   const int nc = R.nrows;
   // pass 1: the sorted column pattern and values of every row of R A P; each thread keeps its
@@ -331,7 +346,66 @@ Csr galerkin(const Csr& A, const Csr& P, const Csr& R) {
   std::vector<int> cnt(nc, 0);
   std::vector<Chunk> chunks;
   std::mutex mu;
-  par_rows(nc, [&](int r0, int r1) {
+  // the window accumulation: the same products and sums, in the same order,
+  // into 25 local entries instead of dense arrays of all coarse columns
+  std::atomic<bool> outside{mc < Window::kSide};
+  if (!outside) {
+    const Window win(mc);
+    par_rows(nc, [&](int r0, int r1) {
+      double ai[Window::kSize], ap[Window::kSize];
+      bool ta[Window::kSize] = {}, tp[Window::kSize] = {};
+      int la[Window::kSize];
+      Chunk ch;
+      ch.r0 = r0;
+      ch.r1 = r1;
+      ch.col.reserve((size_t)(r1 - r0) * 8);
+      ch.val.reserve((size_t)(r1 - r0) * 8);
+      for (int I = r0; I < r1; ++I) {
+        for (int p = R.rowptr[I]; p < R.rowptr[I + 1]; ++p) {
+          const int i = R.col[p];
+          int na = 0;
+          for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            const int j = A.col[q];
+            for (int t = P.rowptr[j]; t < P.rowptr[j + 1]; ++t) {
+              const int w = win.at(P.col[t] - I);
+              if (w < 0) {
+                outside = true;
+                return;
+              }
+              if (!ta[w]) {
+                ta[w] = true;
+                ai[w] = 0.0;
+                la[na++] = w;
+              }
+              ai[w] += A.val[q] * P.val[t];
+            }
+          }
+          for (int k = 0; k < na; ++k) {
+            const int w = la[k];
+            if (!tp[w]) {
+              tp[w] = true;
+              ap[w] = 0.0;
+            }
+            ap[w] += R.val[p] * ai[w];
+            ta[w] = false;
+          }
+        }
+        int c = 0;
+        for (int w = 0; w < Window::kSize; ++w)
+          if (tp[w]) {
+            ch.col.push_back(I + win.offset(w));
+            ch.val.push_back(ap[w]);
+            tp[w] = false;
+            ++c;
+          }
+        cnt[I] = c;
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      chunks.push_back(std::move(ch));
+    }, kGalerkinGrain);
+    if (outside) chunks.clear();
+  }
+  if (outside) par_rows(nc, [&](int r0, int r1) {
     RowAcc ap(P.ncols), ai(P.ncols);
     Chunk ch;
     ch.r0 = r0;
@@ -442,7 +516,7 @@ mg_status mg_square_hierarchy(int32_t side, int32_t nb, const double* blocks, in
   for (int l = 0; l + 1 < J; ++l) {
     h->P.push_back(prolongation(s));
     const Csr R = restriction(s);
-    h->A.push_back(galerkin(h->A.back(), h->P.back(), R));
+    h->A.push_back(galerkin(h->A.back(), h->P.back(), R, (s + 1) / 2 - 2));
     s = (s + 1) / 2;
   }
   auto view = [](const Csr& c) {
