@@ -369,6 +369,60 @@ class Server:
         return done, errors, wall
 
 
+class Intake:
+    """Requests waiting for setup in the batched loop: one FIFO per grid side,
+    and per side the number of hierarchies set up (or being set up) that no
+    batch slot has taken yet, at most `limit` (host memory).  A setup worker
+    takes the oldest request among the sides below their limit, so a side
+    whose batch is full does not hold up the requests of the other sides
+    behind it."""
+
+    def __init__(self, limit: int):
+        import collections
+        self._deque = collections.deque
+        self.limit = limit
+        self.cv = threading.Condition()
+        self.q = {}          # side -> deque of (arrival order, request, arrival time)
+        self.held = {}       # side -> hierarchies not yet in a slot
+        self.seq = 0
+        self.closed = False
+
+    def put(self, req, t_arr: float):
+        with self.cv:
+            self.q.setdefault(req.side, self._deque()).append((self.seq, req, t_arr))
+            self.seq += 1
+            self.cv.notify()
+
+    def close(self):
+        """No more requests will be put."""
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+
+    def take(self):
+        """(request, arrival time) to set up next, its side's count raised; None
+        once closed and empty.  Waits while every waiting side is at its limit."""
+        with self.cv:
+            while True:
+                best = None
+                for side, dq in self.q.items():
+                    if dq and self.held.get(side, 0) < self.limit and (best is None or dq[0][0] < self.q[best][0][0]):
+                        best = side
+                if best is not None:
+                    _, req, t_arr = self.q[best].popleft()
+                    self.held[best] = self.held.get(best, 0) + 1
+                    return req, t_arr
+                if self.closed and not any(self.q.values()):
+                    return None
+                self.cv.wait()
+
+    def release(self, side: int):
+        """A hierarchy of `side` went into a slot (or its setup failed)."""
+        with self.cv:
+            self.held[side] -= 1
+            self.cv.notify_all()
+
+
 def pattern_key(hier) -> str:
     """Key of a native hierarchy's level patterns (row pointers and columns of
     every A_l): requests with equal keys can share a batch context.  The arrays
@@ -403,7 +457,11 @@ class BatchServer:
     depends only on the current iterate, so a request's iterates, cycle count
     and result are the same whatever the rounds and whatever the other columns
     hold (columns are independent; empty slots carry f = 0 and are skipped by
-    the solver's column compaction).  Each batch's device footprint (workspace,
+    the solver's column compaction).  Setup workers build the hierarchies and
+    draw the right-hand sides; they take requests from an Intake, one queue
+    per grid side with at most 2 x capacity set-up hierarchies per side
+    waiting for slots, so a side whose batch is full never holds up the other
+    sides.  Each batch's device footprint (workspace,
     tile lists excluded, plus f and u) is acquired from the HBM budget before its
     context is set up and released when the batch retires.  A request whose
     learned cycle diverges, or stalls (Server's test), leaves the batch and is
@@ -471,20 +529,13 @@ class BatchServer:
         torch, Bd = self.torch, self.Bd
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        incoming: queue.Queue = queue.Queue()
+        # built hierarchies wait on the host until a slot takes them: at most 2 * capacity per side
+        intake = Intake(2 * self.capacity)
         results, errors = [], []
         lock = threading.Lock()
         groups = {}          # pattern key -> group record
         workers = []
         setups_done = threading.Event()
-        # built hierarchies wait on the host until a slot takes them: at most 2 * capacity per side
-        side_slots = {}
-
-        def side_sem(side):
-            with lock:
-                if side not in side_slots:
-                    side_slots[side] = threading.Semaphore(2 * self.capacity)
-                return side_slots[side]
 
         class Group:
             def __init__(self, key):
@@ -517,13 +568,11 @@ class BatchServer:
 
         def setup_worker():
             while True:
-                it = incoming.get()
+                it = intake.take()
                 if it is None:
                     return
                 req, t_arr = it
                 hier = None
-                sem = side_sem(req.side)
-                sem.acquire()
                 try:
                     hier = Bd.SquareHierarchy(req.side, req.blocks)
                     if self.fail_setup is not None and self.fail_setup(req):
@@ -534,7 +583,7 @@ class BatchServer:
                 except Exception as e:  # report and keep serving
                     if hier is not None:
                         hier.close()
-                    sem.release()
+                    intake.release(req.side)
                     with lock:
                         errors.append((req.rid, repr(e)))
 
@@ -615,7 +664,7 @@ class BatchServer:
                                 ctx.load_column(b, hier)
                             finally:
                                 hier.close()
-                                side_sem(req.side).release()
+                                intake.release(req.side)
                             f[:, b].copy_(fv, non_blocking=True)
                             u[:, b] = 0.0
                             slots[b] = [req, t_arr, now(), None, 0,
@@ -674,7 +723,7 @@ class BatchServer:
                         break
                 for rq, _, hh, *_ in waiting:   # built hierarchies never loaded: free them
                     hh.close()
-                    side_sem(rq.side).release()
+                    intake.release(rq.side)
                 left += [it[0] for it in waiting]
                 with lock:
                     errors.append(("group " + g.key, repr(e)))
@@ -694,9 +743,8 @@ class BatchServer:
                 delay = req.arrival - now()
                 if delay > 0:
                     time.sleep(delay)
-            incoming.put((req, req.arrival if open_loop else 0.0))
-        for _ in setups:
-            incoming.put(None)
+            intake.put(req, req.arrival if open_loop else 0.0)
+        intake.close()
         last = now()
         for t in setups:
             while t.is_alive():
