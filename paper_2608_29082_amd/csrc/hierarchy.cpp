@@ -484,10 +484,41 @@ Csr galerkin(const Csr& A, const Csr& P, const Csr& R, int mc) {
   return o;
 }
 
+// The transfers of a grid side (P_l and R_l = P_l^T of every level) depend on
+// the mesh only, not on the coefficients: they are built once per side and
+// shared, read-only, by every hierarchy of that side (serving builds the same
+// few sides over and over).  At most kSideCache sides are kept; a hierarchy
+// holds its side's transfers for as long as it lives.
+struct Transfers {
+  std::vector<Csr> P, R;
+};
+constexpr size_t kSideCache = 8;
+std::shared_ptr<const Transfers> transfers_of(int side, int J) {
+  static std::mutex mu;
+  static std::vector<std::pair<int, std::shared_ptr<const Transfers>>> cache;   // oldest first
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (const auto& e : cache)
+      if (e.first == side) return e.second;
+  }
+  auto t = std::make_shared<Transfers>();
+  for (int l = 0, s = side; l + 1 < J; ++l, s = (s + 1) / 2) {
+    t->P.push_back(prolongation(s));
+    t->R.push_back(restriction(s));
+  }
+  std::lock_guard<std::mutex> g(mu);
+  for (const auto& e : cache)
+    if (e.first == side) return e.second;   // built meanwhile by another call: keep that one
+  if (cache.size() >= kSideCache) cache.erase(cache.begin());
+  cache.emplace_back(side, t);
+  return t;
+}
+
 }  // namespace
 
 struct mg_host_hierarchy {
-  std::vector<Csr> A, P;
+  std::vector<Csr> A;
+  std::shared_ptr<const Transfers> T;   // P_l (and R_l) of the side, shared
   std::vector<mg_csr> Av, Pv;
 };
 
@@ -511,12 +542,11 @@ mg_status mg_square_hierarchy(int32_t side, int32_t nb, const double* blocks, in
     if (!(blocks[k] > 0.0) || !std::isfinite(blocks[k])) return MG_ERR_INVALID_ARG;
   const ActiveCall guard;
   auto* h = new mg_host_hierarchy;
+  h->T = transfers_of(side, J);
   h->A.push_back(assemble(side, nb, blocks));
   s = side;
   for (int l = 0; l + 1 < J; ++l) {
-    h->P.push_back(prolongation(s));
-    const Csr R = restriction(s);
-    h->A.push_back(galerkin(h->A.back(), h->P.back(), R, (s + 1) / 2 - 2));
+    h->A.push_back(galerkin(h->A.back(), h->T->P[l], h->T->R[l], (s + 1) / 2 - 2));
     s = (s + 1) / 2;
   }
   auto view = [](const Csr& c) {
@@ -530,7 +560,7 @@ mg_status mg_square_hierarchy(int32_t side, int32_t nb, const double* blocks, in
     return v;
   };
   for (const Csr& a : h->A) h->Av.push_back(view(a));
-  for (const Csr& p : h->P) h->Pv.push_back(view(p));
+  for (const Csr& p : h->T->P) h->Pv.push_back(view(p));
   *out = h;
   return MG_OK;
 }
