@@ -668,6 +668,8 @@ struct Engine final : EngineBase {
 #ifndef MGL_TILE_LDS_KB
 #define MGL_TILE_LDS_KB 80
 #endif
+// bands per band group of the tile order (on the 513 workload: 1, 2, 8 and 16 made the
+// finest-level convolution 0-2 % slower and the cycle 0.3-1 % slower than 4)
 #ifndef MGL_TILE_GROUP
 #define MGL_TILE_GROUP 4
 #endif
