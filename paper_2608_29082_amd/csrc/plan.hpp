@@ -356,13 +356,8 @@ struct HostPlan {
   std::vector<std::vector<int32_t>> prow, pcol;
 };
 
-// One column's operator on the ELL layout of level L (built from the same
-// pattern): off[k * ld + i] the k-th off-diagonal entry of row i (CSR order,
-// padding 0), dg[i] the diagonal (rows [n, ld): 1).  The values must be finite
-// with nonzero off-diagonal entries and diagonal, so the column's graph is the
-// pattern's.
-// Rows [r0, r1) of column_arrays: on a value off the rules, the failing row
-// (INT_MAX when the row count of the message does not apply) and the message.
+// Rows [r0, r1) of column_arrays; on a value off the rules, the failing row and
+// the message.
 mg_status column_rows(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b,
                       int r0, int r1, int& row, std::string& msg) {
   const int ld = L.off.ld, w = L.off.w;
@@ -400,6 +395,11 @@ mg_status column_rows(const mg_csr* A, const double* v, const HLevel& L, double*
   return MG_OK;
 }
 
+// One column's operator on the ELL layout of level L (built from the same
+// pattern): off[k * ld + i] the k-th off-diagonal entry of row i (CSR order,
+// padding 0), dg[i] the diagonal (rows [n, ld): 1).  The values must be finite
+// with nonzero off-diagonal entries and diagonal, so the column's graph is the
+// pattern's.
 mg_status column_arrays(const mg_csr* A, const double* v, const HLevel& L, double* off, double* dg, int l, int b) {
   const int n = A->nrows, ld = L.off.ld, w = L.off.w;
   // rows [n, ld) of the padded layout
