@@ -881,8 +881,10 @@ struct Engine final : EngineBase {
                          const_cast<C*>(d[l].L.diag), const_cast<C*>(d[l].L.invdiag),
                          f64 ? const_cast<double*>(L64.val) : nullptr, f64 ? const_cast<double*>(L64.diag) : nullptr);
       LAUNCH_OK();
-      HIP_TRY(hipStreamSynchronize(st));   // colstage is reused by the next level
     }
+    // the next call rewrites colhost: its copies end first (the stream orders the
+    // reuse of colstage between levels)
+    HIP_TRY(hipStreamSynchronize(st));
     const int nJ = pl.lv[J - 1].n;
     std::vector<double> Ad((size_t)nJ * nJ, 0.0);
     const std::vector<int32_t>& rp = pl.prow[J - 1];
